@@ -1,0 +1,515 @@
+/*
+ * oracle.c -- plain, slow, single-threaded CPU reference of what the binned
+ * raster pipeline computes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its
+ * Python binding) may include, link, import or call this file; only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg use it.  It
+ * shares no code, header, table or constant with the HIP path.
+ *
+ * What it computes (Piko, Sec. 4.1 "AssignBin/Schedule/Process" and Sec. 4.4
+ * "Sort-Middle Tiled Renderer"; stage list of the Baseline rasterizer in
+ * Sec. 7.1): vertex transform, triangle setup, coverage, depth test and
+ * Gouraud / textured / deferred shading.  The binning and scheduling phases of
+ * the paper only regroup and reorder work (Sec. 4.1: AssignBin decides how
+ * work is grouped, Schedule when and where it runs, Process what is computed),
+ * so the image has a plain definition that uses no bins at all: for every
+ * pixel sample, the nearest covering triangle.  This file is that definition.
+ * The bin lists are produced separately (orc_assign_bin) only so the
+ * AssignBin stage of the HIP path can be checked.
+ *
+ * The paper fixes none of the numeric conventions; the readings used here
+ * (sample position, 8 sub-pixel bits with round-half-even snapping, the
+ * top-left fill rule, the float64 barycentric depth, the (depth, primID)
+ * tie-break, perspective-correct attributes, bilinear clamp-to-edge texturing,
+ * the clamped Lambert deferred pass) are listed in the design notes.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.  Contraction
+ * must stay off: every float operation below is one IEEE-rounded operation,
+ * evaluated in the order written.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Inputs and outputs (plain arrays; all float planes are SoA [c][V]).      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t width, height;
+    const float *pos;        /* [3][V] */
+    int64_t num_vertices;    /* V */
+    const int32_t *idx;      /* [T][3] or NULL (vertex 3t+k) */
+    int64_t num_tris;        /* T */
+    const float *mvp;        /* [16] row-major, or NULL (identity) */
+    const float *color;      /* [3][V] */
+    const float *uv;         /* [2][V] or NULL */
+    const float *normal;     /* [3][V] or NULL */
+    const float *texture;    /* [th][tw][3] or NULL */
+    int32_t tex_w, tex_h;
+    const float *lights;     /* [L][3] */
+    int32_t num_lights;
+    int32_t shading;         /* 0 gouraud, 1 textured, 2 deferred */
+} orc_scene;
+
+typedef struct {
+    float *color;            /* [H][W][4] */
+    float *depth;            /* [H][W] */
+    int32_t *primid;         /* [H][W] */
+    float *bary;             /* [H][W][2] or NULL */
+    float *gbuf_normal;      /* [H][W][3] or NULL */
+    float *gbuf_albedo;      /* [H][W][3] or NULL */
+    int32_t *cover_count;    /* [H][W] or NULL: samples covered, before z test */
+    uint64_t *frag_count;    /* one value or NULL */
+} orc_targets;
+
+/* ------------------------------------------------------------------------ */
+/* Step 1: per-vertex transform, perspective divide, viewport, snap.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int valid;
+    int32_t X, Y;            /* fixed point, 8 fractional bits */
+    float z, iw;             /* NDC depth, 1/w */
+} ovtx;
+
+static ovtx vertex_stage(const orc_scene *s, int64_t v)
+{
+    const int64_t V = s->num_vertices;
+    const float x = s->pos[v], y = s->pos[V + v], z = s->pos[2 * V + v];
+    float c[4];
+    if (s->mvp) {
+        const float *m = s->mvp;
+        for (int r = 0; r < 4; ++r) {
+            float t = m[4 * r + 0] * x;
+            t = t + m[4 * r + 1] * y;
+            t = t + m[4 * r + 2] * z;
+            t = t + m[4 * r + 3];
+            c[r] = t;
+        }
+    } else {
+        c[0] = x; c[1] = y; c[2] = z; c[3] = 1.0f;
+    }
+    ovtx o;
+    memset(&o, 0, sizeof o);
+    int ok = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(c[3]) && c[3] > 0.0f;
+    const float xn = c[0] / c[3];
+    const float yn = c[1] / c[3];
+    const float zn = c[2] / c[3];
+    const float iw = 1.0f / c[3];
+    const float xs = (xn + 1.0f) * (0.5f * (float)s->width);
+    const float ys = (yn + 1.0f) * (0.5f * (float)s->height);
+    ok = ok && isfinite(zn) && isfinite(iw);
+    ok = ok && fabsf(xs) < 16384.0f && fabsf(ys) < 16384.0f;
+    o.valid = ok;
+    if (ok) {
+        o.X = (int32_t)rintf(xs * 256.0f);   /* round half to even */
+        o.Y = (int32_t)rintf(ys * 256.0f);
+        o.z = zn;
+        o.iw = iw;
+    }
+    return o;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: triangle setup.                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int live;
+    int32_t X[3], Y[3];
+    float z[3], iw[3];
+    int64_t A2;              /* twice the signed area, 1/256 px units squared */
+    int s;                   /* orientation sign */
+    int32_t bx0, bx1, by0, by1; /* inclusive pixel bbox of covered-candidate samples */
+    int64_t vid[3];
+} otri;
+
+static int64_t floor_div256(int64_t a)
+{
+    return (a >= 0) ? (a / 256) : -((-a + 255) / 256);
+}
+
+static int64_t vertex_id(const orc_scene *s, int64_t t, int k)
+{
+    return s->idx ? (int64_t)s->idx[3 * t + k] : 3 * t + k;
+}
+
+static otri setup_stage(const orc_scene *s, int64_t t)
+{
+    otri r;
+    memset(&r, 0, sizeof r);
+    int valid = 1;
+    for (int k = 0; k < 3; ++k) {
+        r.vid[k] = vertex_id(s, t, k);
+        if (r.vid[k] < 0 || r.vid[k] >= s->num_vertices) { valid = 0; continue; }
+        ovtx v = vertex_stage(s, r.vid[k]);
+        valid = valid && v.valid;
+        r.X[k] = v.X; r.Y[k] = v.Y; r.z[k] = v.z; r.iw[k] = v.iw;
+    }
+    if (!valid) return r;
+    r.A2 = (int64_t)(r.X[1] - r.X[0]) * (int64_t)(r.Y[2] - r.Y[0])
+         - (int64_t)(r.X[2] - r.X[0]) * (int64_t)(r.Y[1] - r.Y[0]);
+    if (r.A2 == 0) return r;
+    r.s = r.A2 > 0 ? 1 : -1;
+    int32_t mnx = r.X[0], mxx = r.X[0], mny = r.Y[0], mxy = r.Y[0];
+    for (int k = 1; k < 3; ++k) {
+        if (r.X[k] < mnx) mnx = r.X[k];
+        if (r.X[k] > mxx) mxx = r.X[k];
+        if (r.Y[k] < mny) mny = r.Y[k];
+        if (r.Y[k] > mxy) mxy = r.Y[k];
+    }
+    /* pixel p is sampled at 256p+128: smallest p with 256p+128 >= min,
+     * largest p with 256p+128 <= max */
+    int64_t x0 = floor_div256((int64_t)mnx - 128 + 255);
+    int64_t x1 = floor_div256((int64_t)mxx - 128);
+    int64_t y0 = floor_div256((int64_t)mny - 128 + 255);
+    int64_t y1 = floor_div256((int64_t)mxy - 128);
+    if (x0 < 0) x0 = 0;
+    if (y0 < 0) y0 = 0;
+    if (x1 > s->width - 1) x1 = s->width - 1;
+    if (y1 > s->height - 1) y1 = s->height - 1;
+    if (x0 > x1 || y0 > y1) return r;   /* no sample inside the bbox */
+    r.bx0 = (int32_t)x0; r.bx1 = (int32_t)x1; r.by0 = (int32_t)y0; r.by1 = (int32_t)y1;
+    r.live = 1;
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 4: coverage with the top-left rule (y up: top = larger y).          */
+/* Edge k is the edge opposite vertex k, directed v1->v2, v2->v0, v0->v1.   */
+/* ------------------------------------------------------------------------ */
+static void edge_values(const otri *r, int64_t Px, int64_t Py, int64_t E[3])
+{
+    static const int a_of[3] = {1, 2, 0};
+    static const int b_of[3] = {2, 0, 1};
+    for (int k = 0; k < 3; ++k) {
+        const int a = a_of[k], b = b_of[k];
+        const int64_t dx = (int64_t)r->X[b] - r->X[a];
+        const int64_t dy = (int64_t)r->Y[b] - r->Y[a];
+        E[k] = dx * (Py - r->Y[a]) - dy * (Px - r->X[a]);
+    }
+}
+
+static int covers(const otri *r, const int64_t E[3])
+{
+    static const int a_of[3] = {1, 2, 0};
+    static const int b_of[3] = {2, 0, 1};
+    for (int k = 0; k < 3; ++k) {
+        const int64_t e = r->s * E[k];
+        if (e > 0) continue;
+        if (e < 0) return 0;
+        const int64_t dx = (int64_t)r->X[b_of[k]] - r->X[a_of[k]];
+        const int64_t dy = (int64_t)r->Y[b_of[k]] - r->Y[a_of[k]];
+        const int owned = (r->s * dy < 0) || (dy == 0 && r->s * dx < 0);
+        if (!owned) return 0;
+    }
+    return 1;
+}
+
+/* Step 5: screen-linear depth through float64 barycentrics. */
+static void barycentrics64(const otri *r, const int64_t E[3], double beta[3])
+{
+    const int64_t a = r->s * r->A2;          /* > 0 */
+    const double inv = 1.0 / (double)a;
+    for (int k = 0; k < 3; ++k) beta[k] = (double)(r->s * E[k]) * inv;
+}
+
+static float depth_of(const otri *r, const double beta[3])
+{
+    double zd = beta[0] * (double)r->z[0];
+    zd = zd + beta[1] * (double)r->z[1];
+    zd = zd + beta[2] * (double)r->z[2];
+    float z = (float)zd;
+    z = z + 0.0f;                            /* -0 -> +0 */
+    return z;
+}
+
+static uint32_t float_bits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+static float bits_float(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+
+/* ------------------------------------------------------------------------ */
+/* Shading helpers (step 7).                                                */
+/* ------------------------------------------------------------------------ */
+static void persp_bary(const otri *r, const double beta[3], float bp[3])
+{
+    const float bs0 = (float)beta[0], bs1 = (float)beta[1], bs2 = (float)beta[2];
+    const float q0 = bs0 * r->iw[0];
+    const float q1 = bs1 * r->iw[1];
+    const float q2 = bs2 * r->iw[2];
+    const float Q = (q0 + q1) + q2;
+    bp[1] = q1 / Q;
+    bp[2] = q2 / Q;
+    bp[0] = (1.0f - bp[1]) - bp[2];
+}
+
+static float interp(const float *plane, const int64_t vid[3], const float bp[3])
+{
+    float t = bp[0] * plane[vid[0]];
+    t = t + bp[1] * plane[vid[1]];
+    t = t + bp[2] * plane[vid[2]];
+    return t;
+}
+
+/* Bilinear, texel centres at (i+1/2)/N, clamp to edge; row j follows v. */
+typedef struct { int64_t texel[4]; float w[4]; } otap;
+
+static otap bilinear_taps(const orc_scene *s, float u, float v)
+{
+    otap o;
+    const float su = u * (float)s->tex_w - 0.5f;
+    const float sv = v * (float)s->tex_h - 0.5f;
+    const float fi = floorf(su), fj = floorf(sv);
+    const float fs = su - fi, ft = sv - fj;
+    /* clamping the float index first only avoids an out-of-range conversion;
+     * every tap beyond an edge lands on that edge either way */
+    const float ci = fminf(fmaxf(fi, -1.0f), (float)s->tex_w);
+    const float cj = fminf(fmaxf(fj, -1.0f), (float)s->tex_h);
+    int64_t i0 = (int64_t)ci, j0 = (int64_t)cj;
+    int64_t i1 = i0 + 1, j1 = j0 + 1;
+    const int64_t wmax = s->tex_w - 1, hmax = s->tex_h - 1;
+    if (i0 < 0) i0 = 0; if (i0 > wmax) i0 = wmax;
+    if (i1 < 0) i1 = 0; if (i1 > wmax) i1 = wmax;
+    if (j0 < 0) j0 = 0; if (j0 > hmax) j0 = hmax;
+    if (j1 < 0) j1 = 0; if (j1 > hmax) j1 = hmax;
+    o.texel[0] = j0 * s->tex_w + i0;
+    o.texel[1] = j0 * s->tex_w + i1;
+    o.texel[2] = j1 * s->tex_w + i0;
+    o.texel[3] = j1 * s->tex_w + i1;
+    o.w[0] = (1.0f - fs) * (1.0f - ft);
+    o.w[1] = fs * (1.0f - ft);
+    o.w[2] = (1.0f - fs) * ft;
+    o.w[3] = fs * ft;
+    return o;
+}
+
+static float sample_channel(const orc_scene *s, const otap *tp, int c)
+{
+    float t = tp->w[0] * s->texture[3 * tp->texel[0] + c];
+    t = t + tp->w[1] * s->texture[3 * tp->texel[1] + c];
+    t = t + tp->w[2] * s->texture[3 * tp->texel[2] + c];
+    t = t + tp->w[3] * s->texture[3 * tp->texel[3] + c];
+    return t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Per-vertex stage, for checking the snap against closed forms. */
+int orc_vertices(const orc_scene *s, int32_t *X, int32_t *Y, float *z, float *iw, uint8_t *valid)
+{
+    for (int64_t v = 0; v < s->num_vertices; ++v) {
+        ovtx o = vertex_stage(s, v);
+        X[v] = o.X; Y[v] = o.Y; z[v] = o.z; iw[v] = o.iw; valid[v] = (uint8_t)o.valid;
+    }
+    return 0;
+}
+
+/* Per-triangle setup: live flag, inclusive pixel bbox [T][4] = x0,x1,y0,y1, A2. */
+int orc_setup(const orc_scene *s, uint8_t *live, int32_t *bbox, int64_t *A2)
+{
+    for (int64_t t = 0; t < s->num_tris; ++t) {
+        otri r = setup_stage(s, t);
+        live[t] = (uint8_t)r.live;
+        bbox[4 * t + 0] = r.bx0; bbox[4 * t + 1] = r.bx1;
+        bbox[4 * t + 2] = r.by0; bbox[4 * t + 3] = r.by1;
+        A2[t] = r.A2;
+    }
+    return 0;
+}
+
+/*
+ * AssignToBoundingBox (Sec. 4.3, directive table): every bin that the
+ * triangle's sample bbox overlaps.  Bins are bin_size x bin_size pixels,
+ * numbered row-major, ceil(W/B) per row; bin_size 0 means one bin covering
+ * the whole screen (Sec. 4.4 "No Tiling").  Lists are ascending in t.
+ * Writes bin_off[nbins+1]; writes bin_tris when it is non-NULL and the total
+ * fits in cap.  Returns the total number of (bin, triangle) pairs.
+ */
+int64_t orc_assign_bin(const orc_scene *s, int32_t bin_size, int32_t *bin_off,
+                       int32_t *bin_tris, int64_t cap)
+{
+    const int W = s->width, H = s->height;
+    const int bw = bin_size > 0 ? bin_size : W;
+    const int bh = bin_size > 0 ? bin_size : H;
+    const int nbx = (W + bw - 1) / bw, nby = (H + bh - 1) / bh;
+    const int64_t nbins = (int64_t)nbx * nby;
+    int64_t *cnt = calloc((size_t)nbins, sizeof(int64_t));
+    otri *tr = malloc(sizeof(otri) * (size_t)(s->num_tris > 0 ? s->num_tris : 1));
+    if (!cnt || !tr) { free(cnt); free(tr); return -1; }
+    for (int64_t t = 0; t < s->num_tris; ++t) {
+        tr[t] = setup_stage(s, t);
+        if (!tr[t].live) continue;
+        for (int by = tr[t].by0 / bh; by <= tr[t].by1 / bh; ++by)
+            for (int bx = tr[t].bx0 / bw; bx <= tr[t].bx1 / bw; ++bx)
+                cnt[(int64_t)by * nbx + bx] += 1;
+    }
+    int64_t total = 0;
+    for (int64_t b = 0; b < nbins; ++b) { bin_off[b] = (int32_t)total; total += cnt[b]; }
+    bin_off[nbins] = (int32_t)total;
+    if (bin_tris && total <= cap) {
+        for (int64_t b = 0; b < nbins; ++b) cnt[b] = bin_off[b];
+        for (int64_t t = 0; t < s->num_tris; ++t) {
+            if (!tr[t].live) continue;
+            for (int by = tr[t].by0 / bh; by <= tr[t].by1 / bh; ++by)
+                for (int bx = tr[t].bx0 / bw; bx <= tr[t].bx1 / bw; ++bx)
+                    bin_tris[cnt[(int64_t)by * nbx + bx]++] = (int32_t)t;
+        }
+    }
+    free(cnt);
+    free(tr);
+    return total;
+}
+
+/*
+ * The image: for every pixel sample the covering triangle with the smallest
+ * 64-bit key (depth bits << 32 | triangle index) among fragments with
+ * 0 <= z < 1, then the shading of that winner.
+ */
+int orc_render(const orc_scene *s, const orc_targets *o)
+{
+    const int W = s->width, H = s->height;
+    const int64_t npx = (int64_t)W * H;
+    uint64_t *zbuf = malloc(sizeof(uint64_t) * (size_t)(npx > 0 ? npx : 1));
+    if (!zbuf) return -1;
+    for (int64_t p = 0; p < npx; ++p) zbuf[p] = ~0ull;
+    if (o->cover_count) memset(o->cover_count, 0, sizeof(int32_t) * (size_t)npx);
+    uint64_t frags = 0;
+
+    /* steps 2, 4, 5, 6: every triangle in submission order, every sample of its bbox */
+    for (int64_t t = 0; t < s->num_tris; ++t) {
+        otri r = setup_stage(s, t);
+        if (!r.live) continue;
+        for (int py = r.by0; py <= r.by1; ++py) {
+            for (int px = r.bx0; px <= r.bx1; ++px) {
+                const int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+                int64_t E[3];
+                edge_values(&r, Px, Py, E);
+                if (!covers(&r, E)) continue;
+                const int64_t p = (int64_t)py * W + px;
+                frags += 1;
+                if (o->cover_count) o->cover_count[p] += 1;
+                double beta[3];
+                barycentrics64(&r, E, beta);
+                const float z = depth_of(&r, beta);
+                if (!(0.0f <= z && z < 1.0f)) continue;
+                const uint64_t key = ((uint64_t)float_bits(z) << 32) | (uint32_t)t;
+                if (key < zbuf[p]) zbuf[p] = key;
+            }
+        }
+    }
+    if (o->frag_count) *o->frag_count = frags;
+
+    /* step 7: resolve and shade every pixel */
+    for (int py = 0; py < H; ++py) {
+        for (int px = 0; px < W; ++px) {
+            const int64_t p = (int64_t)py * W + px;
+            float *col = o->color ? o->color + 4 * p : NULL;
+            if (zbuf[p] == ~0ull) {
+                if (col) col[0] = col[1] = col[2] = col[3] = 0.0f;
+                if (o->depth) o->depth[p] = 1.0f;
+                if (o->primid) o->primid[p] = -1;
+                if (o->bary) o->bary[2 * p] = o->bary[2 * p + 1] = 0.0f;
+                if (o->gbuf_normal) o->gbuf_normal[3 * p] = o->gbuf_normal[3 * p + 1] = o->gbuf_normal[3 * p + 2] = 0.0f;
+                if (o->gbuf_albedo) o->gbuf_albedo[3 * p] = o->gbuf_albedo[3 * p + 1] = o->gbuf_albedo[3 * p + 2] = 0.0f;
+                continue;
+            }
+            const int64_t t = (int64_t)(zbuf[p] & 0xffffffffull);
+            const float z = bits_float((uint32_t)(zbuf[p] >> 32));
+            otri r = setup_stage(s, t);
+            int64_t E[3];
+            edge_values(&r, 256 * (int64_t)px + 128, 256 * (int64_t)py + 128, E);
+            double beta[3];
+            barycentrics64(&r, E, beta);
+            float bp[3];
+            persp_bary(&r, beta, bp);
+            const int64_t V = s->num_vertices;
+            float rgb[3];
+            for (int c = 0; c < 3; ++c) rgb[c] = interp(s->color + c * V, r.vid, bp);
+            if (s->shading == 1) {
+                const float u = interp(s->uv, r.vid, bp);
+                const float v = interp(s->uv + V, r.vid, bp);
+                otap tp = bilinear_taps(s, u, v);
+                for (int c = 0; c < 3; ++c) rgb[c] = rgb[c] * sample_channel(s, &tp, c);
+            }
+            if (s->shading == 2) {
+                float n[3];
+                for (int c = 0; c < 3; ++c) n[c] = interp(s->normal + c * V, r.vid, bp);
+                float nn = n[0] * n[0];
+                nn = nn + n[1] * n[1];
+                nn = nn + n[2] * n[2];
+                float nh[3] = {0.0f, 0.0f, 0.0f};
+                if (nn != 0.0f) {
+                    const float len = sqrtf(nn);
+                    for (int c = 0; c < 3; ++c) nh[c] = n[c] / len;
+                }
+                if (o->gbuf_normal) for (int c = 0; c < 3; ++c) o->gbuf_normal[3 * p + c] = nh[c];
+                if (o->gbuf_albedo) for (int c = 0; c < 3; ++c) o->gbuf_albedo[3 * p + c] = rgb[c];
+                /* deferred pass: albedo * sum_l max(0, n.l) */
+                float lit = 0.0f;
+                for (int l = 0; l < s->num_lights; ++l) {
+                    const float *L = s->lights + 3 * l;
+                    float d = nh[0] * L[0];
+                    d = d + nh[1] * L[1];
+                    d = d + nh[2] * L[2];
+                    if (d < 0.0f) d = 0.0f;
+                    lit = (l == 0) ? d : lit + d;
+                }
+                for (int c = 0; c < 3; ++c) rgb[c] = rgb[c] * lit;
+            }
+            if (col) { col[0] = rgb[0]; col[1] = rgb[1]; col[2] = rgb[2]; col[3] = 1.0f; }
+            if (o->depth) o->depth[p] = z;
+            if (o->primid) o->primid[p] = (int32_t)t;
+            if (o->bary) { o->bary[2 * p] = bp[1]; o->bary[2 * p + 1] = bp[2]; }
+        }
+    }
+    free(zbuf);
+    return 0;
+}
+
+/*
+ * Reference gradient of an image loss with respect to the per-vertex colours
+ * and the texels, given the forward's primid and bary buffers and the
+ * upstream gradient G[H][W][4] (alpha ignored).  float64 accumulation in
+ * pixel-major order.  Coverage is not differentiated: nothing flows to
+ * positions, UVs or alpha.
+ *   untextured: dC[v_k][c] += b'_k G_c
+ *   textured:   dC[v_k][c] += b'_k G_c T_c ;  dTex[j][c] += w_j G_c Cint_c
+ * grad_vcolor is [3][V] and grad_tex [th][tw][3]; both are accumulated.
+ */
+int orc_backward(const orc_scene *s, const int32_t *primid, const float *bary,
+                 const float *grad, double *grad_vcolor, double *grad_tex)
+{
+    const int W = s->width, H = s->height;
+    const int64_t V = s->num_vertices;
+    for (int64_t p = 0; p < (int64_t)W * H; ++p) {
+        const int32_t t = primid[p];
+        if (t < 0) continue;
+        int64_t vid[3];
+        for (int k = 0; k < 3; ++k) vid[k] = vertex_id(s, t, k);
+        float bp[3];
+        bp[1] = bary[2 * p];
+        bp[2] = bary[2 * p + 1];
+        bp[0] = (1.0f - bp[1]) - bp[2];
+        const float *G = grad + 4 * p;
+        if (s->shading == 1) {
+            float rgb[3];
+            for (int c = 0; c < 3; ++c) rgb[c] = interp(s->color + c * V, vid, bp);
+            const float u = interp(s->uv, vid, bp);
+            const float v = interp(s->uv + V, vid, bp);
+            otap tp = bilinear_taps(s, u, v);
+            for (int c = 0; c < 3; ++c) {
+                const double Tc = (double)sample_channel(s, &tp, c);
+                for (int k = 0; k < 3; ++k)
+                    grad_vcolor[c * V + vid[k]] += (double)bp[k] * (double)G[c] * Tc;
+                for (int j = 0; j < 4; ++j)
+                    grad_tex[3 * tp.texel[j] + c] += (double)tp.w[j] * (double)G[c] * (double)rgb[c];
+            }
+        } else {
+            for (int c = 0; c < 3; ++c)
+                for (int k = 0; k < 3; ++k)
+                    grad_vcolor[c * V + vid[k]] += (double)bp[k] * (double)G[c];
+        }
+    }
+    return 0;
+}
