@@ -1,0 +1,189 @@
+"""Benchmark: binned software raster throughput on one MI355X.
+
+One step = one whole frame of the hot path on resident inputs: vertex
+transform + setup + bin counts (pk_setup), prefix sum + scatter of the bin
+lists (pk_assign_bin), and per-bin coverage / depth test / resolve / shading
+(pk_raster_shade).  Prints one JSON line.  Default workload: the 1920x1080
+displaced grid of 1024x512 quads (1,048,576 triangles) through a perspective
+camera, Gouraud shading, 16x16 bins.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+WORKLOADS = {
+    "grid1080": dict(desc="1920x1080 displaced grid, 1024x512 quads (1,048,576 triangles, "
+                          "shared vertices), perspective camera, Gouraud, 16x16 bins",
+                     bin=16),
+    "micro8m": dict(desc="1920x1080, 8,388,608 independent micropolygons (log-normal area "
+                         "around 0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
+                    bin=16),
+    "batch256": dict(desc="256 scenes at 256x256, log-uniform 1K-200K random triangles each "
+                          "(edge ~ log-normal around 4 px), one batched launch", bin=16),
+    "tiny64": dict(desc="64x64, 256 random triangles, Gouraud, 8x8 bins", bin=8),
+}
+
+
+def make_scene(name: str):
+    from paper_1404_6293_amd import scenes
+    if name == "grid1080":
+        return scenes.grid()
+    if name == "micro8m":
+        return scenes.micro()
+    if name == "batch256":
+        return scenes.batch()
+    if name == "tiny64":
+        return scenes.tiny()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def raster_algorithmic_bytes(sc, npairs: int, covered_px: int, want_bary: bool) -> int:
+    """Algorithmic bytes of one k_raster launch (the per-bin Process kernel):
+    the bin lists read once (4 B per (bin, triangle) pair plus 4 B per bin
+    offset), every output pixel written once (colour 16 B, depth 4 B, primid
+    4 B, bary 8 B when saved; for deferred the G-buffer 24 B instead of the
+    colour), and the attributes of the visible triangle gathered once per
+    covered pixel (3 vertex indices 12 B when indexed, 3 x 3 colour floats
+    36 B, plus 36 B of normals for deferred).  Setup records are an
+    implementation choice and are not counted."""
+    S = int(getattr(sc, "num_scenes", 1) or 1)
+    npix = S * sc.width * sc.height
+    B = int(getattr(sc, "bin_size", 16))
+    nbins = S * (-(-sc.width // B)) * (-(-sc.height // B))
+    deferred = getattr(sc, "shading", "gouraud") == "deferred"
+    per_px = (24 if deferred else 16) + 4 + 4 + (8 if want_bary else 0)
+    per_cov = (12 if sc.idx is not None else 0) + 36 + (36 if deferred else 0)
+    return 4 * npairs + 4 * (nbins + 1) + per_px * npix + per_cov * covered_px
+
+
+def cpu_baseline(sc, budget_s: float = 12.0):
+    """The oracle as it stands (single-threaded C) timed on this host on the
+    same workload: whole scenes, one after another, until the time budget is
+    used (at least one)."""
+    import oracle
+    parts = list(oracle.scene_parts(sc))
+    done_tris, done, t0 = 0, 0, time.perf_counter()
+    while True:
+        part = parts[done % len(parts)]
+        oracle.render(part, want_bary=False)
+        done_tris += int(part.num_tris)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(done_tris / dt / 1e6, 3), "unit": "Mtris/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} scene render(s) of the workload ({done_tris} triangles), "
+                      f"single-threaded, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="grid1080", choices=sorted(WORKLOADS))
+    ap.add_argument("--bin", type=int, default=0)
+    ap.add_argument("--schedule", default="load_balance")
+    ap.add_argument("--tpb", type=int, default=0)
+    ap.add_argument("--no-bary", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(scenes/views shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1404_6293_amd import pk
+
+    wl = WORKLOADS[args.workload]
+    sc = make_scene(args.workload)
+    B = args.bin or wl["bin"]
+    sc.bin_size = B
+    cfg = pk.RenderConfig(bin_size=B, schedule=args.schedule, threads_per_bin=args.tpb,
+                          count_frags=True, want_bary=not args.no_bary)
+    print(f"bench: {args.workload} B={B} {args.schedule} steps={args.steps} "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    r = pk.Renderer(sc, cfg)
+    r.render()                       # sizes the bin-pair capacity once
+    torch.cuda.synchronize()
+    frags = int(r.frag_count.item())
+    npairs = int(r.pairs_needed.item())
+    covered = int((r.out_primid >= 0).sum().item())
+    for _ in range(args.warmup):
+        r.frame()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        e = ev[k]
+        if cfg.count_frags:
+            r.frag_count.zero_()
+        e[0].record(stream)
+        r.setup()
+        e[1].record(stream)
+        r.assign_bin()
+        e[2].record(stream)
+        r.raster_shade()
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert not r.ensure_capacity(), "bin-pair capacity changed during the timed region"
+    stage = {"setup": 0.0, "assign_bin": 0.0, "raster_shade": 0.0}
+    for e in ev:
+        stage["setup"] += e[0].elapsed_time(e[1])
+        stage["assign_bin"] += e[1].elapsed_time(e[2])
+        stage["raster_shade"] += e[2].elapsed_time(e[3])
+    stage = {k: v / K for k, v in stage.items()}
+    ms = dt * 1e3 / K
+    S = int(getattr(sc, "num_scenes", 1) or 1)
+    tris = int(sc.num_tris) * (S if getattr(sc, "instanced", False) else 1)
+    mtris = tris / (ms * 1e-3) / 1e6
+    gfrags = frags / (ms * 1e-3) / 1e9
+
+    alg = raster_algorithmic_bytes(sc, npairs, covered, not args.no_bary)
+    achieved = alg / (stage["raster_shade"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_raster", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "alg_bytes_per_launch": alg,
+                "avg_launch_ms": round(stage["raster_shade"], 4)}
+    out = {
+        "metric": "Mtris/s + Gfrags/s at 1080p (binned raster); batched/backward vs plain, 1 GPU",
+        "value": round(mtris, 2), "unit": "Mtris/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64+f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "bin_size": B,
+                   "schedule": args.schedule, "triangles": tris,
+                   "resolution": f"{sc.width}x{sc.height}", "scenes": S},
+        "gfrags_per_s": round(gfrags, 3), "fragments_per_frame": frags,
+        "bin_pairs_per_frame": npairs, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(sc)
+        cb["host"] = platform.processor() or platform.machine()
+        cb["host_cpus"] = os.cpu_count()
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * pk.h -- C ABI of an MI355X (gfx950) spatially-binned software rasterizer.
+ *
+ * The library implements the sort-middle tiled renderer of Piko (Patney,
+ * Tzeng, Seitz, Owens; Sec. 4.4 "Sort-Middle Tiled Renderer"): a geometry
+ * phase with screen-sized bins (vertex transform and triangle setup), then a
+ * screen-space phase with small square bins.  Each stage is split into the
+ * paper's three phases (Sec. 4.1, Table "phases"):
+ *
+ *   pk_setup        vertex shader + rasterizer setup; the next stage's
+ *                   AssignBin counts are produced in the same kernel
+ *                   (Sec. 5.2.1: a kernel holds Schedule + Process of one
+ *                   stage and AssignBin of the next).
+ *   pk_assign_bin   AssignToBoundingBox (Sec. 4.3, directive table): a prefix
+ *                   sum over the per-bin counts and a scatter into CSR bin
+ *                   lists (Sec. 6, "Bin Management": prefix sums instead of
+ *                   atomically appended lists).
+ *   pk_raster_shade Schedule + Process of the per-bin stage: rasterizer,
+ *                   depth test, fragment shader and composite fused into one
+ *                   kernel per bin (Sec. 5.2.2 kernel fusion; the on-chip
+ *                   depth buffer of Sec. 5.2.4 lives in LDS), followed by the
+ *                   deferred shading pass when requested.
+ *   pk_backward     gradients of an image loss with respect to per-vertex
+ *                   colours and texels (not in the paper).
+ *
+ * Calls follow the paper's statement of the problem: vertices, indices and
+ * attributes in; colour, depth and primitive-ID buffers out; bin size and
+ * schedule as parameters (Sec. 4.1 listing "kernels": Stage<binSizeX,
+ * binSizeY, threadsPerBin, ...>; Sec. 4.3 Schedule directives).
+ *
+ * Conventions that hold for every entry point:
+ *  - Pointers inside pk_mesh, pk_attribs and pk_targets, the workspace and
+ *    every array argument are DEVICE pointers unless marked [host].  The
+ *    pk_params / pk_mesh / pk_attribs / pk_targets structs themselves are
+ *    [host] and read during the call only.
+ *  - The caller owns all memory.  The library never allocates or frees
+ *    device memory, keeps no device state between calls and never
+ *    synchronizes: every call only enqueues kernels on `stream` (a
+ *    hipStream_t; NULL is the default stream) and may be captured into a
+ *    HIP graph.  Results are valid once the stream reaches them.
+ *  - Arguments are validated on the host before anything is enqueued; an
+ *    invalid call returns PK_ERR_INVALID_ARGUMENT (or PK_ERR_UNSUPPORTED)
+ *    and leaves every buffer untouched.  A failed launch returns PK_ERR_HIP.
+ *    No C++ exception crosses the ABI.
+ *  - Pixels are row-major [H][W], row 0 at the bottom of the screen
+ *    (NDC y = -1).  Batched outputs are [S][H][W].
+ *
+ * Fixed numeric conventions (the paper fixes none):
+ *  - A vertex is transformed as clip = MVP * (x, y, z, 1) in float32 with
+ *    each product rounded and the sums taken left to right (no fused
+ *    multiply-add); NDC = clip / w; screen = (ndc + 1) * (W/2, H/2); snapped
+ *    to fixed point with 8 fractional bits, rounding half to even.  A
+ *    triangle is dropped when a vertex has w <= 0, a non-finite value, or a
+ *    screen coordinate outside (-16384, 16384) px, when its area is zero, or
+ *    when no pixel centre lies inside its bounding box.  Both windings draw.
+ *  - Pixel (x, y) is sampled at its centre.  Coverage uses exact integer
+ *    edge functions with a top-left fill rule in y-up coordinates (an edge
+ *    owns its samples when the interior lies to its right in +x, or below
+ *    it for horizontal edges), so triangles sharing edges never double-cover.
+ *  - Depth is z_ndc interpolated with float64 screen-space barycentrics and
+ *    rounded to float32; fragments with z outside [0, 1) are discarded; the
+ *    visible fragment is the one with the smallest (depth, triangle index)
+ *    pair, i.e. a less-than test in submission order.  Results are therefore
+ *    independent of bin size, schedule and batching, bit for bit.
+ *  - Colours, UVs and normals are interpolated perspective-correctly in
+ *    float32.  Empty pixels: colour 0, depth 1, primid -1, bary 0.
+ */
+#ifndef PK_H
+#define PK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PK_OK = 0,
+    PK_ERR_INVALID_ARGUMENT = 1, /* bad parameter; nothing was enqueued */
+    PK_ERR_CAPACITY = 2,         /* reserved: pair overflow is reported on the device */
+    PK_ERR_HIP = 3,              /* a HIP runtime call or launch failed */
+    PK_ERR_UNSUPPORTED = 4       /* valid request this build does not implement */
+} pk_status;
+
+/* Schedule directives of the paper (Sec. 4.3 directive table; Sec. 6
+ * "Work-Group Organization"). */
+typedef enum {
+    PK_SCHED_LOAD_BALANCE = 0, /* one workgroup per bin, hardware dispatcher balances */
+    PK_SCHED_DIRECT_MAP = 1,   /* G persistent workgroups; bin b runs on workgroup b mod G */
+    PK_SCHED_DYNAMIC = 2       /* G persistent workgroups pop bins from a device counter */
+} pk_schedule;
+
+typedef enum {
+    PK_SHADE_GOURAUD = 0,  /* colour = perspective-correct vertex colour */
+    PK_SHADE_TEXTURED = 1, /* colour = Gouraud colour * bilinear texture(uv) */
+    PK_SHADE_DEFERRED = 2  /* write G-buffer (unit normal, albedo), then
+                              colour = albedo * sum_l max(0, n . l_l) */
+} pk_shading;
+
+enum {
+    PK_FLAG_COUNT_FRAGS = 1 /* add the number of covered samples (before the
+                               depth test) to *targets.frag_count */
+};
+
+typedef struct {               /* [host] */
+    int32_t width, height;     /* 1..8192 pixels */
+    int32_t bin_size;          /* screen-space bin edge: 8, 16, 32 or 64 pixels */
+    int32_t schedule;          /* pk_schedule */
+    int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto */
+    int32_t shading;           /* pk_shading */
+    int32_t flags;             /* PK_FLAG_* */
+    int32_t num_scenes;        /* S >= 1 */
+    int32_t instanced;         /* S > 1 only: 1 = S views (one MVP each) of the same
+                                  mesh; 0 = S concatenated scenes (scene_*_off) */
+    int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC workgroup count; 0 = auto */
+} pk_params;
+
+typedef struct {                 /* [host] struct of device pointers */
+    const float *pos;            /* SoA [3][V] float32: x plane, y plane, z plane */
+    int32_t num_vertices;        /* V over all scenes */
+    const int32_t *indices;      /* [T][3] int32 (scene-local vertex numbers), or NULL:
+                                    triangle t of a scene uses its vertices 3t, 3t+1, 3t+2 */
+    int32_t num_tris;            /* T: all scenes (concatenated) or the one mesh (instanced) */
+    const float *mvp;            /* [S][16] float32 row-major acting on column vectors
+                                    (clip_r = sum_c m[4r+c] v_c), or NULL = identity */
+    const int32_t *scene_tri_off;/* [S+1] first triangle of each scene; concatenated S > 1 only */
+    const int32_t *scene_vtx_off;/* [S+1] first vertex of each scene;   concatenated S > 1 only */
+} pk_mesh;
+
+typedef struct {                 /* [host] struct of device pointers */
+    const float *color;          /* [3][V] per-vertex RGB (albedo for DEFERRED) */
+    const float *uv;             /* [2][V] texture coordinates, TEXTURED only */
+    const float *normal;         /* [3][V] per-vertex normals, DEFERRED only */
+    const float *texture;        /* [tex_h][tex_w][3] float32, TEXTURED only; texel
+                                    centres at ((i+1/2)/tex_w, (j+1/2)/tex_h), clamp to edge */
+    int32_t tex_w, tex_h;
+    const float *lights;         /* [num_lights][3] unit directions, DEFERRED only */
+    int32_t num_lights;
+} pk_attribs;
+
+typedef struct {                 /* [host] struct of device pointers; outputs [S][H][W](...) */
+    float *color;                /* [..][4] RGBA float32, alpha 1 where covered */
+    float *depth;                /* [..] float32 */
+    int32_t *primid;             /* [..] scene-local triangle index, -1 where empty */
+    float *bary;                 /* [..][2] perspective-correct (b1, b2), or NULL */
+    float *gbuf_normal;          /* [..][3] unit normal; required for DEFERRED */
+    float *gbuf_albedo;          /* [..][3] albedo;      required for DEFERRED */
+    unsigned long long *frag_count; /* one counter (PK_FLAG_COUNT_FRAGS), accumulated */
+} pk_targets;
+
+/* Size in bytes of the workspace that pk_setup / pk_assign_bin /
+ * pk_raster_shade share for one frame: per-triangle setup records and
+ * bounding boxes (num_tris triangles, times S when instanced), per-bin
+ * counters and offsets, and room for pair_capacity (bin, triangle) pairs.
+ * Returns 0 for invalid parameters.  Host-only; no HIP call. */
+size_t pk_workspace_bytes(const pk_params *p, int32_t num_tris, int64_t pair_capacity);
+
+/* Vertex transform and triangle setup of every triangle (of every scene),
+ * plus the per-bin triangle counts of AssignToBoundingBox.  Writes the
+ * workspace only.  Sec. 7.1 stage list (Vertex Shader, Rasterizer setup);
+ * Sec. 5.2.1 basic kernel mapping. */
+pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream);
+
+/* AssignToBoundingBox (Sec. 4.3): exclusive prefix sum of the per-bin counts
+ * and scatter of triangle indices into CSR bin lists inside the workspace.
+ * *pairs_needed (device, one int64) receives the total number of (bin,
+ * triangle) pairs.  If it exceeds pair_capacity, no list is written and the
+ * following pk_raster_shade writes no pixel; call again with a larger
+ * workspace.  The order of triangles inside one bin is unspecified. */
+pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t pair_capacity,
+                        int64_t *pairs_needed, void *stream);
+
+/* Schedule + Process of the screen-space stage for every bin of every scene:
+ * coverage, depth test in an LDS-resident tile, resolve and shading, writing
+ * every pixel of every target that is non-NULL (Sec. 4.4 sort-middle renderer;
+ * Sec. 5.2.2 fusion of Rasterizer, Fragment Shader, Depth Test, Composite).
+ * With PK_SHADE_DEFERRED the colour comes from a second pass over the
+ * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace. */
+pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
+                          const pk_targets *out, void *stream);
+
+/* Backward pass of Gouraud (or textured) shading: from the forward's saved
+ * primid and bary buffers and the upstream gradient grad_color [S][H][W][4]
+ * (alpha ignored), ACCUMULATE dL/d(vertex colour) into grad_vcolor [3][V] and,
+ * for TEXTURED, dL/d(texel) into grad_tex [tex_h][tex_w][3] (may be NULL
+ * otherwise).  Coverage is not differentiated: nothing flows to positions,
+ * UVs or alpha.  Summation order is unspecified (float32 atomics). */
+pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
+                      const int32_t *primid, const float *bary, const float *grad_color,
+                      float *grad_vcolor, float *grad_tex, void *stream);
+
+/* Where the CSR bin lists written by pk_assign_bin live inside `ws`, for
+ * callers that consume or check them (AssignToBoundingBox, Sec. 4.3).
+ * bin_offsets has num_bins + 1 entries (bins of scene s are numbered
+ * s * bins_per_scene + by * ceil(W/bin_size) + bx); bin_tris holds the
+ * triangle numbers (s * T + t for instanced views, the concatenated index
+ * otherwise).  Host-only: computes addresses, launches nothing. */
+typedef struct {
+    const int32_t *bin_offsets;  /* device */
+    const int32_t *bin_tris;     /* device */
+    int64_t num_bins;
+} pk_bin_view;
+
+pk_status pk_bin_lists(const pk_params *p, int32_t num_tris, void *ws, pk_bin_view *out);
+
+/* Static description of a status code.  Host-only. */
+const char *pk_status_string(pk_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PK_H */

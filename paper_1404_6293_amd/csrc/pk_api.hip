@@ -1,0 +1,252 @@
+// pk_api.hip -- the C ABI of libpk (include/pk.h): host-side validation,
+// workspace layout and kernel launches.  No allocation, no synchronization.
+#include <new>
+
+#include "pk_internal.h"
+
+namespace pk {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2_bin(int b) { return b == 8 || b == 16 || b == 32 || b == 64; }
+
+int ilog2(int b) { int l = 0; while ((1 << l) < b) ++l; return l; }
+
+// Host-side view of the parameters that every entry point shares.
+struct Frame {
+    int64_t items = 0;
+    int64_t nbins_scene = 0;
+    int64_t nbins_total = 0;
+    int nbx = 0, nby = 0;
+};
+
+pk_status check_params(const pk_params *p, Frame &f) {
+    if (!p) return PK_ERR_INVALID_ARGUMENT;
+    if (p->width < 1 || p->width > 8192 || p->height < 1 || p->height > 8192)
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->bin_size == 0) return PK_ERR_UNSUPPORTED;   // whole-screen bins: not in this build
+    if (!is_pow2_bin(p->bin_size)) return PK_ERR_INVALID_ARGUMENT;
+    if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_DYNAMIC)
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->threads_per_bin != 0 && p->threads_per_bin != 64 && p->threads_per_bin != 128 &&
+        p->threads_per_bin != 256)
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_DEFERRED)
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->flags & ~PK_FLAG_COUNT_FRAGS) return PK_ERR_INVALID_ARGUMENT;
+    if (p->num_scenes < 1) return PK_ERR_INVALID_ARGUMENT;
+    if (p->instanced != 0 && p->instanced != 1) return PK_ERR_INVALID_ARGUMENT;
+    if (p->persistent_groups < 0) return PK_ERR_INVALID_ARGUMENT;
+    f.nbx = (p->width + p->bin_size - 1) / p->bin_size;
+    f.nby = (p->height + p->bin_size - 1) / p->bin_size;
+    f.nbins_scene = (int64_t)f.nbx * f.nby;
+    f.nbins_total = f.nbins_scene * p->num_scenes;
+    if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    if ((int64_t)p->num_scenes * p->width * p->height > (int64_t)1 << 40)
+        return PK_ERR_INVALID_ARGUMENT;
+    return PK_OK;
+}
+
+pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
+    if (!m) return PK_ERR_INVALID_ARGUMENT;
+    if (m->num_tris < 0 || m->num_vertices < 0) return PK_ERR_INVALID_ARGUMENT;
+    if (m->num_tris > 0 && (!m->pos || m->num_vertices == 0)) return PK_ERR_INVALID_ARGUMENT;
+    if (p->num_scenes > 1 && !p->instanced && (!m->scene_tri_off || !m->scene_vtx_off))
+        return PK_ERR_INVALID_ARGUMENT;
+    f.items = p->instanced ? (int64_t)m->num_tris * p->num_scenes : m->num_tris;
+    if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    return PK_OK;
+}
+
+struct Layout {
+    size_t rec, bbox, bin_count, bin_off, cursor, misc, pairs, total;
+};
+
+Layout layout(const Frame &f, int64_t pair_capacity) {
+    Layout L;
+    size_t o = 0;
+    L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
+    L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
+    L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
+    L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
+    L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
+    L.misc = o;      o = align_up(o + sizeof(uint32_t) * 64);
+    L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
+    L.total = o;
+    return L;
+}
+
+// The pair list is the last slice: pair_capacity changes the total size
+// only, so every call carves the same addresses.
+Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
+    const Layout L = layout(f, pair_capacity);
+    char *b = static_cast<char *>(ws);
+    Ws w;
+    w.rec = reinterpret_cast<TriRec *>(b + L.rec);
+    w.bbox = reinterpret_cast<uint64_t *>(b + L.bbox);
+    w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
+    w.bin_off = reinterpret_cast<int32_t *>(b + L.bin_off);
+    w.cursor = reinterpret_cast<int32_t *>(b + L.cursor);
+    w.misc = reinterpret_cast<uint32_t *>(b + L.misc);
+    w.pairs = reinterpret_cast<int32_t *>(b + L.pairs);
+    w.pair_capacity = pair_capacity;
+    return w;
+}
+
+Geom geom(const pk_params *p, const pk_mesh *m, const Frame &f) {
+    Geom G;
+    G.pos = m->pos;
+    G.V = m->num_vertices;
+    G.idx = m->indices;
+    G.T = m->num_tris;
+    G.mvp = m->mvp;
+    G.tri_off = m->scene_tri_off;
+    G.vtx_off = m->scene_vtx_off;
+    G.W = p->width;
+    G.H = p->height;
+    G.B = p->bin_size;
+    G.log2B = ilog2(p->bin_size);
+    G.nbx = f.nbx;
+    G.nby = f.nby;
+    G.nbins_scene = (int32_t)f.nbins_scene;
+    G.S = p->num_scenes;
+    G.instanced = (p->num_scenes > 1) ? p->instanced : 0;
+    G.items = f.items;
+    G.nbins_total = f.nbins_total;
+    return G;
+}
+
+pk_status hip_status(hipError_t e) { return e == hipSuccess ? PK_OK : PK_ERR_HIP; }
+
+}  // namespace
+}  // namespace pk
+
+using namespace pk;
+
+extern "C" {
+
+size_t pk_workspace_bytes(const pk_params *p, int32_t num_tris, int64_t pair_capacity) {
+    Frame f;
+    if (check_params(p, f) != PK_OK || num_tris < 0 || pair_capacity < 0 ||
+        pair_capacity >= (int64_t)INT32_MAX)
+        return 0;
+    f.items = p->instanced ? (int64_t)num_tris * p->num_scenes : num_tris;
+    if (f.items >= (int64_t)INT32_MAX) return 0;
+    return layout(f, pair_capacity).total;
+}
+
+pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (!ws) return PK_ERR_INVALID_ARGUMENT;
+    const Geom G = geom(p, m, f);
+    return hip_status(launch_setup(G, carve(ws, f, 0), (hipStream_t)stream));
+}
+
+pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t pair_capacity,
+                        int64_t *pairs_needed, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (!ws || pair_capacity < 0 || pair_capacity >= (int64_t)INT32_MAX)
+        return PK_ERR_INVALID_ARGUMENT;
+    const Geom G = geom(p, m, f);
+    const Ws w = carve(ws, f, pair_capacity);
+    hipError_t e = launch_scan(G, w, pairs_needed, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_scatter(G, w, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
+                          const pk_targets *out, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (!ws || !a || !out) return PK_ERR_INVALID_ARGUMENT;
+    if (f.items > 0 && !a->color) return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_TEXTURED &&
+        (!a->uv || !a->texture || a->tex_w < 1 || a->tex_h < 1))
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_DEFERRED &&
+        (!a->normal || !out->gbuf_normal || !out->gbuf_albedo || !out->primid || !out->color ||
+         a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
+        return PK_ERR_INVALID_ARGUMENT;
+    if ((p->flags & PK_FLAG_COUNT_FRAGS) && !out->frag_count) return PK_ERR_INVALID_ARGUMENT;
+    const Geom G = geom(p, m, f);
+    Shade sh;
+    sh.color = a->color; sh.uv = a->uv; sh.normal = a->normal; sh.texture = a->texture;
+    sh.lights = a->lights; sh.tex_w = a->tex_w; sh.tex_h = a->tex_h;
+    sh.num_lights = a->num_lights; sh.shading = p->shading;
+    sh.out_color = out->color; sh.out_depth = out->depth; sh.out_bary = out->bary;
+    sh.gbuf_n = p->shading == PK_SHADE_DEFERRED ? out->gbuf_normal : nullptr;
+    sh.gbuf_a = p->shading == PK_SHADE_DEFERRED ? out->gbuf_albedo : nullptr;
+    sh.out_primid = out->primid;
+    sh.flags = p->flags;
+    sh.frag_count = (p->flags & PK_FLAG_COUNT_FRAGS) ? out->frag_count : nullptr;
+    int tpb = p->threads_per_bin;
+    if (tpb == 0) tpb = p->bin_size <= 8 ? 64 : 256;
+    int groups = p->persistent_groups;
+    if (groups == 0) groups = 256 * 8;
+    // the pair list is the last slice, so its address does not depend on the
+    // capacity; the lists are read through bin_off only
+    const Ws w = carve(ws, f, 0);
+    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups, (hipStream_t)stream);
+    if (e == hipSuccess && p->shading == PK_SHADE_DEFERRED)
+        e = launch_deferred(G, sh, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
+                      const int32_t *primid, const float *bary, const float *grad_color,
+                      float *grad_vcolor, float *grad_tex, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (p->shading == PK_SHADE_DEFERRED) return PK_ERR_UNSUPPORTED;
+    if (!a || !primid || !bary || !grad_color || !grad_vcolor || !a->color)
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_TEXTURED &&
+        (!a->uv || !a->texture || !grad_tex || a->tex_w < 1 || a->tex_h < 1))
+        return PK_ERR_INVALID_ARGUMENT;
+    const Geom G = geom(p, m, f);
+    Shade sh{};
+    sh.color = a->color; sh.uv = a->uv; sh.texture = a->texture;
+    sh.tex_w = a->tex_w; sh.tex_h = a->tex_h; sh.shading = p->shading;
+    return hip_status(launch_backward(G, sh, primid, bary, grad_color, grad_vcolor, grad_tex,
+                                      (hipStream_t)stream));
+}
+
+pk_status pk_bin_lists(const pk_params *p, int32_t num_tris, void *ws, pk_bin_view *out) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if (!ws || !out || num_tris < 0) return PK_ERR_INVALID_ARGUMENT;
+    f.items = p->instanced ? (int64_t)num_tris * p->num_scenes : num_tris;
+    if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    const Ws w = carve(ws, f, 0);
+    out->bin_offsets = w.bin_off;
+    out->bin_tris = w.pairs;
+    out->num_bins = f.nbins_total;
+    return PK_OK;
+}
+
+const char *pk_status_string(pk_status s) {
+    switch (s) {
+    case PK_OK: return "ok";
+    case PK_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case PK_ERR_CAPACITY: return "pair capacity exceeded";
+    case PK_ERR_HIP: return "HIP runtime error";
+    case PK_ERR_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// pk_internal.h -- device-side data layout and helpers shared by the HIP
+// kernels of libpk (never installed; the public ABI is include/pk.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pk.h"
+
+#pragma clang fp contract(off)
+
+namespace pk {
+
+constexpr int kWave = 64;
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Per-triangle setup record, 64 bytes so one aligned record is half of a
+// 128-byte cache line and loads as four dwordx4.
+struct __align__(16) TriRec {
+    int32_t X0, Y0, X1, Y1;   // fixed-point screen vertices (8 fractional bits)
+    int32_t X2, Y2;
+    float z0, z1;             // NDC depth per vertex
+    float z2, iw0, iw1, iw2;  // 1/w per vertex
+    uint64_t bbox;            // x0 | x1 << 16 | y0 << 32 | y1 << 48 (inclusive pixels)
+    double sinv;              // sign(A2) / |A2|
+};
+static_assert(sizeof(TriRec) == 64, "setup record must stay 64 bytes");
+
+// Everything the geometry kernels need about the mesh and the bin grid.
+struct Geom {
+    const float *pos;
+    int64_t V;
+    const int32_t *idx;
+    int32_t T;                 // triangles of the mesh (instanced) or of all scenes
+    const float *mvp;
+    const int32_t *tri_off;
+    const int32_t *vtx_off;
+    int32_t W, H, B, log2B;
+    int32_t nbx, nby, nbins_scene;
+    int32_t S, instanced;
+    int64_t items;             // instanced ? S*T : T
+    int64_t nbins_total;       // S * nbins_scene
+};
+
+// Workspace slices (device pointers carved out of the caller's buffer).
+struct Ws {
+    TriRec *rec;               // [items]
+    uint64_t *bbox;            // [items], kEmptyKey for culled triangles
+    uint32_t *bin_count;       // [nbins_total]
+    int32_t *bin_off;          // [nbins_total + 1]
+    int32_t *cursor;           // [nbins_total]
+    uint32_t *misc;            // [64]: 0 dynamic queue head, 1 pair overflow flag
+    int32_t *pairs;            // [pair_capacity]
+    int64_t pair_capacity;
+};
+
+struct Shade {
+    const float *color, *uv, *normal, *texture, *lights;
+    int32_t tex_w, tex_h, num_lights, shading;
+    float *out_color, *out_depth, *out_bary, *gbuf_n, *gbuf_a;
+    int32_t *out_primid;
+    unsigned long long *frag_count;
+    int32_t flags;
+};
+
+// Which scene an item belongs to and which triangle of the mesh it is.
+struct ItemRef {
+    int32_t s;       // scene
+    int32_t t;       // scene-local triangle index (the primitive ID)
+    int64_t g;       // index into the index buffer
+    int64_t vbase;   // added to scene-local vertex numbers
+};
+
+__device__ inline ItemRef item_ref(const Geom &G, int64_t item) {
+    ItemRef r;
+    if (G.S == 1) {
+        r.s = 0; r.t = (int32_t)item; r.g = item; r.vbase = 0;
+    } else if (G.instanced) {
+        r.s = (int32_t)(item / G.T);
+        r.t = (int32_t)(item - (int64_t)r.s * G.T);
+        r.g = r.t; r.vbase = 0;
+    } else {
+        int lo = 0, hi = G.S - 1;          // last scene with tri_off[s] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (G.tri_off[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        r.s = lo;
+        r.t = (int32_t)(item - G.tri_off[lo]);
+        r.g = item;
+        r.vbase = G.vtx_off[lo];
+    }
+    return r;
+}
+
+__device__ inline int64_t vertex_of(const Geom &G, const ItemRef &r, int k) {
+    const int64_t local = G.idx ? (int64_t)G.idx[3 * r.g + k] : 3 * (int64_t)r.t + k;
+    return r.vbase + local;
+}
+
+// Vertex shader stage: clip = MVP (x,y,z,1) with every product rounded and
+// the sums taken left to right, divide, viewport, 8-bit sub-pixel snap
+// (round half to even).  Returns false for a vertex that drops its triangle.
+__device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, int32_t &X,
+                                    int32_t &Y, float &z, float &iw) {
+    const float x = G.pos[v], y = G.pos[G.V + v], zz = G.pos[2 * G.V + v];
+    float c0, c1, c2, c3;
+    if (m) {
+        float t;
+        t = m[0] * x;  t = t + m[1] * y;  t = t + m[2] * zz;  t = t + m[3];  c0 = t;
+        t = m[4] * x;  t = t + m[5] * y;  t = t + m[6] * zz;  t = t + m[7];  c1 = t;
+        t = m[8] * x;  t = t + m[9] * y;  t = t + m[10] * zz; t = t + m[11]; c2 = t;
+        t = m[12] * x; t = t + m[13] * y; t = t + m[14] * zz; t = t + m[15]; c3 = t;
+    } else {
+        c0 = x; c1 = y; c2 = zz; c3 = 1.0f;
+    }
+    bool ok = __builtin_isfinite(c0) && __builtin_isfinite(c1) && __builtin_isfinite(c2) &&
+              __builtin_isfinite(c3) && c3 > 0.0f;
+    const float xn = c0 / c3;
+    const float yn = c1 / c3;
+    const float zn = c2 / c3;
+    const float w1 = 1.0f / c3;
+    const float xs = (xn + 1.0f) * (0.5f * (float)G.W);
+    const float ys = (yn + 1.0f) * (0.5f * (float)G.H);
+    ok = ok && __builtin_isfinite(zn) && __builtin_isfinite(w1);
+    ok = ok && fabsf(xs) < 16384.0f && fabsf(ys) < 16384.0f;
+    if (!ok) return false;
+    X = (int32_t)rintf(xs * 256.0f);
+    Y = (int32_t)rintf(ys * 256.0f);
+    z = zn;
+    iw = w1;
+    return true;
+}
+
+__device__ inline uint32_t bb_x0(uint64_t b) { return (uint32_t)(b & 0xffff); }
+__device__ inline uint32_t bb_x1(uint64_t b) { return (uint32_t)((b >> 16) & 0xffff); }
+__device__ inline uint32_t bb_y0(uint64_t b) { return (uint32_t)((b >> 32) & 0xffff); }
+__device__ inline uint32_t bb_y1(uint64_t b) { return (uint32_t)(b >> 48); }
+
+// Exclusive scan of one int per thread over a workgroup of TPB threads.
+// s_wave needs TPB/64 ints.  Contains barriers: call from uniform control flow.
+template <int TPB>
+__device__ inline int block_exclusive_scan(int v, int *s_wave, int &total) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) s_wave[wid] = x;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < TPB / kWave; ++w) {
+        const int t = s_wave[w];
+        before += (w < wid) ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return before + x - v;
+}
+
+// Host launchers (defined in the .hip files).
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st);
+hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
+hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st);
+hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
+                         int groups, hipStream_t st);
+hipError_t launch_deferred(const Geom &G, const Shade &sh, hipStream_t st);
+hipError_t launch_backward(const Geom &G, const Shade &sh, const int32_t *primid,
+                           const float *bary, const float *grad, float *grad_vcolor,
+                           float *grad_tex, hipStream_t st);
+
+}  // namespace pk

@@ -1,0 +1,309 @@
+"""Python binding of libpk (include/pk.h): argument marshalling only.
+
+Every step of the pipeline runs in the HIP kernels of ``libpk.so``; this
+module mirrors the C structs with ctypes, hands device pointers of torch
+tensors to the library and enqueues on torch's current stream.  PyTorch is
+used for device memory and streams only.  If the library is missing the
+calls raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpk.so")
+
+# enums of pk.h
+PK_OK, PK_ERR_INVALID_ARGUMENT, PK_ERR_CAPACITY, PK_ERR_HIP, PK_ERR_UNSUPPORTED = range(5)
+PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC = range(3)
+PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED = range(3)
+PK_FLAG_COUNT_FRAGS = 1
+
+SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIRECT_MAP,
+             "dynamic": PK_SCHED_DYNAMIC}
+SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
+            "deferred": PK_SHADE_DEFERRED}
+
+EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_backward",
+           "pk_bin_lists", "pk_status_string")
+
+
+class PkError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {msg} (status {status})")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bin_size", C.c_int32),
+                ("schedule", C.c_int32), ("threads_per_bin", C.c_int32), ("shading", C.c_int32),
+                ("flags", C.c_int32), ("num_scenes", C.c_int32), ("instanced", C.c_int32),
+                ("persistent_groups", C.c_int32)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("num_vertices", C.c_int32), ("indices", C.c_void_p),
+                ("num_tris", C.c_int32), ("mvp", C.c_void_p), ("scene_tri_off", C.c_void_p),
+                ("scene_vtx_off", C.c_void_p)]
+
+
+class Attribs(C.Structure):
+    _fields_ = [("color", C.c_void_p), ("uv", C.c_void_p), ("normal", C.c_void_p),
+                ("texture", C.c_void_p), ("tex_w", C.c_int32), ("tex_h", C.c_int32),
+                ("lights", C.c_void_p), ("num_lights", C.c_int32)]
+
+
+class BinView(C.Structure):
+    _fields_ = [("bin_offsets", C.c_void_p), ("bin_tris", C.c_void_p), ("num_bins", C.c_int64)]
+
+
+class Targets(C.Structure):
+    _fields_ = [("color", C.c_void_p), ("depth", C.c_void_p), ("primid", C.c_void_p),
+                ("bary", C.c_void_p), ("gbuf_normal", C.c_void_p), ("gbuf_albedo", C.c_void_p),
+                ("frag_count", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpk.so (built in-tree by ``paper_1404_6293_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1404_6293_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.pk_workspace_bytes.restype = C.c_size_t
+        L.pk_workspace_bytes.argtypes = [P, C.c_int32, C.c_int64]
+        L.pk_setup.restype = C.c_int
+        L.pk_setup.argtypes = [P, P, P, P]
+        L.pk_assign_bin.restype = C.c_int
+        L.pk_assign_bin.argtypes = [P, P, P, C.c_int64, P, P]
+        L.pk_raster_shade.restype = C.c_int
+        L.pk_raster_shade.argtypes = [P, P, P, P, P, P]
+        L.pk_backward.restype = C.c_int
+        L.pk_backward.argtypes = [P, P, P, P, P, P, P, P, P]
+        L.pk_bin_lists.restype = C.c_int
+        L.pk_bin_lists.argtypes = [P, C.c_int32, P, P]
+        L.pk_status_string.restype = C.c_char_p
+        L.pk_status_string.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().pk_status_string(status).decode()
+
+
+def _check(fn: str, status: int):
+    if status != PK_OK:
+        raise PkError(fn, status, status_string(status))
+
+
+def _ref(x):
+    return None if x is None else C.byref(x)
+
+
+# --- the four calls of the ABI, same names -------------------------------
+def pk_workspace_bytes(params: Params, num_tris: int, pair_capacity: int) -> int:
+    return int(lib().pk_workspace_bytes(C.byref(params), int(num_tris), int(pair_capacity)))
+
+
+def pk_setup(params: Params, mesh: Mesh, ws: int, stream: int = 0):
+    _check("pk_setup", lib().pk_setup(_ref(params), _ref(mesh), ws, stream))
+
+
+def pk_assign_bin(params: Params, mesh: Mesh, ws: int, pair_capacity: int, pairs_needed: int,
+                  stream: int = 0):
+    _check("pk_assign_bin", lib().pk_assign_bin(_ref(params), _ref(mesh), ws, int(pair_capacity),
+                                                pairs_needed, stream))
+
+
+def pk_raster_shade(params: Params, mesh: Mesh, attribs: Attribs, ws: int, targets: Targets,
+                    stream: int = 0):
+    _check("pk_raster_shade", lib().pk_raster_shade(_ref(params), _ref(mesh), _ref(attribs), ws,
+                                                    _ref(targets), stream))
+
+
+def pk_backward(params: Params, mesh: Mesh, attribs: Attribs, primid: int, bary: int,
+                grad_color: int, grad_vcolor: int, grad_tex: int, stream: int = 0):
+    _check("pk_backward", lib().pk_backward(_ref(params), _ref(mesh), _ref(attribs), primid, bary,
+                                            grad_color, grad_vcolor, grad_tex, stream))
+
+
+def pk_bin_lists(params: Params, num_tris: int, ws: int) -> BinView:
+    v = BinView()
+    _check("pk_bin_lists", lib().pk_bin_lists(_ref(params), int(num_tris), ws, C.byref(v)))
+    return v
+
+
+# --- convenience layer over torch device memory ---------------------------
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class RenderConfig:
+    bin_size: int = 16
+    schedule: str = "load_balance"
+    threads_per_bin: int = 0
+    persistent_groups: int = 0
+    count_frags: bool = False
+    want_bary: bool = True
+
+
+class Renderer:
+    """Holds one scene (or batch) in device memory and renders it.
+
+    ``scene`` is any object with the attributes of
+    ``paper_1404_6293_amd.scenes.Scene``; its arrays are copied to the GPU
+    once.  ``frame()`` enqueues setup, assign-bin and raster/shade on the
+    current stream without synchronizing; ``render()`` also makes sure the
+    bin-pair capacity sufficed (one device-to-host read) and retries if not.
+    """
+
+    def __init__(self, scene, cfg: RenderConfig = RenderConfig(), device: str = "cuda"):
+        import torch
+        lib()  # fail early and loudly when the library is missing
+        self.torch = torch
+        self.scene = scene
+        self.cfg = cfg
+        dev = torch.device(device)
+        self.device = dev
+
+        def up(a, dtype=None):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype=dtype))
+            return torch.from_numpy(a).to(dev)
+
+        sc = scene
+        self.S = int(getattr(sc, "num_scenes", 1) or 1)
+        self.W, self.H = int(sc.width), int(sc.height)
+        self.pos = up(sc.pos, np.float32)
+        self.idx = up(sc.idx, np.int32) if sc.idx is not None else None
+        self.mvp = up(np.asarray(sc.mvp, np.float32).reshape(-1, 16)) if sc.mvp is not None else None
+        inst = bool(getattr(sc, "instanced", False)) and self.S > 1
+        self.tri_off = up(sc.scene_tri_off, np.int32) if (self.S > 1 and not inst) else None
+        self.vtx_off = up(sc.scene_vtx_off, np.int32) if (self.S > 1 and not inst) else None
+        self.color = up(sc.color, np.float32)
+        self.uv = up(getattr(sc, "uv", None), np.float32)
+        self.normal = up(getattr(sc, "normal", None), np.float32)
+        tex = getattr(sc, "texture", None)
+        self.texture = up(tex, np.float32)
+        lights = getattr(sc, "lights", None)
+        if lights is None:
+            lights = np.array([[1.0, 1.0, 1.0]]) / np.sqrt(3.0)
+        self.lights = up(np.asarray(lights, np.float64).astype(np.float32).reshape(-1, 3))
+        self.shading = SHADINGS[getattr(sc, "shading", "gouraud")]
+
+        self.params = Params(self.W, self.H, int(cfg.bin_size), SCHEDULES[cfg.schedule],
+                             int(cfg.threads_per_bin), self.shading,
+                             PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0, self.S, int(inst),
+                             int(cfg.persistent_groups))
+        self.mesh = Mesh(_ptr(self.pos), int(sc.pos.shape[1]), _ptr(self.idx), int(sc.num_tris),
+                         _ptr(self.mvp), _ptr(self.tri_off), _ptr(self.vtx_off))
+        self.attribs = Attribs(_ptr(self.color), _ptr(self.uv), _ptr(self.normal),
+                               _ptr(self.texture), 0 if tex is None else int(tex.shape[1]),
+                               0 if tex is None else int(tex.shape[0]), _ptr(self.lights),
+                               int(self.lights.shape[0]))
+        S, H, W = self.S, self.H, self.W
+        f32 = torch.float32
+        self.out_color = torch.empty((S, H, W, 4), dtype=f32, device=dev)
+        self.out_depth = torch.empty((S, H, W), dtype=f32, device=dev)
+        self.out_primid = torch.empty((S, H, W), dtype=torch.int32, device=dev)
+        self.out_bary = torch.empty((S, H, W, 2), dtype=f32, device=dev) if cfg.want_bary else None
+        deferred = self.shading == PK_SHADE_DEFERRED
+        self.gbuf_n = torch.empty((S, H, W, 3), dtype=f32, device=dev) if deferred else None
+        self.gbuf_a = torch.empty((S, H, W, 3), dtype=f32, device=dev) if deferred else None
+        self.frag_count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.targets = Targets(_ptr(self.out_color), _ptr(self.out_depth), _ptr(self.out_primid),
+                               _ptr(self.out_bary), _ptr(self.gbuf_n), _ptr(self.gbuf_a),
+                               _ptr(self.frag_count))
+        self.pairs_needed = torch.zeros(1, dtype=torch.int64, device=dev)
+        items = int(sc.num_tris) * (S if inst else 1)
+        self.items = items
+        self._alloc_ws(max(4 * items, 1024))
+
+    def _alloc_ws(self, capacity: int):
+        nbytes = pk_workspace_bytes(self.params, int(self.scene.num_tris), capacity)
+        if nbytes == 0:
+            raise PkError("pk_workspace_bytes", PK_ERR_INVALID_ARGUMENT, "invalid parameters")
+        self.capacity = capacity
+        self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+
+    # stages, one call each
+    def setup(self):
+        pk_setup(self.params, self.mesh, self.ws.data_ptr(), _stream())
+
+    def assign_bin(self):
+        pk_assign_bin(self.params, self.mesh, self.ws.data_ptr(), self.capacity,
+                      self.pairs_needed.data_ptr(), _stream())
+
+    def raster_shade(self):
+        pk_raster_shade(self.params, self.mesh, self.attribs, self.ws.data_ptr(), self.targets,
+                        _stream())
+
+    def frame(self):
+        """Enqueue one whole frame; no synchronization."""
+        if self.cfg.count_frags:
+            self.frag_count.zero_()
+        self.setup()
+        self.assign_bin()
+        self.raster_shade()
+
+    def ensure_capacity(self) -> bool:
+        """Read the pair count of the last frame; grow the workspace and return
+        True when it did not fit (the frame must then be rendered again)."""
+        need = int(self.pairs_needed.item())
+        if need > self.capacity:
+            self._alloc_ws(int(need * 1.25) + 1024)
+            return True
+        return False
+
+    def render(self) -> dict:
+        self.frame()
+        if self.ensure_capacity():
+            self.frame()
+            if self.ensure_capacity():
+                raise PkError("render", PK_ERR_CAPACITY, "pair capacity still exceeded")
+        return self.outputs()
+
+    def outputs(self) -> dict:
+        return dict(color=self.out_color, depth=self.out_depth, primid=self.out_primid,
+                    bary=self.out_bary, gbuf_normal=self.gbuf_n, gbuf_albedo=self.gbuf_a,
+                    frag_count=self.frag_count)
+
+    def bin_lists(self):
+        """CSR bin lists of the last frame, copied to the host for checking:
+        (offsets[nbins_total+1], triangle numbers) as NumPy arrays."""
+        import torch
+        v = pk_bin_lists(self.params, int(self.scene.num_tris), self.ws.data_ptr())
+        base = self.ws.data_ptr()
+        o0 = v.bin_offsets - base
+        off = self.ws[o0:o0 + 4 * (v.num_bins + 1)].view(torch.int32).cpu().numpy().copy()
+        n = int(off[-1])
+        o1 = v.bin_tris - base
+        pairs = self.ws[o1:o1 + 4 * n].view(torch.int32).cpu().numpy().copy()
+        return off, pairs
+
+    def backward(self, grad_color, grad_vcolor, grad_tex=None):
+        """Accumulate dL/d(vertex colour) (and dL/d(texel)) from the saved
+        primid/bary of the last frame and the upstream colour gradient."""
+        if self.out_bary is None:
+            raise ValueError("backward needs the saved barycentrics (want_bary=True)")
+        pk_backward(self.params, self.mesh, self.attribs, _ptr(self.out_primid),
+                    _ptr(self.out_bary), _ptr(grad_color), _ptr(grad_vcolor), _ptr(grad_tex),
+                    _stream())

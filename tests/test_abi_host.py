@@ -1,0 +1,142 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/pk.h declares, validates arguments before it enqueues
+anything, and computes the workspace size and status strings on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1404_6293_amd import pk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pk.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pk.LIB_PATH):
+        from paper_1404_6293_amd import build
+        build.build()
+    return pk.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pk_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ("pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_backward", "pk_workspace_bytes",
+              "pk_status_string", "pk_bin_lists"):
+        assert n in names
+    assert set(names) == set(pk.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def _params(**kw):
+    d = dict(width=64, height=64, bin_size=8, schedule=0, threads_per_bin=0, shading=0, flags=0,
+             num_scenes=1, instanced=0, persistent_groups=0)
+    d.update(kw)
+    return pk.Params(**d)
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails validation first
+
+
+def _mesh(**kw):
+    d = dict(pos=FAKE, num_vertices=3, indices=None, num_tris=1, mvp=None, scene_tri_off=None,
+             scene_vtx_off=None)
+    d.update(kw)
+    return pk.Mesh(**d)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
+    dict(bin_size=-8), dict(schedule=3), dict(schedule=-1), dict(threads_per_bin=32),
+    dict(threads_per_bin=512), dict(shading=3), dict(flags=2), dict(num_scenes=0),
+    dict(instanced=2), dict(persistent_groups=-1)])
+def test_invalid_params_rejected_on_host(L, bad):
+    p = _params(**bad)
+    assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_assign_bin(C.byref(p), C.byref(_mesh()), FAKE, 16, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_workspace_bytes(C.byref(p), 10, 100) == 0
+
+
+def test_whole_screen_bins_unsupported(L):
+    p = _params(bin_size=0)
+    assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_UNSUPPORTED
+
+
+def test_null_and_inconsistent_pointers_rejected(L):
+    p = _params()
+    assert L.pk_setup(None, C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_setup(C.byref(p), None, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_setup(C.byref(p), C.byref(_mesh()), None, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_setup(C.byref(p), C.byref(_mesh(pos=None)), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_setup(C.byref(p), C.byref(_mesh(num_tris=-1)), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # concatenated batches need the scene offsets
+    pb = _params(num_scenes=4)
+    assert L.pk_setup(C.byref(pb), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # pair capacity bounds
+    assert L.pk_assign_bin(C.byref(p), C.byref(_mesh()), FAKE, -1, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_assign_bin(C.byref(p), C.byref(_mesh()), FAKE, 1 << 31, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # raster/shade requirements
+    a = pk.Attribs(color=None)
+    t = pk.Targets()
+    assert L.pk_raster_shade(C.byref(p), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    a = pk.Attribs(color=FAKE)
+    pt = _params(shading=1)
+    assert L.pk_raster_shade(C.byref(pt), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    pd = _params(shading=2)
+    assert L.pk_raster_shade(C.byref(pd), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    pf = _params(flags=1)
+    assert L.pk_raster_shade(C.byref(pf), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    # backward
+    assert L.pk_backward(C.byref(p), C.byref(_mesh()), C.byref(a), None, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_backward(C.byref(pd), C.byref(_mesh()), C.byref(a), FAKE, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_UNSUPPORTED
+    assert L.pk_backward(C.byref(pt), C.byref(_mesh()), C.byref(a), FAKE, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_INVALID_ARGUMENT
+
+
+def test_workspace_bytes_arithmetic(L):
+    p = _params(width=100, height=70, bin_size=16)
+    T = 1000
+    b0 = L.pk_workspace_bytes(C.byref(p), T, 0)
+    b1 = L.pk_workspace_bytes(C.byref(p), T, 64)
+    b2 = L.pk_workspace_bytes(C.byref(p), T, 64 + 1)
+    assert b0 > 0 and b1 - b0 == 256 and b2 - b1 == 256
+    nbins = 7 * 5
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    expect = al(64 * T) + al(8 * T) + al(4 * nbins) + al(4 * (nbins + 1)) + al(4 * nbins) + al(256)
+    assert b0 == expect
+    # instanced views multiply the per-triangle slices
+    pi = _params(width=100, height=70, bin_size=16, num_scenes=3, instanced=1)
+    nb3 = 3 * nbins
+    expect3 = al(64 * 3 * T) + al(8 * 3 * T) + al(4 * nb3) + al(4 * (nb3 + 1)) + al(4 * nb3) + al(256)
+    assert L.pk_workspace_bytes(C.byref(pi), T, 0) == expect3
+    assert L.pk_workspace_bytes(C.byref(p), -1, 0) == 0
+    assert L.pk_workspace_bytes(C.byref(p), T, -5) == 0
+
+
+def test_bin_lists_view_points_into_workspace(L):
+    p = _params(width=100, height=70, bin_size=16)
+    v = pk.BinView()
+    base = 1 << 20
+    assert L.pk_bin_lists(C.byref(p), 1000, base, C.byref(v)) == pk.PK_OK
+    assert v.num_bins == 35
+    size = L.pk_workspace_bytes(C.byref(p), 1000, 0)
+    assert base < v.bin_offsets < v.bin_tris == base + size
+    assert L.pk_bin_lists(C.byref(p), 1000, None, C.byref(v)) == pk.PK_ERR_INVALID_ARGUMENT
+
+
+def test_status_strings(L):
+    for s in range(5):
+        assert pk.status_string(s)
+    assert pk.status_string(99) == "unknown status"
+    assert pk.status_string(pk.PK_ERR_INVALID_ARGUMENT) == "invalid argument"

@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Coverage and primitive IDs must match bit for bit; depth is expected to match
+bit for bit (the winner depends on its bits) and is required within 1e-5
+relative; colours, barycentrics and G-buffers within 1e-5 relative + 1e-6
+absolute (float32 values of order one, one interpolation of three terms).
+Bin lists: per-bin counts exact and per-bin triangle sets equal.
+"""
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1404_6293_amd import pk, scenes
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pk.lib()  # must load: no fallback
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_render(sc, **cfg):
+    import torch
+    r = pk.Renderer(sc, pk.RenderConfig(count_frags=True, **cfg))
+    out = r.render()
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    res["renderer"] = r
+    return res
+
+
+def compare(sc, g, o, check_bary=True, check_color=True):
+    np.testing.assert_array_equal(g["primid"], o["primid"])
+    cov = o["primid"] >= 0
+    np.testing.assert_array_equal(g["depth"][~cov], 1.0)
+    np.testing.assert_allclose(g["depth"], o["depth"], rtol=RTOL, atol=0)
+    assert (g["depth"] == o["depth"]).all(), "depth expected bit-exact"
+    if check_color:
+        np.testing.assert_allclose(g["color"], o["color"], rtol=RTOL, atol=ATOL)
+    if check_bary and o.get("bary") is not None and g.get("bary") is not None:
+        np.testing.assert_allclose(g["bary"], o["bary"], rtol=RTOL, atol=ATOL)
+    assert int(g["frag_count"][0]) == int(o["frag_count"].sum())
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny64_random(seed):
+    _note(f"tiny64 seed={seed}")
+    sc = scenes.tiny(seed=seed)
+    compare(sc, gpu_render(sc, bin_size=8), oracle.render(sc))
+
+
+@pytest.mark.parametrize("W,H,B,T", [(37, 29, 8, 40), (100, 70, 16, 300), (130, 66, 64, 500),
+                                     (1, 1, 8, 20), (257, 3, 32, 100), (64, 200, 8, 1000)])
+def test_ragged_screens(W, H, B, T):
+    _note(f"ragged {W}x{H} B={B} T={T}")
+    sc = scenes.tiny(seed=W * 31 + H, width=W, height=H, num_tris=T)
+    compare(sc, gpu_render(sc, bin_size=B), oracle.render(sc))
+
+
+def test_metamorphic_bins_schedules_threads():
+    """Binning and scheduling change only grouping and placement of work
+    (Sec. 4.1), never the image: every configuration is bit-identical."""
+    sc = scenes.tiny(seed=77, width=150, height=110, num_tris=600)
+    o = oracle.render(sc)
+    ref = None
+    for B in (8, 16, 32, 64):
+        for sched in ("load_balance", "direct_map", "dynamic"):
+            for tpb in (64, 128, 256):
+                _note(f"metamorphic B={B} {sched} tpb={tpb}")
+                g = gpu_render(sc, bin_size=B, schedule=sched, threads_per_bin=tpb,
+                               persistent_groups=7 if sched != "load_balance" else 0)
+                if ref is None:
+                    compare(sc, g, o)
+                    ref = g
+                for k in ("color", "depth", "primid", "bary"):
+                    assert (g[k] == ref[k]).all(), (B, sched, tpb, k)
+
+
+@pytest.mark.parametrize("B", [8, 16, 64])
+def test_bin_lists_match_oracle(B):
+    sc = scenes.tiny(seed=5, width=120, height=90, num_tris=400)
+    g = gpu_render(sc, bin_size=B)
+    off, pairs = g["renderer"].bin_lists()
+    ooff, otris = oracle.assign_bin(sc, B)
+    np.testing.assert_array_equal(off, ooff)
+    for b in range(len(ooff) - 1):
+        assert sorted(pairs[off[b]:off[b + 1]]) == list(otris[ooff[b]:ooff[b + 1]])
+
+
+def test_repeat_runs_bit_identical():
+    import torch
+    sc = scenes.tiny(seed=3, width=96, height=96, num_tris=800)
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="dynamic"))
+    first = {k: v.clone() for k, v in r.render().items() if v is not None}
+    for _ in range(5):
+        out = r.render()
+        for k in ("color", "depth", "primid", "bary"):
+            assert torch.equal(out[k], first[k])
+
+
+def test_grid1080_full_frame():
+    """The 1.05M-triangle grid at 1920x1080 with 16-px bins, the benchmark's
+    launch configuration: full-frame comparison with the oracle."""
+    _note("grid1080 full frame")
+    sc = scenes.grid()
+    g = gpu_render(sc, bin_size=16)
+    o = oracle.render(sc)
+    assert int(g["frag_count"][0]) == 1920 * 1080
+    assert (g["primid"] >= 0).all()
+    compare(sc, g, o)
+
+
+def test_deferred_micropolygons_small():
+    _note("micro small deferred")
+    sc = scenes.micro(seed=11, width=256, height=128, num_tris=60000, num_lights=3)
+    g = gpu_render(sc, bin_size=16)
+    o = oracle.render(sc)
+    compare(sc, g, o)
+    np.testing.assert_allclose(g["gbuf_normal"], o["gbuf_normal"], rtol=RTOL, atol=ATOL)
+    np.testing.assert_allclose(g["gbuf_albedo"], o["gbuf_albedo"], rtol=RTOL, atol=ATOL)
+
+
+def test_deferred_tie_heavy():
+    """Micropolygons with depth quantised to 8 levels: many equal depths, the
+    smaller triangle index must win everywhere."""
+    sc = scenes.micro(seed=12, width=200, height=120, num_tris=80000, z_levels=8)
+    compare(sc, gpu_render(sc, bin_size=32, schedule="dynamic"), oracle.render(sc))
+
+
+def test_textured_views():
+    _note("textured instanced views")
+    sc = scenes.diffgrid(size=96, num_views=3, nx=32, ny=16, tex_size=16)
+    g = gpu_render(sc, bin_size=16)
+    compare(sc, g, oracle.render(sc))
+
+
+def test_batched_scenes_match_per_scene_oracle():
+    _note("batched concatenated scenes")
+    sc = scenes.batch(num_scenes=6, size=64, tmin=50, tmax=3000)
+    g = gpu_render(sc, bin_size=8, schedule="dynamic")
+    compare(sc, g, oracle.render(sc))
+
+
+def test_batched_equals_sequential_plain():
+    import torch
+    sc = scenes.batch(num_scenes=5, size=80, tmin=100, tmax=4000, seed0=900)
+    gb = gpu_render(sc, bin_size=16)
+    for s in range(5):
+        gs = gpu_render(scenes.split_batch(sc, s), bin_size=16)
+        for k in ("color", "depth", "primid", "bary"):
+            assert (gb[k][s] == gs[k][0]).all(), (s, k)
+
+
+def test_empty_and_culled_inputs():
+    # no triangles at all
+    sc = scenes.tiny(seed=1, width=40, height=30, num_tris=1)
+    sc0 = SimpleNamespace(**{**vars(sc), "num_tris": 0})
+    g = gpu_render(sc0, bin_size=8)
+    assert (g["primid"] == -1).all() and (g["depth"] == 1).all() and (g["color"] == 0).all()
+    # every way a triangle gets dropped
+    W = H = 32
+    P = []
+    P += [(0.0, 0.0, 0.5), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5)]                 # kept
+    P += [(0.0, 0.0, 0.5), (0.0, 0.0, 0.5), (0.3, 0.3, 0.5)]                 # zero area
+    P += [(np.nan, 0.0, 0.5), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5)]              # NaN
+    P += [(np.inf, 0.0, 0.5), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5)]              # inf
+    P += [(3.0, 3.0, 0.5), (3.5, 3.0, 0.5), (3.0, 3.5, 0.5)]                 # off screen
+    P += [(2000.0, 0.0, 0.5), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5)]              # guard band
+    P += [(0.01, 0.01, 0.5), (0.012, 0.01, 0.5), (0.01, 0.012, 0.5)]         # no sample inside
+    P += [(-0.5, -0.5, 1.5), (0.5, -0.5, 1.5), (0.0, 0.5, 1.5)]              # z >= 1
+    P += [(-0.5, -0.5, -0.2), (0.5, -0.5, -0.2), (0.0, 0.5, -0.2)]           # z < 0
+    pos = np.asarray(P, np.float32).T.copy()
+    col = np.random.default_rng(0).uniform(0, 1, pos.shape).astype(np.float32)
+    sc = SimpleNamespace(width=W, height=H, pos=pos, color=col, idx=None, num_tris=pos.shape[1] // 3,
+                         mvp=None, num_scenes=1, scene_tri_off=None, scene_vtx_off=None,
+                         instanced=False, uv=None, normal=None, texture=None, lights=None,
+                         shading="gouraud")
+    o = oracle.render(sc)
+    g = gpu_render(sc, bin_size=8)
+    compare(sc, g, o)
+    assert set(np.unique(g["primid"])) <= {-1, 0}
+    # w <= 0 through a matrix that puts w = -z
+    mvp = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, -1, 0], np.float32)
+    sc2 = SimpleNamespace(**{**vars(sc), "mvp": mvp})
+    g2 = gpu_render(sc2, bin_size=8)
+    compare(sc2, g2, oracle.render(sc2))
+
+
+def test_capacity_overflow_then_retry():
+    import torch
+    sc = scenes.tiny(seed=8, width=128, height=128, num_tris=500)
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=8))
+    r._alloc_ws(10)                      # far too small
+    r.frame()
+    torch.cuda.synchronize()
+    need = int(r.pairs_needed.item())
+    assert need > 10
+    # the overflowing frame writes only empty pixels, never out of bounds
+    assert (r.out_primid.cpu().numpy() == -1).all()
+    assert r.ensure_capacity()
+    r.frame()
+    assert not r.ensure_capacity()
+    o = oracle.render(sc)
+    np.testing.assert_array_equal(r.out_primid.cpu().numpy(), o["primid"])
+
+
+def test_backward_matches_oracle_gradient():
+    import torch
+    sc = scenes.diffgrid(size=64, num_views=3, nx=32, ny=16, tex_size=16)
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16))
+    out = r.render()
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((3, 64, 64, 4)).astype(np.float32)
+    gv = torch.zeros((3, sc.pos.shape[1]), dtype=torch.float32, device="cuda")
+    gt = torch.zeros(sc.texture.shape, dtype=torch.float32, device="cuda")
+    r.backward(torch.from_numpy(G).cuda(), gv, gt)
+    torch.cuda.synchronize()
+    pid, bary = out["primid"].cpu().numpy(), out["bary"].cpu().numpy()
+    ov, ot = oracle.backward(sc, pid, bary, G)
+    # float32 atomics sum n terms in any order: |error| <= n eps sum|terms|;
+    # with |G| every term is non-negative, so the oracle gives sum|terms|
+    av, at = oracle.backward(sc, pid, bary, np.abs(G))
+    n = 64
+    eps = 2.0 ** -24
+    assert (np.abs(gv.cpu().numpy() - ov) <= 1e-4 * np.abs(ov) + n * eps * av + 1e-7).all()
+    assert (np.abs(gt.cpu().numpy() - ot) <= 1e-4 * np.abs(ot) + n * eps * at + 1e-7).all()
