@@ -48,7 +48,7 @@
  * Fixed numeric conventions (the paper fixes none):
  *  - A vertex is transformed as clip = MVP * (x, y, z, 1) in float32 with
  *    each product rounded and the sums taken left to right (no fused
- *    multiply-add); NDC = clip / w; screen = (ndc + 1) * (W/2, H/2); snapped
+ *    multiply-add); NDC = clip * (1/w) with one correctly rounded reciprocal; screen = (ndc + 1) * (W/2, H/2); snapped
  *    to fixed point with 8 fractional bits, rounding half to even.  A
  *    triangle is dropped when a vertex has w <= 0, a non-finite value, or a
  *    screen coordinate outside (-16384, 16384) px, when its area is zero, or

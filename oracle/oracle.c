@@ -93,10 +93,11 @@ static ovtx vertex_stage(const orc_scene *s, int64_t v)
     ovtx o;
     memset(&o, 0, sizeof o);
     int ok = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(c[3]) && c[3] > 0.0f;
-    const float xn = c[0] / c[3];
-    const float yn = c[1] / c[3];
-    const float zn = c[2] / c[3];
+    /* one correctly rounded reciprocal of w, then products */
     const float iw = 1.0f / c[3];
+    const float xn = c[0] * iw;
+    const float yn = c[1] * iw;
+    const float zn = c[2] * iw;
     const float xs = (xn + 1.0f) * (0.5f * (float)s->width);
     const float ys = (yn + 1.0f) * (0.5f * (float)s->height);
     ok = ok && isfinite(zn) && isfinite(iw);

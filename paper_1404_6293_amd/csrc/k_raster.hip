@@ -23,6 +23,8 @@
 
 namespace pk {
 
+constexpr int kDynBatch = 4;   // bins taken per pop of a DYNAMIC queue
+
 struct RasterArgs {
     Geom G;
     Ws w;
@@ -158,26 +160,67 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
     __shared__ int32_t s_prim[TPB];   // scene-local triangle index
     __shared__ int32_t s_start[TPB];  // exclusive prefix sum of candidate counts
     __shared__ int32_t s_wave[TPB / kWave];
-    __shared__ int64_t s_bin;
+    __shared__ int64_t s_bin, s_bin_end;
     __shared__ unsigned long long s_frag[TPB / kWave];
 
     const Geom &G = a.G;
     const int tid = threadIdx.x;
     unsigned long long frags = 0;
+    // Bins are split into kXcd contiguous ranges; workgroup w works in range
+    // w mod kXcd (workgroups are dealt to the dies round-robin), so each die's
+    // L2 sees a compact screen region.  The mapping is a bijection whatever
+    // the real placement is; only locality depends on it.
+    const int64_t nb = G.nbins_total;
+    const int64_t q = nb / kXcd, rem = nb % kXcd;
+    const int xcd = blockIdx.x % kXcd;
+    const int64_t r_beg = xcd * q + min<int64_t>(xcd, rem);
+    const int64_t r_len = q + (xcd < rem ? 1 : 0);
+    const int64_t lane_in_xcd = blockIdx.x / kXcd;
+    const int64_t groups_in_xcd = (gridDim.x - xcd + kXcd - 1) / kXcd;
+    // DYNAMIC: current queue (range) and the bins of the last batch taken
+    int qx = xcd, q_tried = 0;
+    int64_t batch_beg = 0, batch_end = 0;
     int64_t iter = 0;
     for (;;) {
         int64_t bin;
         if (a.schedule == PK_SCHED_DYNAMIC) {
-            if (tid == 0) s_bin = (int64_t)atomicAdd(&a.w.misc[0], 1u);
-            __syncthreads();
-            bin = s_bin;
+            if (batch_beg >= batch_end) {
+                // take kDynBatch bins from this die's queue; when it is empty,
+                // move on to the other dies' queues
+                if (tid == 0) {
+                    int64_t b0 = 0, b1 = 0;
+                    while (q_tried < kXcd) {
+                        const int64_t qb = qx * q + min<int64_t>(qx, rem);
+                        const int64_t ql = q + (qx < rem ? 1 : 0);
+                        const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)kDynBatch);
+                        if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + kDynBatch, ql); break; }
+                        qx = (qx + 1) % kXcd;
+                        ++q_tried;
+                    }
+                    s_bin = b0;
+                    s_bin_end = b1;
+                }
+                __syncthreads();
+                batch_beg = s_bin;
+                batch_end = s_bin_end;
+                __syncthreads();
+                if (batch_beg >= batch_end) break;
+            }
+            bin = batch_beg++;
         } else if (a.schedule == PK_SCHED_DIRECT_MAP) {
-            bin = blockIdx.x + iter * (int64_t)gridDim.x;
+            if (gridDim.x < kXcd) {            // too few groups to give every die a range
+                bin = blockIdx.x + iter * (int64_t)gridDim.x;
+                if (bin >= nb) break;
+            } else {
+                const int64_t l = lane_in_xcd + iter * groups_in_xcd;
+                if (l >= r_len) break;
+                bin = r_beg + l;
+            }
         } else {
-            bin = (iter == 0) ? (int64_t)blockIdx.x : G.nbins_total;
+            if (iter > 0 || lane_in_xcd >= r_len) break;
+            bin = r_beg + lane_in_xcd;
         }
         ++iter;
-        if (bin >= G.nbins_total) break;
         const int32_t s = (int32_t)(bin / G.nbins_scene);
         const int32_t lb = (int32_t)(bin - (int64_t)s * G.nbins_scene);
         const int32_t by = lb / G.nbx, bx = lb - by * G.nbx;
@@ -304,7 +347,7 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
         __threadfence();
         const uint32_t done = atomicAdd(&a.w.misc[2], 1u);
         if (done == gridDim.x - 1) {
-            atomicExch(&a.w.misc[0], 0u);
+            for (int i = 0; i < kXcd; ++i) atomicExch(&a.w.misc[8 + i], 0u);
             atomicExch(&a.w.misc[2], 0u);
         }
     }

@@ -70,10 +70,11 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     size_t o = 0;
     L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
     L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
+    // counters and misc words are adjacent so one fill clears both
     L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
+    L.misc = o;      o = align_up(o + sizeof(uint32_t) * 64);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
-    L.misc = o;      o = align_up(o + sizeof(uint32_t) * 64);
     L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
     L.total = o;
     return L;

@@ -11,6 +11,7 @@
 namespace pk {
 
 constexpr int kWave = 64;
+constexpr int kXcd = 8;       // accelerator complex dies of an MI355X
 constexpr unsigned long long kEmptyKey = ~0ull;
 
 // Per-triangle setup record, 64 bytes so one aligned record is half of a
@@ -48,7 +49,8 @@ struct Ws {
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
     int32_t *cursor;           // [nbins_total]
-    uint32_t *misc;            // [64]: 0 dynamic queue head, 1 pair overflow flag
+    uint32_t *misc;            // [64], right after bin_count: 1 pair overflow flag,
+                               // 2 workgroups done (DYNAMIC), 8..15 queue heads
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
 };
@@ -98,8 +100,8 @@ __device__ inline int64_t vertex_of(const Geom &G, const ItemRef &r, int k) {
 }
 
 // Vertex shader stage: clip = MVP (x,y,z,1) with every product rounded and
-// the sums taken left to right, divide, viewport, 8-bit sub-pixel snap
-// (round half to even).  Returns false for a vertex that drops its triangle.
+// the sums taken left to right, NDC = clip * (1/w) with one correctly
+// rounded reciprocal, viewport, 8-bit sub-pixel snap (round half to even).  Returns false for a vertex that drops its triangle.
 __device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, int32_t &X,
                                     int32_t &Y, float &z, float &iw) {
     const float x = G.pos[v], y = G.pos[G.V + v], zz = G.pos[2 * G.V + v];
@@ -115,10 +117,10 @@ __device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, in
     }
     bool ok = __builtin_isfinite(c0) && __builtin_isfinite(c1) && __builtin_isfinite(c2) &&
               __builtin_isfinite(c3) && c3 > 0.0f;
-    const float xn = c0 / c3;
-    const float yn = c1 / c3;
-    const float zn = c2 / c3;
-    const float w1 = 1.0f / c3;
+    const float w1 = 1.0f / c3;     // correctly rounded; NDC = clip * (1/w)
+    const float xn = c0 * w1;
+    const float yn = c1 * w1;
+    const float zn = c2 * w1;
     const float xs = (xn + 1.0f) * (0.5f * (float)G.W);
     const float ys = (yn + 1.0f) * (0.5f * (float)G.H);
     ok = ok && __builtin_isfinite(zn) && __builtin_isfinite(w1);
@@ -159,6 +161,76 @@ __device__ inline int block_exclusive_scan(int v, int *s_wave, int &total) {
     total = tot;
     __syncthreads();
     return before + x - v;
+}
+
+// ---- wave-level aggregation of atomics on per-bin counters -------------
+// Lanes of a wave often target the same bin (consecutive triangles of a
+// mesh are neighbours on screen).  When the wave's keys change at most
+// kCoherent times between neighbouring lanes, lanes are grouped by key and
+// one lane per group issues a single atomic for the whole group; otherwise
+// every lane issues its own.  key < 0 means "no update".  Must be called by
+// every active lane of the wave (uniform control flow).
+constexpr int kCoherent = 16;
+
+__device__ inline uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & (kWave - 1);
+    return lane ? (~0ull >> (kWave - lane)) : 0ull;
+}
+
+__device__ inline bool wave_keys_coherent(int key) {
+    const int prev = __shfl_up(key, 1, kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool boundary = key >= 0 && (lane == 0 || key != prev);
+    return __popcll(__ballot(boundary)) <= kCoherent;
+}
+
+// counter[key] += 1 for every lane with key >= 0.
+__device__ inline void agg_count(uint32_t *counter, int key) {
+    if (wave_keys_coherent(key)) {
+        uint64_t active = __ballot(key >= 0);
+        const int lane = threadIdx.x & (kWave - 1);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int k = __shfl(key, leader, kWave);
+            const uint64_t same = __ballot(key == k) & active;
+            if (lane == leader) atomicAdd(counter + k, (uint32_t)__popcll(same));
+            active &= ~same;
+        }
+    } else if (key >= 0) {
+        atomicAdd(counter + key, 1u);
+    }
+}
+
+// slot = counter[key]++ for every lane with key >= 0 (distinct slots per
+// lane; lanes with the same key get consecutive slots in lane order).
+__device__ inline int32_t agg_slot(int32_t *counter, int key) {
+    if (wave_keys_coherent(key)) {
+        uint64_t active = __ballot(key >= 0);
+        const int lane = threadIdx.x & (kWave - 1);
+        int my_leader = lane, my_rank = 0, group = 0;
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int k = __shfl(key, leader, kWave);
+            const uint64_t same = __ballot(key == k) & active;
+            if (key == k) {
+                my_leader = leader;
+                my_rank = __popcll(same & lanemask_lt());
+            }
+            if (lane == leader) group = __popcll(same);
+            active &= ~same;
+        }
+        int32_t base = 0;
+        if (group) base = atomicAdd(counter + key, group);   // leaders, all at once
+        base = __shfl(base, my_leader, kWave);
+        return base + my_rank;
+    }
+    return key >= 0 ? atomicAdd(counter + key, 1) : 0;
+}
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, kWave));
+    return v;
 }
 
 // Host launchers (defined in the .hip files).

@@ -80,10 +80,10 @@ def vertex(x, y, z, mvp, W, H) -> _Vtx:
     o.valid = all(abs(v) < big for v in c) and c[3] > 0
     if not o.valid:
         return o
-    xn = round_f32(c[0] / c[3])
-    yn = round_f32(c[1] / c[3])
-    zn = round_f32(c[2] / c[3])
     iw = round_f32(F(1) / c[3])
+    xn = round_f32(c[0] * iw)
+    yn = round_f32(c[1] * iw)
+    zn = round_f32(c[2] * iw)
     xs = round_f32(round_f32(xn + 1) * round_f32(F(W, 2)))
     ys = round_f32(round_f32(yn + 1) * round_f32(F(H, 2)))
     if not (abs(zn) < big and abs(iw) < big and abs(xs) < 16384 and abs(ys) < 16384):

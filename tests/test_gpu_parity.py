@@ -78,11 +78,12 @@ def test_metamorphic_bins_schedules_threads():
     o = oracle.render(sc)
     ref = None
     for B in (8, 16, 32, 64):
-        for sched in ("load_balance", "direct_map", "dynamic"):
+        for sched, groups in (("load_balance", 0), ("direct_map", 7), ("direct_map", 40),
+                              ("dynamic", 7), ("dynamic", 0)):
             for tpb in (64, 128, 256):
-                _note(f"metamorphic B={B} {sched} tpb={tpb}")
+                _note(f"metamorphic B={B} {sched} groups={groups} tpb={tpb}")
                 g = gpu_render(sc, bin_size=B, schedule=sched, threads_per_bin=tpb,
-                               persistent_groups=7 if sched != "load_balance" else 0)
+                               persistent_groups=groups)
                 if ref is None:
                     compare(sc, g, o)
                     ref = g
