@@ -26,13 +26,15 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 WORKLOADS = {
     "grid1080": dict(desc="1920x1080 displaced grid, 1024x512 quads (1,048,576 triangles, "
                           "shared vertices), perspective camera, Gouraud, 16x16 bins",
-                     bin=16),
+                     bin=16, schedule="direct_map", tpb=128, bary=False),
     "micro8m": dict(desc="1920x1080, 8,388,608 independent micropolygons (log-normal area "
                          "around 0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
-                    bin=16),
+                    bin=16, schedule="direct_map", tpb=128, bary=False),
     "batch256": dict(desc="256 scenes at 256x256, log-uniform 1K-200K random triangles each "
-                          "(edge ~ log-normal around 4 px), one batched launch", bin=16),
-    "tiny64": dict(desc="64x64, 256 random triangles, Gouraud, 8x8 bins", bin=8),
+                          "(edge ~ log-normal around 4 px), one batched launch",
+                     bin=16, schedule="direct_map", tpb=128, bary=False),
+    "tiny64": dict(desc="64x64, 256 random triangles, Gouraud, 8x8 bins", bin=8,
+                   schedule="direct_map", tpb=64, bary=False),
 }
 
 
@@ -96,9 +98,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid1080", choices=sorted(WORKLOADS))
     ap.add_argument("--bin", type=int, default=0)
-    ap.add_argument("--schedule", default="load_balance")
-    ap.add_argument("--tpb", type=int, default=0)
-    ap.add_argument("--no-bary", action="store_true")
+    ap.add_argument("--schedule", default="")
+    ap.add_argument("--tpb", type=int, default=-1)
+    ap.add_argument("--bary", action="store_true", help="also save barycentrics")
+    ap.add_argument("--fuse-resolve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
@@ -126,11 +129,15 @@ def main():
     wl = WORKLOADS[args.workload]
     sc = make_scene(args.workload)
     B = args.bin or wl["bin"]
+    sched = args.schedule or wl["schedule"]
+    tpb = wl["tpb"] if args.tpb < 0 else args.tpb
+    bary = args.bary or wl["bary"]
     sc.bin_size = B
-    cfg = pk.RenderConfig(bin_size=B, schedule=args.schedule, threads_per_bin=args.tpb,
-                          count_frags=True, want_bary=not args.no_bary)
-    print(f"bench: {args.workload} B={B} {args.schedule} steps={args.steps} "
-          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    cfg = pk.RenderConfig(bin_size=B, schedule=sched, threads_per_bin=tpb, count_frags=True,
+                          want_bary=bary, fuse_resolve=args.fuse_resolve)
+    print(f"bench: {args.workload} B={B} {sched} tpb={tpb} bary={bary} "
+          f"fused={args.fuse_resolve} steps={args.steps} warmup={args.warmup}",
+          file=sys.stderr, flush=True)
     r = pk.Renderer(sc, cfg)
     r.render()                       # sizes the bin-pair capacity once
     torch.cuda.synchronize()
@@ -172,7 +179,7 @@ def main():
     mtris = tris / (ms * 1e-3) / 1e6
     gfrags = frags / (ms * 1e-3) / 1e9
 
-    alg = raster_algorithmic_bytes(sc, npairs, covered, not args.no_bary)
+    alg = raster_algorithmic_bytes(sc, npairs, covered, bary)
     achieved = alg / (stage["raster_shade"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_raster", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -184,7 +191,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "bin_size": B,
-                   "schedule": args.schedule, "triangles": tris,
+                   "schedule": sched, "threads_per_bin": tpb, "fused_resolve": args.fuse_resolve,
+                   "saved_bary": bary, "triangles": tris,
                    "resolution": f"{sc.width}x{sc.height}", "scenes": S},
         "gfrags_per_s": round(gfrags, 3), "fragments_per_frame": frags,
         "bin_pairs_per_frame": npairs, "stage_ms": {k: round(v, 4) for k, v in stage.items()},

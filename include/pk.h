@@ -99,8 +99,12 @@ typedef enum {
 } pk_shading;
 
 enum {
-    PK_FLAG_COUNT_FRAGS = 1 /* add the number of covered samples (before the
-                               depth test) to *targets.frag_count */
+    PK_FLAG_COUNT_FRAGS = 1,  /* add the number of covered samples (before the
+                                 depth test) to *targets.frag_count */
+    PK_FLAG_FUSE_RESOLVE = 2  /* resolve and shade inside the per-bin kernel
+                                 (Rasterizer and Fragment Shader fused, Sec. 7.2)
+                                 instead of in a separate per-pixel pass over the
+                                 bins' winning keys; the image is the same */
 };
 
 typedef struct {               /* [host] */
@@ -152,7 +156,8 @@ typedef struct {                 /* [host] struct of device pointers; outputs [S
 /* Size in bytes of the workspace that pk_setup / pk_assign_bin /
  * pk_raster_shade share for one frame: per-triangle setup records and
  * bounding boxes (num_tris triangles, times S when instanced), per-bin
- * counters and offsets, and room for pair_capacity (bin, triangle) pairs.
+ * counters and offsets, one 64-bit key per output pixel, and room for
+ * pair_capacity (bin, triangle) pairs.
  * Returns 0 for invalid parameters.  Host-only; no HIP call. */
 size_t pk_workspace_bytes(const pk_params *p, int32_t num_tris, int64_t pair_capacity);
 

@@ -23,44 +23,91 @@
 
 namespace pk {
 
-constexpr int kDynBatch = 4;   // bins taken per pop of a DYNAMIC queue
-
 struct RasterArgs {
     Geom G;
     Ws w;
     Shade sh;
     int32_t schedule;
+    int32_t dyn_batch;      // bins taken per pop of a DYNAMIC queue
 };
 
-// Per-pixel resolve: unpack the winning key, recompute barycentrics at the
-// pixel centre, shade and write every requested target.
-__device__ inline void resolve_pixel(const RasterArgs &a, int32_t s, int64_t item_base,
+// Resolve of one pixel in three phases so that the loads of several pixels
+// can be in flight together: (1) unpack the winning key and load the
+// winner's setup record and vertex numbers, (2) load the vertex attributes
+// the shading needs, (3) recompute the barycentrics at the pixel centre,
+// shade, and write every requested target.
+struct Resolve {
+    uint32_t t;         // winner (scene-local), or ~0u for an empty pixel
+    float depth;
+    uint4 xy;           // X0 Y0 X1 Y1 of the winner's setup record
+    uint2 xy2;          // X2 Y2
+    float iw[3];
+    double sinv;
+    int32_t v[3];       // vertex numbers
+    float c[3][3];      // vertex colours [vertex][channel]
+    float ex[3][3];     // uv (2 channels) or normal (3 channels) [vertex][channel]
+};
+
+template <int SHADE>
+__device__ inline void resolve_fetch(const RasterArgs &a, int32_t s, int64_t item_base,
                                      int64_t vbase_scene, int px, int py,
-                                     unsigned long long key) {
+                                     unsigned long long key, Resolve &r) {
     const Geom &G = a.G;
+    r.t = key == kEmptyKey ? ~0u : (uint32_t)(key & 0xffffffffu);
+    r.depth = __uint_as_float((uint32_t)(key >> 32));
+    if (r.t == ~0u) return;
+    const TriRec *rp = a.w.rec + (item_base + r.t);
+    r.xy = *reinterpret_cast<const uint4 *>(&rp->X0);
+    r.xy2 = *reinterpret_cast<const uint2 *>(&rp->X2);
+    r.iw[0] = rp->iw0; r.iw[1] = rp->iw1; r.iw[2] = rp->iw2;
+    r.sinv = rp->sinv;
+    const int64_t g = G.instanced ? (int64_t)r.t : item_base + r.t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        r.v[k] = (int32_t)(vbase_scene + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)r.t + k));
+}
+
+template <int SHADE>
+__device__ inline void resolve_attribs(const RasterArgs &a, Resolve &r) {
+    if (r.t == ~0u) return;
     const Shade &sh = a.sh;
-    const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
-    if (key == kEmptyKey) {
+    const int64_t V = a.G.V;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) r.c[k][ch] = sh.color[ch * V + r.v[k]];
+        if (SHADE == PK_SHADE_TEXTURED) {
+            r.ex[k][0] = sh.uv[r.v[k]];
+            r.ex[k][1] = sh.uv[V + r.v[k]];
+        }
+        if (SHADE == PK_SHADE_DEFERRED) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) r.ex[k][ch] = sh.normal[ch * V + r.v[k]];
+        }
+    }
+}
+
+template <int SHADE>
+__device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, int py,
+                                      const Resolve &r) {
+    const Shade &sh = a.sh;
+    const int64_t p = ((int64_t)s * a.G.H + py) * a.G.W + px;
+    if (r.t == ~0u) {
         if (sh.out_color) reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(0, 0, 0, 0);
         if (sh.out_depth) sh.out_depth[p] = 1.0f;
         if (sh.out_primid) sh.out_primid[p] = -1;
         if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(0, 0);
-        if (sh.gbuf_n) { sh.gbuf_n[3 * p] = 0; sh.gbuf_n[3 * p + 1] = 0; sh.gbuf_n[3 * p + 2] = 0; }
-        if (sh.gbuf_a) { sh.gbuf_a[3 * p] = 0; sh.gbuf_a[3 * p + 1] = 0; sh.gbuf_a[3 * p + 2] = 0; }
+        if (SHADE == PK_SHADE_DEFERRED) {
+            sh.gbuf_n[3 * p] = 0; sh.gbuf_n[3 * p + 1] = 0; sh.gbuf_n[3 * p + 2] = 0;
+            sh.gbuf_a[3 * p] = 0; sh.gbuf_a[3 * p + 1] = 0; sh.gbuf_a[3 * p + 2] = 0;
+        }
         return;
     }
-    const int32_t t = (int32_t)(key & 0xffffffffu);
-    const float depth = __uint_as_float((uint32_t)(key >> 32));
-    const TriRec *rp = a.w.rec + (item_base + t);
-    const uint4 q0 = reinterpret_cast<const uint4 *>(rp)[0];
-    const uint4 q1 = reinterpret_cast<const uint4 *>(rp)[1];
-    const uint4 q2 = reinterpret_cast<const uint4 *>(rp)[2];
-    const uint4 q3 = reinterpret_cast<const uint4 *>(rp)[3];
-    const int32_t X0 = (int32_t)q0.x, Y0 = (int32_t)q0.y, X1 = (int32_t)q0.z, Y1 = (int32_t)q0.w;
-    const int32_t X2 = (int32_t)q1.x, Y2 = (int32_t)q1.y;
-    const float iw0 = __uint_as_float(q2.y), iw1 = __uint_as_float(q2.z),
-                iw2 = __uint_as_float(q2.w);
-    const double sinv = __hiloint2double((int)q3.w, (int)q3.z);
+    const int32_t X0 = (int32_t)r.xy.x, Y0 = (int32_t)r.xy.y, X1 = (int32_t)r.xy.z,
+                  Y1 = (int32_t)r.xy.w;
+    const int32_t X2 = (int32_t)r.xy2.x, Y2 = (int32_t)r.xy2.y;
+    const float iw0 = r.iw[0], iw1 = r.iw[1], iw2 = r.iw[2];
+    const double sinv = r.sinv;
     const int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
     const int64_t E0 = (int64_t)(X2 - X1) * (Py - Y1) - (int64_t)(Y2 - Y1) * (Px - X1);
     const int64_t E1 = (int64_t)(X0 - X2) * (Py - Y2) - (int64_t)(Y0 - Y2) * (Px - X2);
@@ -72,29 +119,21 @@ __device__ inline void resolve_pixel(const RasterArgs &a, int32_t s, int64_t ite
     const float Q = (qq0 + qq1) + qq2;
     const float b1 = qq1 / Q, b2 = qq2 / Q;
     const float b0 = (1.0f - b1) - b2;
-    // vertices of the winner
-    const int64_t g = item_base + t - (G.instanced ? item_base : 0);
-    int64_t v[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        v[k] = vbase_scene + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)t + k);
-    const int64_t V = G.V;
     float rgb[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float *pl = sh.color + c * V;
-        float acc = b0 * pl[v[0]];
-        acc = acc + b1 * pl[v[1]];
-        acc = acc + b2 * pl[v[2]];
-        rgb[c] = acc;
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = b0 * r.c[0][ch];
+        acc = acc + b1 * r.c[1][ch];
+        acc = acc + b2 * r.c[2][ch];
+        rgb[ch] = acc;
     }
-    if (sh.shading == PK_SHADE_TEXTURED) {
-        float u = b0 * sh.uv[v[0]];
-        u = u + b1 * sh.uv[v[1]];
-        u = u + b2 * sh.uv[v[2]];
-        float vv = b0 * sh.uv[V + v[0]];
-        vv = vv + b1 * sh.uv[V + v[1]];
-        vv = vv + b2 * sh.uv[V + v[2]];
+    if (SHADE == PK_SHADE_TEXTURED) {
+        float u = b0 * r.ex[0][0];
+        u = u + b1 * r.ex[1][0];
+        u = u + b2 * r.ex[2][0];
+        float vv = b0 * r.ex[0][1];
+        vv = vv + b1 * r.ex[1][1];
+        vv = vv + b2 * r.ex[2][1];
         const float su = u * (float)sh.tex_w - 0.5f, sv = vv * (float)sh.tex_h - 0.5f;
         const float fi = floorf(su), fj = floorf(sv);
         const float fs = su - fi, ft = sv - fj;
@@ -109,23 +148,22 @@ __device__ inline void resolve_pixel(const RasterArgs &a, int32_t s, int64_t ite
         const float *t01 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i0);
         const float *t11 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i1);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float tc = w00 * t00[c];
-            tc = tc + w10 * t10[c];
-            tc = tc + w01 * t01[c];
-            tc = tc + w11 * t11[c];
-            rgb[c] = rgb[c] * tc;
+        for (int ch = 0; ch < 3; ++ch) {
+            float tc = w00 * t00[ch];
+            tc = tc + w10 * t10[ch];
+            tc = tc + w01 * t01[ch];
+            tc = tc + w11 * t11[ch];
+            rgb[ch] = rgb[ch] * tc;
         }
     }
-    if (sh.shading == PK_SHADE_DEFERRED) {
+    if (SHADE == PK_SHADE_DEFERRED) {
         float n[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float *pl = sh.normal + c * V;
-            float acc = b0 * pl[v[0]];
-            acc = acc + b1 * pl[v[1]];
-            acc = acc + b2 * pl[v[2]];
-            n[c] = acc;
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = b0 * r.ex[0][ch];
+            acc = acc + b1 * r.ex[1][ch];
+            acc = acc + b2 * r.ex[2][ch];
+            n[ch] = acc;
         }
         float nn = n[0] * n[0];
         nn = nn + n[1] * n[1];
@@ -140,31 +178,109 @@ __device__ inline void resolve_pixel(const RasterArgs &a, int32_t s, int64_t ite
     } else if (sh.out_color) {
         reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
     }
-    if (sh.out_depth) sh.out_depth[p] = depth;
-    if (sh.out_primid) sh.out_primid[p] = t;
+    if (sh.out_depth) sh.out_depth[p] = r.depth;
+    if (sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
     if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(b1, b2);
 }
 
-template <int TPB, int B>
-__global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
+// One staged triangle of a bin, in registers: edge functions normalised so
+// that a sample is covered iff all three are > 0 (the top-left ownership bit
+// is folded into the constant), clipped candidate rectangle, depth inputs.
+// Edge values are integers below 2^48 held in float64: every product, sum and
+// step below stays an integer below 2^53, so the float64 arithmetic is exact
+// and equals the integer definition bit for bit (and feeds the float64
+// barycentrics without conversions).
+struct EdgeTri {
+    int32_t A[3], Bc[3];   // e_k(P) = A_k Px + B_k Py + C_k   (P in 1/256 px)
+    double C[3];
+    float z[3];
+    double inv;            // 1 / |A2|
+    int32_t x0, y0, wdt, cnt, own, prim;
+};
+
+__device__ inline void load_tri(const Ws &w, int32_t item, int64_t item_base, int32_t px0,
+                                int32_t py0, int32_t pw, int32_t ph, EdgeTri &t) {
+    const TriRec *rp = w.rec + item;
+    const uint4 q0 = reinterpret_cast<const uint4 *>(rp)[0];
+    const uint4 q1 = reinterpret_cast<const uint4 *>(rp)[1];
+    const uint4 q2 = reinterpret_cast<const uint4 *>(rp)[2];
+    const uint4 q3 = reinterpret_cast<const uint4 *>(rp)[3];
+    const int32_t X[3] = {(int32_t)q0.x, (int32_t)q0.z, (int32_t)q1.x};
+    const int32_t Y[3] = {(int32_t)q0.y, (int32_t)q0.w, (int32_t)q1.y};
+    const double sinv = __hiloint2double((int)q3.w, (int)q3.z);
+    const int sgn = sinv > 0.0 ? 1 : -1;
+    t.own = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int ka = (k + 1) % 3, kb = (k + 2) % 3;   // edge v_ka -> v_kb, opposite v_k
+        const int32_t dx = X[kb] - X[ka], dy = Y[kb] - Y[ka];
+        const int32_t Ak = -sgn * dy, Bk = sgn * dx;
+        const int own = (Ak > 0) || (Ak == 0 && Bk < 0);
+        t.own |= own << k;
+        t.A[k] = Ak;
+        t.Bc[k] = Bk;
+        t.C[k] = (double)(-((int64_t)Ak * X[ka] + (int64_t)Bk * Y[ka]) + own);
+    }
+    t.z[0] = __uint_as_float(q1.z);
+    t.z[1] = __uint_as_float(q1.w);
+    t.z[2] = __uint_as_float(q2.x);
+    t.inv = sinv > 0.0 ? sinv : -sinv;
+    const uint64_t bb = ((uint64_t)q3.y << 32) | q3.x;
+    t.x0 = max((int32_t)bb_x0(bb), px0);
+    t.y0 = max((int32_t)bb_y0(bb), py0);
+    const int32_t x1 = min((int32_t)bb_x1(bb), px0 + pw - 1);
+    const int32_t y1 = min((int32_t)bb_y1(bb), py0 + ph - 1);
+    t.wdt = x1 - t.x0 + 1;
+    const int32_t hgt = y1 - t.y0 + 1;
+    t.cnt = (t.wdt > 0 && hgt > 0) ? t.wdt * hgt : 0;
+    t.prim = (int32_t)(item - item_base);
+}
+
+// Depth of a covered sample from its biased edge values: the float64
+// barycentric form, then the (depth, primitive) key.  Returns false when the
+// fragment is outside [0, 1).
+__device__ inline bool depth_key(double e0, double e1, double e2, int own, double inv,
+                                 float z0, float z1, float z2, uint32_t prim,
+                                 unsigned long long &key) {
+    const double be0 = (e0 - (double)(own & 1)) * inv;
+    const double be1 = (e1 - (double)((own >> 1) & 1)) * inv;
+    const double be2 = (e2 - (double)((own >> 2) & 1)) * inv;
+    double zd = be0 * (double)z0;
+    zd = zd + be1 * (double)z1;
+    zd = zd + be2 * (double)z2;
+    float z = (float)zd;
+    z = z + 0.0f;
+    key = ((unsigned long long)__float_as_uint(z) << 32) | prim;
+    return 0.0f <= z && z < 1.0f;
+}
+
+// SHADE value of a bin kernel that ends by storing its tile of winning keys
+// for the per-pixel resolve kernel instead of resolving in place
+constexpr int kKeysOnly = -1;
+
+// word planes of the per-wave staging area (C and inv as float64 hi/lo words)
+enum : int {
+    kStA = 0, kStB = 3, kStClo = 6, kStChi = 9, kStZ = 12, kStInvLo = 15, kStInvHi = 16,
+    kStOrg = 17, kStWid = 18, kStMag = 19, kStPrim = 20, kStStart = 21, kStFields = 22
+};
+
+template <int TPB, int B, int SHADE>
+__global__ __launch_bounds__(TPB)
+__attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(RasterArgs a) {
     constexpr int NPIX = B * B;
+    constexpr int NW = TPB / kWave;
+    constexpr int kLoopMax = 12;   // wave-max candidates for the per-lane loop
     __shared__ unsigned long long s_key[NPIX];
-    // staged chunk of triangles (SoA to keep LDS accesses conflict-free)
-    __shared__ int32_t s_A[3][TPB], s_B[3][TPB];
-    __shared__ int64_t s_C[3][TPB];
-    __shared__ float s_z[3][TPB];
-    __shared__ double s_inv[TPB];
-    __shared__ int32_t s_org[TPB];    // x0 | y0 << 16 (absolute pixels)
-    __shared__ int32_t s_wid[TPB];    // width | owned mask << 8
-    __shared__ uint32_t s_mag[TPB];   // ceil(2^32 / width), 0 for width 1
-    __shared__ int32_t s_prim[TPB];   // scene-local triangle index
-    __shared__ int32_t s_start[TPB];  // exclusive prefix sum of candidate counts
-    __shared__ int32_t s_wave[TPB / kWave];
+    // per-wave staging for the expansion mode (large triangles): one word
+    // plane per field so every field sits at a constant offset from the
+    // wave's base and the lane's slot
+    __shared__ uint32_t s_st[NW][kStFields][kWave];
     __shared__ int64_t s_bin, s_bin_end;
-    __shared__ unsigned long long s_frag[TPB / kWave];
+    __shared__ unsigned long long s_frag[NW];
 
     const Geom &G = a.G;
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
     unsigned long long frags = 0;
     // Bins are split into kXcd contiguous ranges; workgroup w works in range
     // w mod kXcd (workgroups are dealt to the dies round-robin), so each die's
@@ -185,15 +301,15 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
         int64_t bin;
         if (a.schedule == PK_SCHED_DYNAMIC) {
             if (batch_beg >= batch_end) {
-                // take kDynBatch bins from this die's queue; when it is empty,
-                // move on to the other dies' queues
+                // take a batch of bins from this die's queue; when it is
+                // empty, move on to the other dies' queues
                 if (tid == 0) {
                     int64_t b0 = 0, b1 = 0;
                     while (q_tried < kXcd) {
                         const int64_t qb = qx * q + min<int64_t>(qx, rem);
                         const int64_t ql = q + (qx < rem ? 1 : 0);
-                        const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)kDynBatch);
-                        if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + kDynBatch, ql); break; }
+                        const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)a.dyn_batch);
+                        if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + a.dyn_batch, ql); break; }
                         qx = (qx + 1) % kXcd;
                         ++q_tried;
                     }
@@ -201,8 +317,8 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
                     s_bin_end = b1;
                 }
                 __syncthreads();
-                batch_beg = s_bin;
-                batch_end = s_bin_end;
+                batch_beg = __builtin_amdgcn_readfirstlane((int)s_bin);
+                batch_end = __builtin_amdgcn_readfirstlane((int)s_bin_end);
                 __syncthreads();
                 if (batch_beg >= batch_end) break;
             }
@@ -235,97 +351,162 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
         const int32_t lend = overflow ? 0 : a.w.bin_off[bin + 1];
         __syncthreads();
 
-        for (int32_t c0 = lbeg; c0 < lend; c0 += TPB) {
-            const int32_t nv = min(TPB, lend - c0);
-            int cnt = 0;
-            if (tid < nv) {
-                const int32_t item = a.w.pairs[c0 + tid];
-                const TriRec *rp = a.w.rec + item;
-                const uint4 q0 = reinterpret_cast<const uint4 *>(rp)[0];
-                const uint4 q1 = reinterpret_cast<const uint4 *>(rp)[1];
-                const uint4 q2 = reinterpret_cast<const uint4 *>(rp)[2];
-                const uint4 q3 = reinterpret_cast<const uint4 *>(rp)[3];
-                const int32_t X[3] = {(int32_t)q0.x, (int32_t)q0.z, (int32_t)q1.x};
-                const int32_t Y[3] = {(int32_t)q0.y, (int32_t)q0.w, (int32_t)q1.y};
-                const uint64_t bb = ((uint64_t)q3.y << 32) | q3.x;
-                const double sinv = __hiloint2double((int)q3.w, (int)q3.z);
-                const int sgn = sinv > 0.0 ? 1 : -1;
-                int owned = 0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int ka = (k + 1) % 3, kb = (k + 2) % 3;   // edge v_ka -> v_kb
-                    const int32_t dx = X[kb] - X[ka], dy = Y[kb] - Y[ka];
-                    const int32_t Ak = -sgn * dy, Bk = sgn * dx;
-                    const int own = (Ak > 0) || (Ak == 0 && Bk < 0);
-                    owned |= own << k;
-                    s_A[k][tid] = Ak;
-                    s_B[k][tid] = Bk;
-                    s_C[k][tid] = -((int64_t)Ak * X[ka] + (int64_t)Bk * Y[ka]) + own;
-                }
-                s_z[0][tid] = __uint_as_float(q1.z);
-                s_z[1][tid] = __uint_as_float(q1.w);
-                s_z[2][tid] = __uint_as_float(q2.x);
-                s_inv[tid] = sinv > 0.0 ? sinv : -sinv;
-                const int32_t x0 = max((int32_t)bb_x0(bb), px0), x1 = min((int32_t)bb_x1(bb), px0 + pw - 1);
-                const int32_t y0 = max((int32_t)bb_y0(bb), py0), y1 = min((int32_t)bb_y1(bb), py0 + ph - 1);
-                const int32_t wdt = x1 - x0 + 1, hgt = y1 - y0 + 1;
-                cnt = (wdt > 0 && hgt > 0) ? wdt * hgt : 0;
-                s_org[tid] = x0 | (y0 << 16);
-                s_wid[tid] = max(wdt, 1) | (owned << 8);
-                // ceil(2^32 / width) makes umulhi an exact divide for the
-                // candidate counts of one bin (< 2^12); width 1 needs no divide
-                s_mag[tid] = wdt > 1 ? 0xffffffffu / (uint32_t)wdt + 1u : 0u;
-                s_prim[tid] = (int32_t)(item - item_base);
-            }
-            int total;
-            const int start = block_exclusive_scan<TPB>(cnt, s_wave, total);
-            s_start[tid] = start;
-            __syncthreads();
-            for (int j = tid; j < total; j += TPB) {
-                int lo = 0, hi = nv - 1;     // last staged triangle with start <= j
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_start[mid] <= j) lo = mid; else hi = mid - 1;
-                }
-                const uint32_t local = (uint32_t)(j - s_start[lo]);
-                const int32_t wi = s_wid[lo];
-                const uint32_t wdt = (uint32_t)(wi & 0xff);
-                const uint32_t mag = s_mag[lo];
-                const uint32_t row = mag ? __umulhi(local, mag) : local;
-                const uint32_t col = local - row * wdt;
-                const int32_t org = s_org[lo];
-                const int32_t px = (org & 0xffff) + (int32_t)col;
-                const int32_t py = (org >> 16) + (int32_t)row;
-                const int32_t Px = 256 * px + 128, Py = 256 * py + 128;
-                const int64_t e0 = (int64_t)s_A[0][lo] * Px + (int64_t)s_B[0][lo] * Py + s_C[0][lo];
-                const int64_t e1 = (int64_t)s_A[1][lo] * Px + (int64_t)s_B[1][lo] * Py + s_C[1][lo];
-                const int64_t e2 = (int64_t)s_A[2][lo] * Px + (int64_t)s_B[2][lo] * Py + s_C[2][lo];
-                if (e0 > 0 && e1 > 0 && e2 > 0) {
-                    ++frags;
-                    const int own = wi >> 8;
-                    const double inv = s_inv[lo];
-                    const double be0 = (double)(e0 - (own & 1)) * inv;
-                    const double be1 = (double)(e1 - ((own >> 1) & 1)) * inv;
-                    const double be2 = (double)(e2 - ((own >> 2) & 1)) * inv;
-                    double zd = be0 * (double)s_z[0][lo];
-                    zd = zd + be1 * (double)s_z[1][lo];
-                    zd = zd + be2 * (double)s_z[2][lo];
-                    float z = (float)zd;
-                    z = z + 0.0f;
-                    if (0.0f <= z && z < 1.0f) {
-                        const unsigned long long key =
-                            ((unsigned long long)__float_as_uint(z) << 32) | (uint32_t)s_prim[lo];
-                        atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
+        // Process: every wave takes chunks of 64 triangles of the bin list
+#pragma unroll 1
+        for (int32_t c0 = lbeg + wv * kWave; c0 < lend; c0 += TPB) {
+            EdgeTri t;
+            t.cnt = 0;
+            if (c0 + lane < lend)
+                load_tri(a.w, a.w.pairs[c0 + lane], item_base, px0, py0, pw, ph, t);
+            const int mx = wave_max(t.cnt);
+            if (mx <= kLoopMax) {
+                // small triangles: each lane walks its own candidates with
+                // incrementally stepped edge functions
+                double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+                int col = 0, px = t.x0, py = t.y0;
+                const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
+                e0 = (double)t.A[0] * Px + (double)t.Bc[0] * Py + t.C[0];
+                e1 = (double)t.A[1] * Px + (double)t.Bc[1] * Py + t.C[1];
+                e2 = (double)t.A[2] * Px + (double)t.Bc[2] * Py + t.C[2];
+                const double sx0 = (double)(256 * t.A[0]), sx1 = (double)(256 * t.A[1]),
+                             sx2 = (double)(256 * t.A[2]);
+                // to the next row start: +256 B, minus the (width-1) x steps taken
+                const double back = (double)(256 * (t.wdt - 1));
+                const double sy0 = (double)(256 * t.Bc[0]) - back * (double)t.A[0];
+                const double sy1 = (double)(256 * t.Bc[1]) - back * (double)t.A[1];
+                const double sy2 = (double)(256 * t.Bc[2]) - back * (double)t.A[2];
+#pragma unroll 1
+                for (int j = 0; j < mx; ++j) {
+                    if (j < t.cnt) {
+                        if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
+                            ++frags;
+                            unsigned long long key;
+                            if (depth_key(e0, e1, e2, t.own, t.inv, t.z[0], t.z[1], t.z[2],
+                                          (uint32_t)t.prim, key))
+                                atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
+                        }
+                        if (++col < t.wdt) {
+                            e0 += sx0; e1 += sx1; e2 += sx2;
+                            ++px;
+                        } else {
+                            col = 0;
+                            px = t.x0;
+                            ++py;
+                            e0 += sy0; e1 += sy1; e2 += sy2;
+                        }
                     }
                 }
+            } else {
+                // large triangles: lay the wave's candidates end to end and
+                // give each lane every 64th; find the triangle by binary search
+                int total = t.cnt;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const int y = __shfl_up(total, d, kWave);
+                    if (lane >= d) total += y;
+                }
+                const int start = total - t.cnt;
+                total = __shfl(total, kWave - 1, kWave);
+                uint32_t (*st)[kWave] = s_st[wv];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    st[kStA + k][lane] = (uint32_t)t.A[k];
+                    st[kStB + k][lane] = (uint32_t)t.Bc[k];
+                    st[kStClo + k][lane] = (uint32_t)__double2loint(t.C[k]);
+                    st[kStChi + k][lane] = (uint32_t)__double2hiint(t.C[k]);
+                    st[kStZ + k][lane] = __float_as_uint(t.z[k]);
+                }
+                st[kStInvLo][lane] = (uint32_t)__double2loint(t.inv);
+                st[kStInvHi][lane] = (uint32_t)__double2hiint(t.inv);
+                st[kStOrg][lane] = (uint32_t)(t.x0 | (t.y0 << 16));
+                st[kStWid][lane] = (uint32_t)(max(t.wdt, 1) | (t.own << 8));
+                // ceil(2^32 / width) makes umulhi an exact divide for the
+                // candidate counts of one bin (< 2^12); width 1 needs no divide
+                st[kStMag][lane] = t.wdt > 1 ? 0xffffffffu / (uint32_t)t.wdt + 1u : 0u;
+                st[kStPrim][lane] = (uint32_t)t.prim;
+                st[kStStart][lane] = (uint32_t)start;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int nv = min(kWave, lend - c0);
+#pragma unroll 1
+                for (int j = lane; j < total; j += kWave) {
+                    int lo = 0, hi = nv - 1;   // last staged triangle with start <= j
+#pragma unroll 1
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if ((int)st[kStStart][mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    const uint32_t local = (uint32_t)(j - (int)st[kStStart][lo]);
+                    const int32_t wi = (int32_t)st[kStWid][lo];
+                    const uint32_t wdt = (uint32_t)(wi & 0xff);
+                    const uint32_t mag = st[kStMag][lo];
+                    const uint32_t row = mag ? __umulhi(local, mag) : local;
+                    const uint32_t col = local - row * wdt;
+                    const int32_t org = (int32_t)st[kStOrg][lo];
+                    const int32_t px = (org & 0xffff) + (int32_t)col;
+                    const int32_t py = (org >> 16) + (int32_t)row;
+                    const double Px = (double)(256 * px + 128), Py = (double)(256 * py + 128);
+                    double e[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double Ck = __hiloint2double((int)st[kStChi + k][lo], (int)st[kStClo + k][lo]);
+                        e[k] = (double)(int32_t)st[kStA + k][lo] * Px +
+                               (double)(int32_t)st[kStB + k][lo] * Py + Ck;
+                    }
+                    if (e[0] > 0.0 && e[1] > 0.0 && e[2] > 0.0) {
+                        ++frags;
+                        unsigned long long key;
+                        const double inv = __hiloint2double((int)st[kStInvHi][lo], (int)st[kStInvLo][lo]);
+                        if (depth_key(e[0], e[1], e[2], wi >> 8, inv, __uint_as_float(st[kStZ][lo]),
+                                      __uint_as_float(st[kStZ + 1][lo]), __uint_as_float(st[kStZ + 2][lo]),
+                                      st[kStPrim][lo], key))
+                            atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
+                    }
+                }
+                // the staging slots are rewritten by this wave's next chunk
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __syncthreads();
         }
-        // EndBin: every fragment of this bin has been tested; resolve
-        for (int i = tid; i < NPIX; i += TPB) {
-            const int lx = i % B, ly = i / B;
-            if (lx < pw && ly < ph)
-                resolve_pixel(a, s, item_base, vbase, px0 + lx, py0 + ly, s_key[i]);
+        __syncthreads();
+        // EndBin: every fragment of this bin has been tested
+        if (SHADE == kKeysOnly) {
+            // hand the tile's winning keys to the per-pixel resolve kernel
+            unsigned long long *keys = a.w.keys + (int64_t)s * G.W * G.H;
+#pragma unroll 1
+            for (int i = tid; i < NPIX; i += TPB) {
+                const int lx = i % B, ly = i / B;
+                if (lx < pw && ly < ph)
+                    keys[(int64_t)(py0 + ly) * G.W + px0 + lx] = s_key[i];
+            }
+        } else {
+            // resolve in place, two pixels per thread at a time so their
+            // gathers overlap
+            constexpr int PPT = NPIX / TPB >= 2 ? 2 : 1;
+#pragma unroll 1
+            for (int i0 = tid; i0 < NPIX; i0 += PPT * TPB) {
+                Resolve rs[PPT];
+                int lx[PPT], ly[PPT];
+                bool on[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int i = i0 + k * TPB;
+                    lx[k] = i % B;
+                    ly[k] = i / B;
+                    on[k] = i < NPIX && lx[k] < pw && ly[k] < ph;
+                    if (on[k])
+                        resolve_fetch<SHADE>(a, s, item_base, vbase, px0 + lx[k], py0 + ly[k],
+                                             s_key[i], rs[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (on[k]) resolve_attribs<SHADE>(a, rs[k]);
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (on[k]) resolve_finish<SHADE>(a, s, px0 + lx[k], py0 + ly[k], rs[k]);
+            }
         }
         __syncthreads();
     }
@@ -334,16 +515,16 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
         unsigned long long f = frags;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) f += __shfl_down(f, d, kWave);
-        if ((tid & (kWave - 1)) == 0) s_frag[tid / kWave] = f;
+        if (lane == 0) s_frag[wv] = f;
         __syncthreads();
         if (tid == 0) {
             unsigned long long tot = 0;
-            for (int i = 0; i < TPB / kWave; ++i) tot += s_frag[i];
+            for (int i = 0; i < NW; ++i) tot += s_frag[i];
             if (tot) atomicAdd(a.sh.frag_count, tot);
         }
     }
     if (a.schedule == PK_SCHED_DYNAMIC && tid == 0) {
-        // the last workgroup out rewinds the queue for the next launch
+        // the last workgroup out rewinds the queues for the next launch
         __threadfence();
         const uint32_t done = atomicAdd(&a.w.misc[2], 1u);
         if (done == gridDim.x - 1) {
@@ -353,30 +534,81 @@ __global__ __launch_bounds__(TPB) void k_raster(RasterArgs a) {
     }
 }
 
-template <int TPB>
+// Resolve of every pixel of every scene from the key buffer: one thread per
+// pixel, so the record and attribute gathers of many pixels are in flight.
+template <int SHADE>
+__global__ __launch_bounds__(256) void k_resolve(RasterArgs a) {
+    const Geom &G = a.G;
+    const int64_t npix_scene = (int64_t)G.W * G.H;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= npix_scene * G.S) return;
+    const int32_t s = (int32_t)(p / npix_scene);
+    const int64_t ps = p - (int64_t)s * npix_scene;
+    const int py = (int)(ps / G.W), px = (int)(ps - (int64_t)py * G.W);
+    const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
+    const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
+    Resolve r;
+    resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, a.w.keys[p], r);
+    resolve_attribs<SHADE>(a, r);
+    resolve_finish<SHADE>(a, s, px, py, r);
+}
+
+template <int TPB, int SHADE>
 static hipError_t launch_tpb(const RasterArgs &a, dim3 grid, hipStream_t st) {
     switch (a.G.B) {
-    case 8:  hipLaunchKernelGGL((k_raster<TPB, 8>), grid, dim3(TPB), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_raster<TPB, 16>), grid, dim3(TPB), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_raster<TPB, 32>), grid, dim3(TPB), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_raster<TPB, 64>), grid, dim3(TPB), 0, st, a); break;
+    case 8:  hipLaunchKernelGGL((k_raster<TPB, 8, SHADE>), grid, dim3(TPB), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_raster<TPB, 16, SHADE>), grid, dim3(TPB), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_raster<TPB, 32, SHADE>), grid, dim3(TPB), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_raster<TPB, 64, SHADE>), grid, dim3(TPB), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int SHADE>
+static hipError_t launch_shade(const RasterArgs &a, int tpb, dim3 grid, hipStream_t st) {
+    switch (tpb) {
+    case 64:  return launch_tpb<64, SHADE>(a, grid, st);
+    case 128: return launch_tpb<128, SHADE>(a, grid, st);
+    case 256: return launch_tpb<256, SHADE>(a, grid, st);
+    default:  return hipErrorInvalidValue;
+    }
+}
+
+template <int SHADE>
+static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
+    const int64_t npix = (int64_t)a.G.S * a.G.W * a.G.H;
+    hipLaunchKernelGGL((k_resolve<SHADE>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st,
+                       a);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
-                         int groups, hipStream_t st) {
+                         int groups, bool fused, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
-    RasterArgs a{G, w, sh, schedule};
+    // DYNAMIC pops are device-scope atomics on eight counters; take enough
+    // bins per pop that each workgroup pops about four times
+    int64_t per = G.nbins_total / ((int64_t)groups * 4);
+    const int32_t dyn_batch = (int32_t)(per < 1 ? 1 : (per > 64 ? 64 : per));
+    RasterArgs a{G, w, sh, schedule, dyn_batch};
     int64_t nblk = G.nbins_total;
     if (schedule != PK_SCHED_LOAD_BALANCE) nblk = groups < G.nbins_total ? groups : G.nbins_total;
     const dim3 grid((unsigned)nblk);
-    switch (tpb) {
-    case 64:  return launch_tpb<64>(a, grid, st);
-    case 128: return launch_tpb<128>(a, grid, st);
-    case 256: return launch_tpb<256>(a, grid, st);
-    default:  return hipErrorInvalidValue;
+    if (!fused) {
+        const hipError_t e = launch_shade<kKeysOnly>(a, tpb, grid, st);
+        if (e != hipSuccess) return e;
+        switch (sh.shading) {
+        case PK_SHADE_GOURAUD:  return launch_resolve<PK_SHADE_GOURAUD>(a, st);
+        case PK_SHADE_TEXTURED: return launch_resolve<PK_SHADE_TEXTURED>(a, st);
+        case PK_SHADE_DEFERRED: return launch_resolve<PK_SHADE_DEFERRED>(a, st);
+        default:                return hipErrorInvalidValue;
+        }
+    }
+    switch (sh.shading) {
+    case PK_SHADE_GOURAUD:  return launch_shade<PK_SHADE_GOURAUD>(a, tpb, grid, st);
+    case PK_SHADE_TEXTURED: return launch_shade<PK_SHADE_TEXTURED>(a, tpb, grid, st);
+    case PK_SHADE_DEFERRED: return launch_shade<PK_SHADE_DEFERRED>(a, tpb, grid, st);
+    default:                return hipErrorInvalidValue;
     }
 }
 

@@ -18,6 +18,7 @@ int ilog2(int b) { int l = 0; while ((1 << l) < b) ++l; return l; }
 // Host-side view of the parameters that every entry point shares.
 struct Frame {
     int64_t items = 0;
+    int64_t npix = 0;      // S * W * H
     int64_t nbins_scene = 0;
     int64_t nbins_total = 0;
     int nbx = 0, nby = 0;
@@ -36,7 +37,7 @@ pk_status check_params(const pk_params *p, Frame &f) {
         return PK_ERR_INVALID_ARGUMENT;
     if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_DEFERRED)
         return PK_ERR_INVALID_ARGUMENT;
-    if (p->flags & ~PK_FLAG_COUNT_FRAGS) return PK_ERR_INVALID_ARGUMENT;
+    if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE)) return PK_ERR_INVALID_ARGUMENT;
     if (p->num_scenes < 1) return PK_ERR_INVALID_ARGUMENT;
     if (p->instanced != 0 && p->instanced != 1) return PK_ERR_INVALID_ARGUMENT;
     if (p->persistent_groups < 0) return PK_ERR_INVALID_ARGUMENT;
@@ -45,8 +46,8 @@ pk_status check_params(const pk_params *p, Frame &f) {
     f.nbins_scene = (int64_t)f.nbx * f.nby;
     f.nbins_total = f.nbins_scene * p->num_scenes;
     if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
-    if ((int64_t)p->num_scenes * p->width * p->height > (int64_t)1 << 40)
-        return PK_ERR_INVALID_ARGUMENT;
+    f.npix = (int64_t)p->num_scenes * p->width * p->height;
+    if (f.npix > (int64_t)1 << 40) return PK_ERR_INVALID_ARGUMENT;
     return PK_OK;
 }
 
@@ -62,7 +63,7 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
 }
 
 struct Layout {
-    size_t rec, bbox, bin_count, bin_off, cursor, misc, pairs, total;
+    size_t rec, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
@@ -75,6 +76,7 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * 64);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
+    L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix);
     L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
     L.total = o;
     return L;
@@ -91,6 +93,7 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
     w.bin_off = reinterpret_cast<int32_t *>(b + L.bin_off);
     w.cursor = reinterpret_cast<int32_t *>(b + L.cursor);
+    w.keys = reinterpret_cast<unsigned long long *>(b + L.keys);
     w.misc = reinterpret_cast<uint32_t *>(b + L.misc);
     w.pairs = reinterpret_cast<int32_t *>(b + L.pairs);
     w.pair_capacity = pair_capacity;
@@ -198,7 +201,8 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     // the pair list is the last slice, so its address does not depend on the
     // capacity; the lists are read through bin_off only
     const Ws w = carve(ws, f, 0);
-    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups, (hipStream_t)stream);
+    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups,
+                                 (p->flags & PK_FLAG_FUSE_RESOLVE) != 0, (hipStream_t)stream);
     if (e == hipSuccess && p->shading == PK_SHADE_DEFERRED)
         e = launch_deferred(G, sh, (hipStream_t)stream);
     return hip_status(e);

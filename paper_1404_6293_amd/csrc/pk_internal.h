@@ -51,6 +51,7 @@ struct Ws {
     int32_t *cursor;           // [nbins_total]
     uint32_t *misc;            // [64], right after bin_count: 1 pair overflow flag,
                                // 2 workgroups done (DYNAMIC), 8..15 queue heads
+    unsigned long long *keys;  // [S][H][W] winning (depth, primitive) keys
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
 };
@@ -239,7 +240,7 @@ hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st);
 hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
 hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st);
 hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
-                         int groups, hipStream_t st);
+                         int groups, bool fused, hipStream_t st);
 hipError_t launch_deferred(const Geom &G, const Shade &sh, hipStream_t st);
 hipError_t launch_backward(const Geom &G, const Shade &sh, const int32_t *primid,
                            const float *bary, const float *grad, float *grad_vcolor,

@@ -23,6 +23,7 @@ PK_OK, PK_ERR_INVALID_ARGUMENT, PK_ERR_CAPACITY, PK_ERR_HIP, PK_ERR_UNSUPPORTED 
 PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC = range(3)
 PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED = range(3)
 PK_FLAG_COUNT_FRAGS = 1
+PK_FLAG_FUSE_RESOLVE = 2
 
 SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIRECT_MAP,
              "dynamic": PK_SCHED_DYNAMIC}
@@ -162,6 +163,7 @@ class RenderConfig:
     persistent_groups: int = 0
     count_frags: bool = False
     want_bary: bool = True
+    fuse_resolve: bool = False
 
 
 class Renderer:
@@ -211,7 +213,8 @@ class Renderer:
 
         self.params = Params(self.W, self.H, int(cfg.bin_size), SCHEDULES[cfg.schedule],
                              int(cfg.threads_per_bin), self.shading,
-                             PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0, self.S, int(inst),
+                             (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
+                             | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0), self.S, int(inst),
                              int(cfg.persistent_groups))
         self.mesh = Mesh(_ptr(self.pos), int(sc.pos.shape[1]), _ptr(self.idx), int(sc.num_tris),
                          _ptr(self.mvp), _ptr(self.tri_off), _ptr(self.vtx_off))

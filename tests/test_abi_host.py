@@ -60,7 +60,7 @@ def _mesh(**kw):
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
     dict(bin_size=-8), dict(schedule=3), dict(schedule=-1), dict(threads_per_bin=32),
-    dict(threads_per_bin=512), dict(shading=3), dict(flags=2), dict(num_scenes=0),
+    dict(threads_per_bin=512), dict(shading=3), dict(flags=4), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
     p = _params(**bad)
@@ -113,12 +113,14 @@ def test_workspace_bytes_arithmetic(L):
     assert b0 > 0 and b1 - b0 == 256 and b2 - b1 == 256
     nbins = 7 * 5
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    expect = al(64 * T) + al(8 * T) + al(4 * nbins) + al(4 * (nbins + 1)) + al(4 * nbins) + al(256)
+    expect = (al(64 * T) + al(8 * T) + al(4 * nbins) + al(4 * (nbins + 1)) + al(4 * nbins)
+              + al(256) + al(8 * 100 * 70))
     assert b0 == expect
     # instanced views multiply the per-triangle slices
     pi = _params(width=100, height=70, bin_size=16, num_scenes=3, instanced=1)
     nb3 = 3 * nbins
-    expect3 = al(64 * 3 * T) + al(8 * 3 * T) + al(4 * nb3) + al(4 * (nb3 + 1)) + al(4 * nb3) + al(256)
+    expect3 = (al(64 * 3 * T) + al(8 * 3 * T) + al(4 * nb3) + al(4 * (nb3 + 1)) + al(4 * nb3)
+               + al(256) + al(8 * 3 * 100 * 70))
     assert L.pk_workspace_bytes(C.byref(pi), T, 0) == expect3
     assert L.pk_workspace_bytes(C.byref(p), -1, 0) == 0
     assert L.pk_workspace_bytes(C.byref(p), T, -5) == 0

@@ -81,9 +81,10 @@ def test_metamorphic_bins_schedules_threads():
         for sched, groups in (("load_balance", 0), ("direct_map", 7), ("direct_map", 40),
                               ("dynamic", 7), ("dynamic", 0)):
             for tpb in (64, 128, 256):
-                _note(f"metamorphic B={B} {sched} groups={groups} tpb={tpb}")
+                fused = (tpb == 128)
+                _note(f"metamorphic B={B} {sched} groups={groups} tpb={tpb} fused={fused}")
                 g = gpu_render(sc, bin_size=B, schedule=sched, threads_per_bin=tpb,
-                               persistent_groups=groups)
+                               persistent_groups=groups, fuse_resolve=fused)
                 if ref is None:
                     compare(sc, g, o)
                     ref = g
@@ -125,10 +126,11 @@ def test_grid1080_full_frame():
     compare(sc, g, o)
 
 
-def test_deferred_micropolygons_small():
-    _note("micro small deferred")
+@pytest.mark.parametrize("fused", [False, True])
+def test_deferred_micropolygons_small(fused):
+    _note(f"micro small deferred fused={fused}")
     sc = scenes.micro(seed=11, width=256, height=128, num_tris=60000, num_lights=3)
-    g = gpu_render(sc, bin_size=16)
+    g = gpu_render(sc, bin_size=16, fuse_resolve=fused)
     o = oracle.render(sc)
     compare(sc, g, o)
     np.testing.assert_allclose(g["gbuf_normal"], o["gbuf_normal"], rtol=RTOL, atol=ATOL)
@@ -142,10 +144,11 @@ def test_deferred_tie_heavy():
     compare(sc, gpu_render(sc, bin_size=32, schedule="dynamic"), oracle.render(sc))
 
 
-def test_textured_views():
-    _note("textured instanced views")
+@pytest.mark.parametrize("fused", [False, True])
+def test_textured_views(fused):
+    _note(f"textured instanced views fused={fused}")
     sc = scenes.diffgrid(size=96, num_views=3, nx=32, ny=16, tex_size=16)
-    g = gpu_render(sc, bin_size=16)
+    g = gpu_render(sc, bin_size=16, fuse_resolve=fused)
     compare(sc, g, oracle.render(sc))
 
 
