@@ -91,6 +91,87 @@ def cpu_baseline(sc, budget_s: float = 12.0):
                       f"single-threaded, {dt:.1f} s"}
 
 
+def _median_ms(torch, fn, reps):
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_batched(reps: int = 10) -> dict:
+    """256 scenes at 256x256 (log-uniform 1K-200K triangles each): one batched
+    frame replayed from a captured HIP graph, against the same 256 scenes
+    rendered as 256 sequential plain frames with the same configuration."""
+    import torch
+    from paper_1404_6293_amd import pk, scenes
+    sc = scenes.batch()
+    cfg = pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
+                          count_frags=True, want_bary=False)
+    rb = pk.Renderer(sc, cfg)
+    rb.capture()
+    torch.cuda.synchronize()
+    frags = int(rb.frag_count.item())
+    ms_b = _median_ms(torch, rb.replay, reps)
+    assert not rb.ensure_capacity()
+    plain = [pk.Renderer(scenes.split_batch(sc, s), cfg) for s in range(sc.num_scenes)]
+    for r in plain:
+        r.render()
+    torch.cuda.synchronize()
+
+    def seq():
+        for r in plain:
+            r.frame()
+    ms_p = _median_ms(torch, seq, max(3, reps // 3))
+    tris = int(sc.num_tris)
+    return {"workload": "batch256: 256 scenes at 256x256, log-uniform 1K-200K random triangles "
+                        "each (edge ~ log-normal around 4 px), 16x16 bins, direct_map",
+            "triangles": tris, "fragments": frags,
+            "batched_graph_ms": round(ms_b, 4), "sequential_plain_ms": round(ms_p, 4),
+            "speedup": round(ms_p / ms_b, 3),
+            "batched_mtris_per_s": round(tris / ms_b / 1e3, 1),
+            "batched_gfrags_per_s": round(frags / ms_b / 1e6, 3)}
+
+
+def bench_backward(reps: int = 10) -> dict:
+    """64 views at 512x512 of the 1024x512-quad grid, textured (512x512x3):
+    forward with saved barycentrics against the backward pass to vertex
+    colours and texels."""
+    import numpy as np
+    import torch
+    from paper_1404_6293_amd import pk, scenes
+    sc = scenes.diffgrid()
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
+                                        count_frags=True, want_bary=True))
+    r.render()
+    torch.cuda.synchronize()
+    covered = int((r.out_primid >= 0).sum().item())
+    ms_f = _median_ms(torch, r.frame, reps)
+    g = torch.from_numpy(np.random.default_rng(0).standard_normal(
+        (sc.num_scenes, sc.height, sc.width, 4)).astype(np.float32)).cuda()
+    gv = torch.zeros((3, sc.pos.shape[1]), dtype=torch.float32, device="cuda")
+    gt = torch.zeros(sc.texture.shape, dtype=torch.float32, device="cuda")
+
+    def bwd():
+        gv.zero_()
+        gt.zero_()
+        r.backward(g, gv, gt)
+    ms_b = _median_ms(torch, bwd, reps)
+    atomics = covered * 21
+    return {"workload": "diff64: 64 views at 512x512 of a 1024x512-quad grid (1,048,576 "
+                        "triangles), per-vertex RGB modulated by a bilinear 512x512x3 texture",
+            "covered_pixels": covered, "forward_ms": round(ms_f, 4),
+            "backward_ms": round(ms_b, 4), "backward_over_forward": round(ms_b / ms_f, 3),
+            "fp32_atomics": atomics,
+            "atomic_rate_g_per_s": round(atomics / ms_b / 1e6, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +184,8 @@ def main():
     ap.add_argument("--bary", action="store_true", help="also save barycentrics")
     ap.add_argument("--fuse-resolve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and backward comparisons")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -198,6 +281,11 @@ def main():
         "bin_pairs_per_frame": npairs, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
     }
+    if not args.no_extras and args.workload == "grid1080":
+        print("bench: batched vs plain", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched()
+        print("bench: backward vs forward", file=sys.stderr, flush=True)
+        out["backward"] = bench_backward()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(sc)
         cb["host"] = platform.processor() or platform.machine()

@@ -28,28 +28,50 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_setup(Geom G, Ws w) {
-    const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    // lanes past the end stay in the wave (culled) so that the per-bin
-    // counting below runs with the whole wave
-    const bool in_range = item < G.items;
+// A setup/scatter workgroup covers kGroupItems consecutive triangles.  When
+// the scenes those triangles belong to have at most kHist bins in total, the
+// per-bin counts are first accumulated in LDS and flushed with one global
+// atomic per touched bin (and the scatter reserves one contiguous slot range
+// per touched bin); otherwise lanes fall back to wave-aggregated global
+// atomics.  Device-scope atomics are slow on this part, LDS atomics are not.
+constexpr int kGroupThreads = 256;
+constexpr int kItemsPerThread = 4;
+constexpr int kGroupItems = kGroupThreads * kItemsPerThread;
+constexpr int kHist = 8192;
+
+__device__ inline int32_t scene_of(const Geom &G, int64_t item) {
+    if (G.S == 1) return 0;
+    if (G.instanced) return (int32_t)(item / G.T);
+    return item_ref(G, item).s;
+}
+
+// Scene window [s_lo, ...] of this workgroup's items; nwin = bins in it.
+__device__ inline bool group_window(const Geom &G, int64_t first, int32_t &s_lo, int64_t &nwin) {
+    const int64_t last = min(first + kGroupItems, G.items) - 1;
+    s_lo = scene_of(G, first);
+    const int32_t s_hi = scene_of(G, last);
+    nwin = (int64_t)(s_hi - s_lo + 1) * G.nbins_scene;
+    return nwin <= kHist;
+}
+
+// Setup of one triangle: transform, snap, cull, record.  Returns the packed
+// pixel bbox (kEmptyKey when culled) and the triangle's scene.
+__device__ inline uint64_t setup_one(const Geom &G, const Ws &w, int64_t item, int32_t &s) {
+    s = 0;
+    if (item >= G.items) return kEmptyKey;
     int32_t X[3] = {0, 0, 0}, Y[3] = {0, 0, 0};
     float z[3] = {0, 0, 0}, iw[3] = {0, 0, 0};
-    bool ok = in_range;
-    int32_t s = 0;
-    if (in_range) {
-        const ItemRef r = item_ref(G, item);
-        s = r.s;
-        const float *m = G.mvp ? G.mvp + 16 * (int64_t)r.s : nullptr;
+    const ItemRef r = item_ref(G, item);
+    s = r.s;
+    const float *m = G.mvp ? G.mvp + 16 * (int64_t)r.s : nullptr;
+    bool ok = true;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int64_t v = vertex_of(G, r, k);
-            if (v < 0 || v >= G.V) { ok = false; continue; }
-            ok = vertex_stage(G, v, m, X[k], Y[k], z[k], iw[k]) && ok;
-        }
+    for (int k = 0; k < 3; ++k) {
+        const int64_t v = vertex_of(G, r, k);
+        if (v < 0 || v >= G.V) { ok = false; continue; }
+        ok = vertex_stage(G, v, m, X[k], Y[k], z[k], iw[k]) && ok;
     }
     uint64_t bb = kEmptyKey;
-    int32_t x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (ok) {
         const int64_t A2 = (int64_t)(X[1] - X[0]) * (Y[2] - Y[0]) -
                            (int64_t)(X[2] - X[0]) * (Y[1] - Y[0]);
@@ -57,8 +79,8 @@ __global__ __launch_bounds__(256) void k_setup(Geom G, Ws w) {
             const int32_t mnx = min(X[0], min(X[1], X[2])), mxx = max(X[0], max(X[1], X[2]));
             const int32_t mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
             // pixel p is sampled at 256 p + 128 (arithmetic shifts floor)
-            x0 = max((mnx + 127) >> 8, 0); x1 = min((mxx - 128) >> 8, G.W - 1);
-            y0 = max((mny + 127) >> 8, 0); y1 = min((mxy - 128) >> 8, G.H - 1);
+            const int32_t x0 = max((mnx + 127) >> 8, 0), x1 = min((mxx - 128) >> 8, G.W - 1);
+            const int32_t y0 = max((mny + 127) >> 8, 0), y1 = min((mxy - 128) >> 8, G.H - 1);
             if (x0 <= x1 && y0 <= y1) {
                 bb = (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) |
                      ((uint64_t)y1 << 48);
@@ -77,20 +99,67 @@ __global__ __launch_bounds__(256) void k_setup(Geom G, Ws w) {
             }
         }
     }
-    if (in_range) w.bbox[item] = bb;
-    // AssignBin counts of the screen-space stage, one round per bin of the
-    // largest bin rectangle in the wave
-    const bool live = bb != kEmptyKey;
-    const int bx0 = x0 >> G.log2B, bx1 = x1 >> G.log2B;
-    const int by0 = y0 >> G.log2B;
-    const int nbx_t = bx1 - bx0 + 1;
-    const int nb = live ? nbx_t * ((y1 >> G.log2B) - by0 + 1) : 0;
-    const int rounds = wave_max(nb);
-    const int base = s * G.nbins_scene;
-    int cx = bx0, cy = by0;
-    for (int r = 0; r < rounds; ++r) {
-        agg_count(w.bin_count, r < nb ? base + cy * G.nbx + cx : -1);
-        if (++cx > bx1) { cx = bx0; ++cy; }
+    w.bbox[item] = bb;
+    return bb;
+}
+
+// Bin rectangle of a packed bbox: nb bins starting at (bx0, by0), nbx_t wide.
+struct BinRect {
+    int bx0, by0, nbx_t, nb;
+};
+
+__device__ inline BinRect bin_rect(const Geom &G, uint64_t bb) {
+    BinRect r;
+    if (bb == kEmptyKey) { r.bx0 = r.by0 = 0; r.nbx_t = 1; r.nb = 0; return r; }
+    r.bx0 = bb_x0(bb) >> G.log2B;
+    r.by0 = bb_y0(bb) >> G.log2B;
+    r.nbx_t = (bb_x1(bb) >> G.log2B) - r.bx0 + 1;
+    r.nb = r.nbx_t * ((bb_y1(bb) >> G.log2B) - r.by0 + 1);
+    return r;
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
+    __shared__ uint32_t s_hist[kHist];
+    const int tid = threadIdx.x;
+    const int64_t first = blockIdx.x * (int64_t)kGroupItems;
+    int32_t s_lo;
+    int64_t nwin;
+    const bool lds = group_window(G, first, s_lo, nwin);
+    if (lds) {
+        for (int i = tid; i < nwin; i += kGroupThreads) s_hist[i] = 0;
+        __syncthreads();
+    }
+#pragma unroll 1
+    for (int k = 0; k < kItemsPerThread; ++k) {
+        const int64_t item = first + k * kGroupThreads + tid;
+        int32_t s;
+        const uint64_t bb = setup_one(G, w, item, s);
+        const BinRect br = bin_rect(G, bb);
+        // AssignBin counts of the screen-space stage
+        if (lds) {
+            uint32_t *h = s_hist + (int64_t)(s - s_lo) * G.nbins_scene;
+            for (int i = 0; i < br.nb; ++i) {
+                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
+                atomicAdd(h + by * G.nbx + bx, 1u);
+            }
+        } else {
+            // one round per bin of the largest bin rectangle in the wave
+            const int rounds = wave_max(br.nb);
+            const int base = s * G.nbins_scene;
+            int cx = br.bx0, cy = br.by0;
+            for (int r = 0; r < rounds; ++r) {
+                agg_count(w.bin_count, r < br.nb ? base + cy * G.nbx + cx : -1);
+                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
+            }
+        }
+    }
+    if (lds) {
+        __syncthreads();
+        uint32_t *dst = w.bin_count + (int64_t)s_lo * G.nbins_scene;
+        for (int i = tid; i < nwin; i += kGroupThreads) {
+            const uint32_t c = s_hist[i];
+            if (c) atomicAdd(dst + i, c);
+        }
     }
 }
 
@@ -99,8 +168,8 @@ hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st) {
     const int64_t words = (reinterpret_cast<char *>(w.misc) - reinterpret_cast<char *>(w.bin_count)) / 4 + 64;
     hipError_t e = launch_fill_u32(w.bin_count, words, 0u, st);
     if (e != hipSuccess || G.items == 0) return e;
-    const int64_t blocks = (G.items + 255) / 256;
-    hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(256), 0, st, G, w);
+    const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), 0, st, G, w);
     return hipGetLastError();
 }
 
@@ -175,31 +244,77 @@ hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStr
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_scatter(Geom G, Ws w) {
-    const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
+    __shared__ uint32_t s_hist[kHist];
     if (w.misc[1]) return;   // pair capacity exceeded: lists stay unwritten
-    const uint64_t bb = item < G.items ? w.bbox[item] : kEmptyKey;
-    const bool live = bb != kEmptyKey;
-    int32_t s = 0;
-    if (live && G.S > 1) s = G.instanced ? (int32_t)(item / G.T) : item_ref(G, item).s;
-    const int bx0 = bb_x0(bb) >> G.log2B, bx1 = bb_x1(bb) >> G.log2B;
-    const int by0 = bb_y0(bb) >> G.log2B, by1 = bb_y1(bb) >> G.log2B;
-    const int nb = live ? (bx1 - bx0 + 1) * (by1 - by0 + 1) : 0;
-    const int rounds = wave_max(nb);
-    const int base = s * G.nbins_scene;
-    int cx = bx0, cy = by0;
-    for (int r = 0; r < rounds; ++r) {
-        const int key = r < nb ? base + cy * G.nbx + cx : -1;
-        const int32_t slot = agg_slot(w.cursor, key);
-        if (key >= 0) w.pairs[slot] = (int32_t)item;
-        if (++cx > bx1) { cx = bx0; ++cy; }
+    const int tid = threadIdx.x;
+    const int64_t first = blockIdx.x * (int64_t)kGroupItems;
+    int32_t s_lo;
+    int64_t nwin;
+    const bool lds = group_window(G, first, s_lo, nwin);
+    uint64_t bb[kItemsPerThread];
+    int32_t sc[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+        const int64_t item = first + k * kGroupThreads + tid;
+        bb[k] = item < G.items ? w.bbox[item] : kEmptyKey;
+        sc[k] = bb[k] != kEmptyKey ? scene_of(G, item) : 0;
+    }
+    if (lds) {
+        for (int i = tid; i < nwin; i += kGroupThreads) s_hist[i] = 0;
+        __syncthreads();
+        // count this workgroup's pairs per bin
+#pragma unroll
+        for (int k = 0; k < kItemsPerThread; ++k) {
+            const BinRect br = bin_rect(G, bb[k]);
+            uint32_t *h = s_hist + (int64_t)(sc[k] - s_lo) * G.nbins_scene;
+            for (int i = 0; i < br.nb; ++i) {
+                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
+                atomicAdd(h + by * G.nbx + bx, 1u);
+            }
+        }
+        __syncthreads();
+        // reserve one contiguous range per touched bin
+        int32_t *cur = w.cursor + (int64_t)s_lo * G.nbins_scene;
+        for (int i = tid; i < nwin; i += kGroupThreads) {
+            const uint32_t c = s_hist[i];
+            if (c) s_hist[i] = (uint32_t)atomicAdd(cur + i, (int32_t)c);
+        }
+        __syncthreads();
+        // hand out the slots
+#pragma unroll
+        for (int k = 0; k < kItemsPerThread; ++k) {
+            const int64_t item = first + k * kGroupThreads + tid;
+            const BinRect br = bin_rect(G, bb[k]);
+            uint32_t *h = s_hist + (int64_t)(sc[k] - s_lo) * G.nbins_scene;
+            for (int i = 0; i < br.nb; ++i) {
+                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
+                const uint32_t slot = atomicAdd(h + by * G.nbx + bx, 1u);
+                w.pairs[slot] = (int32_t)item;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+        const int64_t item = first + k * kGroupThreads + tid;
+        const BinRect br = bin_rect(G, bb[k]);
+        const int rounds = wave_max(br.nb);
+        const int base = sc[k] * G.nbins_scene;
+        int cx = br.bx0, cy = br.by0;
+        for (int r = 0; r < rounds; ++r) {
+            const int key = r < br.nb ? base + cy * G.nbx + cx : -1;
+            const int32_t slot = agg_slot(w.cursor, key);
+            if (key >= 0) w.pairs[slot] = (int32_t)item;
+            if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
+        }
     }
 }
 
 hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st) {
     if (G.items == 0) return hipSuccess;
-    const int64_t blocks = (G.items + 255) / 256;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, G, w);
+    const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(kGroupThreads), 0, st, G, w);
     return hipGetLastError();
 }
 

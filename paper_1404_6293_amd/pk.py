@@ -158,7 +158,7 @@ def _stream() -> int:
 @dataclass
 class RenderConfig:
     bin_size: int = 16
-    schedule: str = "load_balance"
+    schedule: str = "direct_map"
     threads_per_bin: int = 0
     persistent_groups: int = 0
     count_frags: bool = False
@@ -166,64 +166,101 @@ class RenderConfig:
     fuse_resolve: bool = False
 
 
-class Renderer:
-    """Holds one scene (or batch) in device memory and renders it.
+def _light_default():
+    return np.array([[1.0, 1.0, 1.0]]) / np.sqrt(3.0)
+
+
+class DeviceScene:
+    """Inputs of one render call resident in device memory.
 
     ``scene`` is any object with the attributes of
-    ``paper_1404_6293_amd.scenes.Scene``; its arrays are copied to the GPU
-    once.  ``frame()`` enqueues setup, assign-bin and raster/shade on the
-    current stream without synchronizing; ``render()`` also makes sure the
-    bin-pair capacity sufficed (one device-to-host read) and retries if not.
+    ``paper_1404_6293_amd.scenes.Scene``.  NumPy arrays are copied to the
+    device once; torch tensors already on the device (e.g. vertex colours that
+    require grad) are used in place.
+    """
+
+    def __init__(self, scene, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        self.device = dev
+
+        def up(a, dtype):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor):
+                t = a.detach() if a.requires_grad else a
+                return t.to(device=dev, dtype=dtype).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(np.asarray(a), dtype=np.dtype(
+                {torch.float32: np.float32, torch.int32: np.int32}[dtype]))).to(dev)
+
+        sc = scene
+        f32, i32 = torch.float32, torch.int32
+        self.S = int(getattr(sc, "num_scenes", 1) or 1)
+        self.W, self.H = int(sc.width), int(sc.height)
+        self.instanced = bool(getattr(sc, "instanced", False)) and self.S > 1
+        self.pos = up(sc.pos, f32)
+        self.num_vertices = int(self.pos.shape[1])
+        self.num_tris = int(sc.num_tris)
+        self.idx = up(sc.idx, i32) if sc.idx is not None else None
+        self.mvp = up(sc.mvp, f32).reshape(-1, 16) if sc.mvp is not None else None
+        if self.mvp is not None and self.mvp.shape[0] != self.S:
+            raise ValueError(f"mvp has {self.mvp.shape[0]} matrices for {self.S} scenes")
+        batched = self.S > 1 and not self.instanced
+        self.tri_off = up(sc.scene_tri_off, i32) if batched else None
+        self.vtx_off = up(sc.scene_vtx_off, i32) if batched else None
+        self.color = up(sc.color, f32)
+        self.uv = up(getattr(sc, "uv", None), f32)
+        self.normal = up(getattr(sc, "normal", None), f32)
+        self.texture = up(getattr(sc, "texture", None), f32)
+        lights = getattr(sc, "lights", None)
+        if lights is None:
+            lights = _light_default()
+        self.lights = up(np.asarray(lights, np.float64).astype(np.float32).reshape(-1, 3), f32)
+        self.shading = SHADINGS[getattr(sc, "shading", "gouraud")]
+        self.items = self.num_tris * (self.S if self.instanced else 1)
+
+    def mesh(self) -> Mesh:
+        return Mesh(_ptr(self.pos), self.num_vertices, _ptr(self.idx), self.num_tris,
+                    _ptr(self.mvp), _ptr(self.tri_off), _ptr(self.vtx_off))
+
+    def attribs(self) -> Attribs:
+        tex = self.texture
+        return Attribs(_ptr(self.color), _ptr(self.uv), _ptr(self.normal), _ptr(tex),
+                       0 if tex is None else int(tex.shape[1]),
+                       0 if tex is None else int(tex.shape[0]), _ptr(self.lights),
+                       int(self.lights.shape[0]))
+
+
+class Renderer:
+    """Renders one scene (or batch of scenes / views) held in device memory.
+
+    ``frame()`` enqueues setup, assign-bin and raster/shade on the current
+    stream without synchronizing; ``render()`` also makes sure the bin-pair
+    capacity sufficed (one device-to-host read) and retries if not.
+    ``capture()`` records one frame into a HIP graph for ``replay()``.
     """
 
     def __init__(self, scene, cfg: RenderConfig = RenderConfig(), device: str = "cuda"):
         import torch
         lib()  # fail early and loudly when the library is missing
         self.torch = torch
-        self.scene = scene
         self.cfg = cfg
-        dev = torch.device(device)
-        self.device = dev
-
-        def up(a, dtype=None):
-            if a is None:
-                return None
-            a = np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype=dtype))
-            return torch.from_numpy(a).to(dev)
-
-        sc = scene
-        self.S = int(getattr(sc, "num_scenes", 1) or 1)
-        self.W, self.H = int(sc.width), int(sc.height)
-        self.pos = up(sc.pos, np.float32)
-        self.idx = up(sc.idx, np.int32) if sc.idx is not None else None
-        self.mvp = up(np.asarray(sc.mvp, np.float32).reshape(-1, 16)) if sc.mvp is not None else None
-        inst = bool(getattr(sc, "instanced", False)) and self.S > 1
-        self.tri_off = up(sc.scene_tri_off, np.int32) if (self.S > 1 and not inst) else None
-        self.vtx_off = up(sc.scene_vtx_off, np.int32) if (self.S > 1 and not inst) else None
-        self.color = up(sc.color, np.float32)
-        self.uv = up(getattr(sc, "uv", None), np.float32)
-        self.normal = up(getattr(sc, "normal", None), np.float32)
-        tex = getattr(sc, "texture", None)
-        self.texture = up(tex, np.float32)
-        lights = getattr(sc, "lights", None)
-        if lights is None:
-            lights = np.array([[1.0, 1.0, 1.0]]) / np.sqrt(3.0)
-        self.lights = up(np.asarray(lights, np.float64).astype(np.float32).reshape(-1, 3))
-        self.shading = SHADINGS[getattr(sc, "shading", "gouraud")]
-
+        self.dev = scene if isinstance(scene, DeviceScene) else DeviceScene(scene, device)
+        d = self.dev
+        self.device = d.device
+        self.S, self.W, self.H = d.S, d.W, d.H
+        self.shading = d.shading
         self.params = Params(self.W, self.H, int(cfg.bin_size), SCHEDULES[cfg.schedule],
                              int(cfg.threads_per_bin), self.shading,
                              (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
-                             | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0), self.S, int(inst),
-                             int(cfg.persistent_groups))
-        self.mesh = Mesh(_ptr(self.pos), int(sc.pos.shape[1]), _ptr(self.idx), int(sc.num_tris),
-                         _ptr(self.mvp), _ptr(self.tri_off), _ptr(self.vtx_off))
-        self.attribs = Attribs(_ptr(self.color), _ptr(self.uv), _ptr(self.normal),
-                               _ptr(self.texture), 0 if tex is None else int(tex.shape[1]),
-                               0 if tex is None else int(tex.shape[0]), _ptr(self.lights),
-                               int(self.lights.shape[0]))
+                             | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0), self.S,
+                             int(d.instanced), int(cfg.persistent_groups))
+        self.mesh = d.mesh()
+        self.attribs = d.attribs()
         S, H, W = self.S, self.H, self.W
         f32 = torch.float32
+        dev = self.device
         self.out_color = torch.empty((S, H, W, 4), dtype=f32, device=dev)
         self.out_depth = torch.empty((S, H, W), dtype=f32, device=dev)
         self.out_primid = torch.empty((S, H, W), dtype=torch.int32, device=dev)
@@ -236,16 +273,17 @@ class Renderer:
                                _ptr(self.out_bary), _ptr(self.gbuf_n), _ptr(self.gbuf_a),
                                _ptr(self.frag_count))
         self.pairs_needed = torch.zeros(1, dtype=torch.int64, device=dev)
-        items = int(sc.num_tris) * (S if inst else 1)
-        self.items = items
-        self._alloc_ws(max(4 * items, 1024))
+        self.items = d.items
+        self.graph = None
+        self._alloc_ws(max(4 * self.items, 1024))
 
     def _alloc_ws(self, capacity: int):
-        nbytes = pk_workspace_bytes(self.params, int(self.scene.num_tris), capacity)
+        nbytes = pk_workspace_bytes(self.params, self.dev.num_tris, capacity)
         if nbytes == 0:
             raise PkError("pk_workspace_bytes", PK_ERR_INVALID_ARGUMENT, "invalid parameters")
         self.capacity = capacity
         self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        self.graph = None   # a captured graph holds the old workspace address
 
     # stages, one call each
     def setup(self):
@@ -284,6 +322,30 @@ class Renderer:
                 raise PkError("render", PK_ERR_CAPACITY, "pair capacity still exceeded")
         return self.outputs()
 
+    def capture(self, warmup: int = 2):
+        """Record one frame into a HIP graph (after sizing the workspace with a
+        checked render).  Replays reuse this workspace and these outputs; a
+        replay whose bin pairs outgrow the capacity writes empty pixels, which
+        ``ensure_capacity`` detects afterwards (then capture again)."""
+        torch = self.torch
+        self.render()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self.frame()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.frame()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("no captured graph: call capture() first")
+        self.graph.replay()
+
     def outputs(self) -> dict:
         return dict(color=self.out_color, depth=self.out_depth, primid=self.out_primid,
                     bary=self.out_bary, gbuf_normal=self.gbuf_n, gbuf_albedo=self.gbuf_a,
@@ -293,7 +355,7 @@ class Renderer:
         """CSR bin lists of the last frame, copied to the host for checking:
         (offsets[nbins_total+1], triangle numbers) as NumPy arrays."""
         import torch
-        v = pk_bin_lists(self.params, int(self.scene.num_tris), self.ws.data_ptr())
+        v = pk_bin_lists(self.params, self.dev.num_tris, self.ws.data_ptr())
         base = self.ws.data_ptr()
         o0 = v.bin_offsets - base
         off = self.ws[o0:o0 + 4 * (v.num_bins + 1)].view(torch.int32).cpu().numpy().copy()
