@@ -114,7 +114,7 @@ typedef struct {               /* [host] */
     int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto */
     int32_t shading;           /* pk_shading */
     int32_t flags;             /* PK_FLAG_* */
-    int32_t num_scenes;        /* S >= 1 */
+    int32_t num_scenes;        /* S, 1..65535 */
     int32_t instanced;         /* S > 1 only: 1 = S views (one MVP each) of the same
                                   mesh; 0 = S concatenated scenes (scene_*_off) */
     int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC workgroup count; 0 = auto */

@@ -76,6 +76,30 @@ def _load():
     return _lib
 
 
+class using_library:
+    """Temporarily route every oracle call to another build of oracle.c
+    (the mutation tests compile planted mistakes into a scratch library)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _load()                      # make sure the real one is set up first
+        lib = C.CDLL(self.path)
+        for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_backward"):
+            src, dst = getattr(_lib, name), getattr(lib, name)
+            dst.restype, dst.argtypes = src.restype, src.argtypes
+        _lib = lib
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data
 

@@ -198,13 +198,21 @@ struct EdgeTri {
     int32_t x0, y0, wdt, cnt, own, prim;
 };
 
-__device__ inline void load_tri(const Ws &w, int32_t item, int64_t item_base, int32_t px0,
-                                int32_t py0, int32_t pw, int32_t ph, EdgeTri &t) {
+struct RawTri {
+    uint4 q0, q1, q2, q3;   // the 64-byte setup record
+};
+
+__device__ inline void fetch_tri(const Ws &w, int32_t item, RawTri &r) {
     const TriRec *rp = w.rec + item;
-    const uint4 q0 = reinterpret_cast<const uint4 *>(rp)[0];
-    const uint4 q1 = reinterpret_cast<const uint4 *>(rp)[1];
-    const uint4 q2 = reinterpret_cast<const uint4 *>(rp)[2];
-    const uint4 q3 = reinterpret_cast<const uint4 *>(rp)[3];
+    r.q0 = reinterpret_cast<const uint4 *>(rp)[0];
+    r.q1 = reinterpret_cast<const uint4 *>(rp)[1];
+    r.q2 = reinterpret_cast<const uint4 *>(rp)[2];
+    r.q3 = reinterpret_cast<const uint4 *>(rp)[3];
+}
+
+__device__ inline void decode_tri(const RawTri &r, int32_t item, int64_t item_base, int32_t px0,
+                                  int32_t py0, int32_t pw, int32_t ph, EdgeTri &t) {
+    const uint4 q0 = r.q0, q1 = r.q1, q2 = r.q2, q3 = r.q3;
     const int32_t X[3] = {(int32_t)q0.x, (int32_t)q0.z, (int32_t)q1.x};
     const int32_t Y[3] = {(int32_t)q0.y, (int32_t)q0.w, (int32_t)q1.y};
     const double sinv = __hiloint2double((int)q3.w, (int)q3.z);
@@ -282,6 +290,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave;
     unsigned long long frags = 0;
+    const bool overflow = a.w.misc[1] != 0;   // pair capacity exceeded: no lists
     // Bins are split into kXcd contiguous ranges; workgroup w works in range
     // w mod kXcd (workgroups are dealt to the dies round-robin), so each die's
     // L2 sees a compact screen region.  The mapping is a bijection whatever
@@ -293,11 +302,29 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const int64_t r_len = q + (xcd < rem ? 1 : 0);
     const int64_t lane_in_xcd = blockIdx.x / kXcd;
     const int64_t groups_in_xcd = (gridDim.x - xcd + kXcd - 1) / kXcd;
+    // DIRECT_MAP: the bin of iteration i is known in advance (-1: none)
+    auto dm_bin = [&](int64_t i) -> int64_t {
+        if (gridDim.x < kXcd) {            // too few groups to give every die a range
+            const int64_t b = blockIdx.x + i * (int64_t)gridDim.x;
+            return b < nb ? b : -1;
+        }
+        const int64_t l = lane_in_xcd + i * groups_in_xcd;
+        return l < r_len ? r_beg + l : -1;
+    };
+    // Software pipeline (DIRECT_MAP): while bin i is processed, the CSR
+    // offsets of bin i+2, the first pair numbers of bin i+1 and, once bin i's
+    // tests are done, their setup records are fetched, so each bin starts
+    // with its first chunk already in registers.
+    const bool piped = a.schedule == PK_SCHED_DIRECT_MAP;
+    int32_t nx_beg = 0, nx_end = 0;         // offsets of bin i+1
+    int32_t nx_item = -1;                   // bin i+1: this lane's first pair
+    RawTri pf;                              // current bin, first chunk: this lane's
+    int32_t pf_item = -1;                   //   setup record and pair number
+    bool pf_ok = false;
     // DYNAMIC: current queue (range) and the bins of the last batch taken
     int qx = xcd, q_tried = 0;
     int64_t batch_beg = 0, batch_end = 0;
-    int64_t iter = 0;
-    for (;;) {
+    for (int64_t it = 0;; ++it) {
         int64_t bin;
         if (a.schedule == PK_SCHED_DYNAMIC) {
             if (batch_beg >= batch_end) {
@@ -323,20 +350,13 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 if (batch_beg >= batch_end) break;
             }
             bin = batch_beg++;
-        } else if (a.schedule == PK_SCHED_DIRECT_MAP) {
-            if (gridDim.x < kXcd) {            // too few groups to give every die a range
-                bin = blockIdx.x + iter * (int64_t)gridDim.x;
-                if (bin >= nb) break;
-            } else {
-                const int64_t l = lane_in_xcd + iter * groups_in_xcd;
-                if (l >= r_len) break;
-                bin = r_beg + l;
-            }
+        } else if (piped) {
+            bin = dm_bin(it);
+            if (bin < 0) break;
         } else {
-            if (iter > 0 || lane_in_xcd >= r_len) break;
+            if (it > 0 || lane_in_xcd >= r_len) break;
             bin = r_beg + lane_in_xcd;
         }
-        ++iter;
         const int32_t s = (int32_t)(bin / G.nbins_scene);
         const int32_t lb = (int32_t)(bin - (int64_t)s * G.nbins_scene);
         const int32_t by = lb / G.nbx, bx = lb - by * G.nbx;
@@ -346,18 +366,49 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
 
         for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
-        const bool overflow = a.w.misc[1] != 0;
-        const int32_t lbeg = overflow ? 0 : a.w.bin_off[bin];
-        const int32_t lend = overflow ? 0 : a.w.bin_off[bin + 1];
+        int32_t lbeg = 0, lend = 0;
+        if (!overflow) {
+            if (piped && it > 0) {
+                lbeg = nx_beg;
+                lend = nx_end;
+            } else {
+                lbeg = a.w.bin_off[bin];
+                lend = a.w.bin_off[bin + 1];
+            }
+        }
+        // pipeline stage 1: the next bin's offsets (first use after this bin)
+        int64_t b_next = -1;
+        if (piped && !overflow) {
+            b_next = dm_bin(it + 1);
+            if (b_next >= 0) { nx_beg = a.w.bin_off[b_next]; nx_end = a.w.bin_off[b_next + 1]; }
+        }
         __syncthreads();
 
         // Process: every wave takes chunks of 64 triangles of the bin list
+        const int32_t first = lbeg + wv * kWave;
+        bool use_pf = pf_ok;
 #pragma unroll 1
-        for (int32_t c0 = lbeg + wv * kWave; c0 < lend; c0 += TPB) {
+        for (int32_t c0 = first; c0 < lend; c0 += TPB) {
             EdgeTri t;
             t.cnt = 0;
-            if (c0 + lane < lend)
-                load_tri(a.w, a.w.pairs[c0 + lane], item_base, px0, py0, pw, ph, t);
+            if (c0 + lane < lend) {
+                RawTri raw;
+                int32_t item;
+                if (use_pf) {
+                    raw = pf;
+                    item = pf_item;
+                } else {
+                    item = a.w.pairs[c0 + lane];
+                    fetch_tri(a.w, item, raw);
+                }
+                decode_tri(raw, item, item_base, px0, py0, pw, ph, t);
+            }
+            use_pf = false;
+            if (c0 == first && b_next >= 0) {
+                // pipeline stage 2: the next bin's first pair numbers
+                const int32_t j = nx_beg + wv * kWave + lane;
+                nx_item = j < nx_end ? a.w.pairs[j] : -1;
+            }
             const int mx = wave_max(t.cnt);
             if (mx <= kLoopMax) {
                 // small triangles: each lane walks its own candidates with
@@ -470,6 +521,18 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
+        // pipeline stage 3: setup records of the next bin's first chunk
+        pf_ok = false;
+        if (b_next >= 0) {
+            if (first >= lend) {
+                // this wave had no chunk in this bin: stage 2 still to do
+                const int32_t j = nx_beg + wv * kWave + lane;
+                nx_item = j < nx_end ? a.w.pairs[j] : -1;
+            }
+            if (nx_item >= 0) fetch_tri(a.w, nx_item, pf);
+            pf_item = nx_item;
+            pf_ok = true;
+        }
         __syncthreads();
         // EndBin: every fragment of this bin has been tested
         if (SHADE == kKeysOnly) {
@@ -535,18 +598,20 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
 }
 
 // Resolve of every pixel of every scene from the key buffer: one thread per
-// pixel, so the record and attribute gathers of many pixels are in flight.
+// pixel, 64 x 4 pixel tiles per workgroup, the scene on the grid's z axis
+// (no divisions to find a pixel's coordinates).
+constexpr int kResW = 64, kResH = 4;
+
 template <int SHADE>
-__global__ __launch_bounds__(256) void k_resolve(RasterArgs a) {
+__global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const Geom &G = a.G;
-    const int64_t npix_scene = (int64_t)G.W * G.H;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= npix_scene * G.S) return;
-    const int32_t s = (int32_t)(p / npix_scene);
-    const int64_t ps = p - (int64_t)s * npix_scene;
-    const int py = (int)(ps / G.W), px = (int)(ps - (int64_t)py * G.W);
+    const int px = blockIdx.x * kResW + threadIdx.x;
+    const int py = blockIdx.y * kResH + threadIdx.y;
+    const int32_t s = blockIdx.z;
+    if (px >= G.W || py >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
+    const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
     Resolve r;
     resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, a.w.keys[p], r);
     resolve_attribs<SHADE>(a, r);
@@ -577,9 +642,9 @@ static hipError_t launch_shade(const RasterArgs &a, int tpb, dim3 grid, hipStrea
 
 template <int SHADE>
 static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
-    const int64_t npix = (int64_t)a.G.S * a.G.W * a.G.H;
-    hipLaunchKernelGGL((k_resolve<SHADE>), dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st,
-                       a);
+    const dim3 grid((unsigned)((a.G.W + kResW - 1) / kResW), (unsigned)((a.G.H + kResH - 1) / kResH),
+                    (unsigned)a.G.S);
+    hipLaunchKernelGGL((k_resolve<SHADE>), grid, dim3(kResW, kResH), 0, st, a);
     return hipGetLastError();
 }
 

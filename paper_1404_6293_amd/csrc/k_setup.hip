@@ -41,7 +41,7 @@ constexpr int kHist = 8192;
 
 __device__ inline int32_t scene_of(const Geom &G, int64_t item) {
     if (G.S == 1) return 0;
-    if (G.instanced) return (int32_t)(item / G.T);
+    if (G.instanced) return (int32_t)((uint32_t)item / (uint32_t)G.T);   // items < 2^31
     return item_ref(G, item).s;
 }
 

@@ -38,7 +38,7 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_DEFERRED)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE)) return PK_ERR_INVALID_ARGUMENT;
-    if (p->num_scenes < 1) return PK_ERR_INVALID_ARGUMENT;
+    if (p->num_scenes < 1 || p->num_scenes > 65535) return PK_ERR_INVALID_ARGUMENT;
     if (p->instanced != 0 && p->instanced != 1) return PK_ERR_INVALID_ARGUMENT;
     if (p->persistent_groups < 0) return PK_ERR_INVALID_ARGUMENT;
     f.nbx = (p->width + p->bin_size - 1) / p->bin_size;

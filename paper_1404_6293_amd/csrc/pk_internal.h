@@ -78,7 +78,8 @@ __device__ inline ItemRef item_ref(const Geom &G, int64_t item) {
     if (G.S == 1) {
         r.s = 0; r.t = (int32_t)item; r.g = item; r.vbase = 0;
     } else if (G.instanced) {
-        r.s = (int32_t)(item / G.T);
+        // items < 2^31: a 32-bit divide instead of the 64-bit routine
+        r.s = (int32_t)((uint32_t)item / (uint32_t)G.T);
         r.t = (int32_t)(item - (int64_t)r.s * G.T);
         r.g = r.t; r.vbase = 0;
     } else {

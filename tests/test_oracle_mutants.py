@@ -1,0 +1,202 @@
+"""The oracle's pins must reject plausible mistakes.
+
+Each case plants one mistake in a scratch copy of oracle.c (on the CPU),
+compiles it, and runs a fast subset of the pins against it; at least one pin
+must fail.  The unmodified source must pass the same subset."""
+import os
+import subprocess
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import oracle
+from paper_1404_6293_amd import scenes
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "fill_rule_flipped": ("(r->s * dy < 0) || (dy == 0 && r->s * dx < 0)",
+                          "(r->s * dy > 0) || (dy == 0 && r->s * dx < 0)"),
+    "horizontal_edges_wrong": ("(dy == 0 && r->s * dx < 0)", "(dy == 0 && r->s * dx > 0)"),
+    # (key < zbuf versus key <= zbuf is an equivalent mutation: keys carry the
+    # triangle index, so two different fragments never have equal keys)
+    "later_equal_depth_wins": ("if (key < zbuf[p]) zbuf[p] = key;",
+                               "if ((key >> 32) <= (zbuf[p] >> 32) || zbuf[p] == ~0ull) zbuf[p] = key;"),
+    "bbox_off_by_one": ("floor_div256((int64_t)mnx - 128 + 255)", "floor_div256((int64_t)mnx - 128 + 256)"),
+    # (cutting the upper x bound the same way is an equivalent mutation: a
+    # sample exactly on the right-most vertex is never covered under this rule)
+    "bbox_top_cut": ("floor_div256((int64_t)mxy - 128)", "floor_div256((int64_t)mxy - 129)"),
+    "depth_index_swapped": ("zd = zd + beta[2] * (double)r->z[2];", "zd = zd + beta[2] * (double)r->z[1];"),
+    "no_perspective_division": ("const float q1 = bs1 * r->iw[1];", "const float q1 = bs1;"),
+    "snap_truncates": ("o.X = (int32_t)rintf(xs * 256.0f);", "o.X = (int32_t)(xs * 256.0f);"),
+    "y_down": ("const float ys = (yn + 1.0f) * (0.5f * (float)s->height);",
+               "const float ys = (1.0f - yn) * (0.5f * (float)s->height);"),
+    "texture_axes_swapped": ("const float fs = su - fi, ft = sv - fj;", "const float ft = su - fi, fs = sv - fj;"),
+    "texel_centre_shift": ("const float su = u * (float)s->tex_w - 0.5f;", "const float su = u * (float)s->tex_w;"),
+    "deferred_no_clamp": ("if (d < 0.0f) d = 0.0f;", ""),
+    "colour_weight_swapped": ("t = t + bp[1] * plane[vid[1]];", "t = t + bp[2] * plane[vid[1]];"),
+    "edge_sign": ("E[k] = dx * (Py - r->Y[a]) - dy * (Px - r->X[a]);",
+                  "E[k] = dx * (Py - r->Y[a]) + dy * (Px - r->X[a]);"),
+    "backward_weight": ("grad_vcolor[c * V + vid[k]] += (double)bp[k] * (double)G[c];",
+                        "grad_vcolor[c * V + vid[k]] += (double)bp[2 - k] * (double)G[c];"),
+}
+
+
+def _build(tmp_path, name, text):
+    src = tmp_path / f"{name}.c"
+    lib = tmp_path / f"lib{name}.so"
+    src.write_text(text)
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(lib), str(src), "-lm"])
+    return str(lib)
+
+
+def _ndc(W, H, X, Y, Z, idx=None, **kw):
+    X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    pos = np.stack([X / (128.0 * W) - 1.0, Y / (128.0 * H) - 1.0, np.asarray(Z, np.float64)]).astype(np.float32)
+    d = dict(width=W, height=H, pos=pos,
+             color=np.random.default_rng(0).uniform(0, 1, (3, pos.shape[1])).astype(np.float32),
+             idx=None if idx is None else np.asarray(idx, np.int32),
+             num_tris=pos.shape[1] // 3 if idx is None else len(idx), mvp=None, num_scenes=1,
+             scene_tri_off=None, scene_vtx_off=None, instanced=False, uv=None, normal=None,
+             texture=None, lights=None, shading="gouraud")
+    d.update(kw)
+    return SimpleNamespace(**d)
+
+
+def _pins_fail() -> list:
+    """Run the fast pin subset; return the names of the checks that failed."""
+    failed = []
+
+    def check(name, fn):
+        try:
+            if not fn():
+                failed.append(name)
+        except Exception:                       # a crash also counts as caught
+            failed.append(name)
+
+    def brute(seed):
+        sc = scenes.tiny(seed=seed, width=24, height=18, num_tris=8)
+        o = oracle.render(sc, want_cover=True)
+        b = bf.render(sc)
+        if not (o["cover_count"][0] == b["cover"]).all():
+            return False
+        ok = True
+        for (py, px), lst in b["cand"].items():
+            zs = sorted((float(bf.round_f32(z)), t) for (z, t, *_r) in lst)
+            ok &= o["primid"][0, py, px] == zs[0][1] or abs(zs[0][0] - zs[1][0]) < 1e-6
+            if o["primid"][0, py, px] == b["winner"][py, px]:
+                ok &= bool(np.allclose(o["color"][0, py, px, :3], b["color"][py, px], rtol=1e-5, atol=1e-6))
+        return ok
+
+    for seed in range(6):
+        check(f"brute{seed}", lambda seed=seed: brute(seed))
+    # perspective grid through the brute force
+    check("brute_persp", lambda: (lambda sc: (lambda o, b: (o["cover_count"][0] == b["cover"]).all()
+                                  and np.allclose(o["color"][0][b["winner"] >= 0][:, :3],
+                                                  b["color"][b["winner"] >= 0], rtol=1e-5, atol=1e-6))(
+        oracle.render(sc, want_cover=True), bf.render(sc)))(scenes.grid(seed=3, width=40, height=24, nx=8, ny=4)))
+
+    def watertight():
+        W = H = 24
+        X = [256 * 2, 256 * 20, 256 * 20, 256 * 2, 256 * 11 + 128]
+        Y = [256 * 3, 256 * 3, 256 * 19, 256 * 19, 256 * 10 + 128]
+        idx = [[0, 1, 4], [1, 2, 4], [4, 2, 3], [0, 4, 3]]
+        o = oracle.render(_ndc(W, H, X, Y, [0.5] * 5, idx=idx), want_cover=True)
+        inside = np.zeros((H, W), bool)
+        inside[3:19, 2:20] = True
+        c = o["cover_count"][0]
+        return (c[inside] == 1).all() and (c[~inside] == 0).all()
+    check("watertight", watertight)
+
+    def flat_top():
+        # top vertex on a sample centre, horizontal top edge going right: the
+        # sample at that vertex belongs to the triangle
+        sx, sy = 256 * 6 + 128, 256 * 9 + 128
+        sc = _ndc(16, 16, [sx, sx + 1280, sx + 512], [sy, sy, sy - 1536], [0.5] * 3)
+        o, b = oracle.render(sc, want_cover=True), bf.render(sc)
+        return b["cover"][9, 6] == 1 and (o["cover_count"][0] == b["cover"]).all()
+    check("flat_top", flat_top)
+
+    def ties():
+        rng = np.random.default_rng(12)
+        X = rng.integers(0, 256 * 24, 90)
+        Y = rng.integers(0, 256 * 24, 90)
+        Z = np.repeat(rng.integers(0, 3, 30) / 4.0, 3)
+        sc = _ndc(24, 24, X, Y, Z)
+        o, b = oracle.render(sc), bf.render(sc)
+        for (py, px), lst in b["cand"].items():
+            zmin = min(z for (z, *_r) in lst)
+            if o["primid"][0, py, px] != min(t for (z, t, *_r) in lst if z == zmin):
+                return False
+        return True
+    check("ties", ties)
+
+    def snap():
+        sc = SimpleNamespace(width=64, height=64, pos=np.array([[-0.68731689453125], [0.25], [0.5]], np.float32),
+                             color=np.zeros((3, 1), np.float32), idx=None, num_tris=0, mvp=None,
+                             uv=None, normal=None, texture=None, lights=None, shading="gouraud")
+        X, Y, *_r = oracle.vertices(sc)
+        return X[0] == 2562 and Y[0] == 10240
+    check("snap", snap)
+
+    def texture():
+        rng = np.random.default_rng(4)
+        tex = rng.uniform(0, 1, (6, 8, 3)).astype(np.float32)
+        X, Y = [0, 4096, 0, 4096], [0, 0, 4096, 4096]
+        ok = True
+        for (i, j) in [(3, 2), (7, 5)]:
+            uv = np.array([[(i + 0.5) / 8] * 4, [(j + 0.5) / 6] * 4])
+            sc = _ndc(16, 16, X, Y, [0.5] * 4, idx=[[0, 1, 3], [0, 3, 2]], color=np.ones((3, 4), np.float32),
+                      uv=uv.astype(np.float32), texture=tex, shading="textured")
+            o = oracle.render(sc)
+            ok &= bool(np.allclose(o["color"][0, :, :, :3], tex[j, i], atol=1e-6))
+        return ok
+    check("texture", texture)
+
+    def deferred():
+        X, Y = [0, 4096, 0, 4096], [0, 0, 4096, 4096]
+        n = np.repeat(-scenes.default_light().reshape(3, 1), 4, axis=1)
+        sc = _ndc(16, 16, X, Y, [0.5] * 4, idx=[[0, 1, 3], [0, 3, 2]], normal=n.astype(np.float32),
+                  lights=scenes.default_light(), shading="deferred")
+        return np.abs(oracle.render(sc)["color"][0, :, :, :3]).max() <= 1e-7
+    check("deferred", deferred)
+
+    def backward_sum():
+        sc = scenes.tiny(seed=2, width=24, height=18, num_tris=8)
+        o = oracle.render(sc)
+        G = np.random.default_rng(1).standard_normal((1, 18, 24, 4)).astype(np.float32)
+        gv, _ = oracle.backward(sc, o["primid"], o["bary"], G)
+        # d(sum_p G.img)/dC[v][c] has the closed form sum over pixels of b'_k G_c
+        h = 1e-3
+        ok = True
+        for (c, v) in [(0, 3), (1, 7), (2, 13)]:
+            col = sc.color.copy()
+            col[c, v] += h
+            s2 = SimpleNamespace(**{**vars(sc), "color": col})
+            lp = float((oracle.render(s2)["color"][..., :3].astype(np.float64) * G[..., :3]).sum())
+            col[c, v] -= 2 * h
+            s3 = SimpleNamespace(**{**vars(sc), "color": col})
+            lm = float((oracle.render(s3)["color"][..., :3].astype(np.float64) * G[..., :3]).sum())
+            ok &= abs((lp - lm) / (2 * h) - gv[c, v]) <= 1e-3 * abs(gv[c, v]) + 1e-3
+        return ok
+    check("backward", backward_sum)
+    return failed
+
+
+def test_unmodified_oracle_passes_subset(tmp_path):
+    lib = _build(tmp_path, "orig", open(SRC).read())
+    with oracle.using_library(lib):
+        assert _pins_fail() == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert old in text, f"mutation anchor for {name} not found"
+    lib = _build(tmp_path, name, text.replace(old, new, 1))
+    with oracle.using_library(lib):
+        failed = _pins_fail()
+    assert failed, f"no pin caught the planted mistake {name}"
