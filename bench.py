@@ -2,8 +2,9 @@
 
 One step = one whole frame of the hot path on resident inputs: vertex
 transform + setup + bin counts (pk_setup), prefix sum + scatter of the bin
-lists (pk_assign_bin), and per-bin coverage / depth test / resolve / shading
-(pk_raster_shade).  Prints one JSON line.  Default workload: the 1920x1080
+lists (pk_assign_bin), per-bin coverage and depth test (pk_raster_shade with
+the shading deferred) and the per-pixel resolve / shading pass (pk_shade).
+Prints one JSON line.  Default workload: the 1920x1080
 displaced grid of 1024x512 quads (1,048,576 triangles) through a perspective
 camera, Gouraud shading, 16x16 bins.
 """
@@ -51,23 +52,34 @@ def make_scene(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def raster_algorithmic_bytes(sc, npairs: int, covered_px: int, want_bary: bool) -> int:
-    """Algorithmic bytes of one k_raster launch (the per-bin Process kernel):
-    the bin lists read once (4 B per (bin, triangle) pair plus 4 B per bin
-    offset), every output pixel written once (colour 16 B, depth 4 B, primid
-    4 B, bary 8 B when saved; for deferred the G-buffer 24 B instead of the
-    colour), and the attributes of the visible triangle gathered once per
-    covered pixel (3 vertex indices 12 B when indexed, 3 x 3 colour floats
-    36 B, plus 36 B of normals for deferred).  Setup records are an
-    implementation choice and are not counted."""
+def bin_kernel_algorithmic_bytes(sc, npairs: int) -> int:
+    """Algorithmic bytes of one launch of the per-bin coverage + depth-test
+    kernel (k_raster, keys written for the per-pixel pass): per (bin, triangle)
+    pair the 4-byte list entry and the 36 bytes that coverage and depth need
+    of the triangle (three snapped vertices: x, y, z as 32-bit words); per bin
+    its two 4-byte CSR offsets; per pixel the 8-byte winning (depth, primitive)
+    key it writes.  The setup record's actual size (64 B) is an
+    implementation choice and is not counted."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
     npix = S * sc.width * sc.height
     B = int(getattr(sc, "bin_size", 16))
     nbins = S * (-(-sc.width // B)) * (-(-sc.height // B))
+    return 40 * npairs + 8 * nbins + 8 * npix
+
+
+def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
+    """Algorithmic bytes of the per-pixel resolve + shade pass: the 8-byte
+    key of every pixel read once, every output pixel written once (colour
+    16 B, depth 4 B, primid 4 B, bary 8 B when saved; for deferred the
+    G-buffer 24 B instead of the colour), and the attributes of the visible
+    triangle gathered once per covered pixel (3 vertex indices 12 B when
+    indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for deferred)."""
+    S = int(getattr(sc, "num_scenes", 1) or 1)
+    npix = S * sc.width * sc.height
     deferred = getattr(sc, "shading", "gouraud") == "deferred"
-    per_px = (24 if deferred else 16) + 4 + 4 + (8 if want_bary else 0)
+    per_px = 8 + (24 if deferred else 16) + 4 + 4 + (8 if want_bary else 0)
     per_cov = (12 if sc.idx is not None else 0) + 36 + (36 if deferred else 0)
-    return 4 * npairs + 4 * (nbins + 1) + per_px * npix + per_cov * covered_px
+    return per_px * npix + per_cov * covered_px
 
 
 def cpu_baseline(sc, budget_s: float = 12.0):
@@ -105,21 +117,39 @@ def _median_ms(torch, fn, reps):
     return ts[len(ts) // 2]
 
 
+def _tuned(sc, cands, want_bary=False):
+    """Autotuned configuration for a scene (cached across bench runs)."""
+    from paper_1404_6293_amd import autotune
+    cache = os.environ.get(autotune.CACHE_ENV, os.path.join(ROOT, "gpurun_out", "autotune.json"))
+    best, times = autotune.autotune(sc, want_bary=want_bary, cands=cands, reps=3,
+                                    cache_path=cache)
+    return best, times
+
+
 def bench_batched(reps: int = 10) -> dict:
     """256 scenes at 256x256 (log-uniform 1K-200K triangles each): one batched
-    frame replayed from a captured HIP graph, against the same 256 scenes
-    rendered as 256 sequential plain frames with the same configuration."""
+    frame replayed from a captured HIP graph with an autotuned bin size and
+    schedule, against the same 256 scenes rendered as 256 sequential plain
+    frames with the same configuration."""
     import torch
-    from paper_1404_6293_amd import pk, scenes
+    from paper_1404_6293_amd import autotune, pk, scenes
     sc = scenes.batch()
-    cfg = pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
-                          count_frags=True, want_bary=False)
-    rb = pk.Renderer(sc, cfg)
-    rb.capture()
+    dev = pk.DeviceScene(sc)
+    cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map", "dynamic"),
+                                     threads=(128,), fused=(False,)))
+    cfg, times = _tuned(dev, cands)
+    cfg.count_frags = True
+    rb = pk.Renderer(dev, cfg)
+    rb.render()
     torch.cuda.synchronize()
     frags = int(rb.frag_count.item())
+    rb.count_fragments(False)
+    rb.capture()
+    torch.cuda.synchronize()
     ms_b = _median_ms(torch, rb.replay, reps)
     assert not rb.ensure_capacity()
+    del rb
+    cfg.count_frags = False
     plain = [pk.Renderer(scenes.split_batch(sc, s), cfg) for s in range(sc.num_scenes)]
     for r in plain:
         r.render()
@@ -131,12 +161,41 @@ def bench_batched(reps: int = 10) -> dict:
     ms_p = _median_ms(torch, seq, max(3, reps // 3))
     tris = int(sc.num_tris)
     return {"workload": "batch256: 256 scenes at 256x256, log-uniform 1K-200K random triangles "
-                        "each (edge ~ log-normal around 4 px), 16x16 bins, direct_map",
+                        "each (edge ~ log-normal around 4 px)",
+            "tuned": {"bin_size": cfg.bin_size, "schedule": cfg.schedule,
+                      "threads_per_bin": cfg.threads_per_bin},
+            "tuning_ms": {k: round(v, 4) for k, v in times.items()},
             "triangles": tris, "fragments": frags,
             "batched_graph_ms": round(ms_b, 4), "sequential_plain_ms": round(ms_p, 4),
             "speedup": round(ms_p / ms_b, 3),
             "batched_mtris_per_s": round(tris / ms_b / 1e3, 1),
             "batched_gfrags_per_s": round(frags / ms_b / 1e6, 3)}
+
+
+def bench_micro(reps: int = 10) -> dict:
+    """2^23 micropolygons at 1920x1080 with deferred shading, bin size
+    autotuned in {8, 16, 32, 64}."""
+    import torch
+    from paper_1404_6293_amd import autotune, pk, scenes
+    sc = scenes.micro()
+    dev = pk.DeviceScene(sc)
+    cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map",),
+                                     threads=(128,), fused=(False,)))
+    cfg, times = _tuned(dev, cands)
+    cfg.count_frags = True
+    r = pk.Renderer(dev, cfg)
+    r.render()
+    torch.cuda.synchronize()
+    frags = int(r.frag_count.item())
+    r.count_fragments(False)
+    ms = _median_ms(torch, r.frame, reps)
+    tris = int(sc.num_tris)
+    return {"workload": "micro8m: 1920x1080, 8,388,608 micropolygons (log-normal area around "
+                        "0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
+            "tuned": {"bin_size": cfg.bin_size, "schedule": cfg.schedule},
+            "tuning_ms": {k: round(v, 4) for k, v in times.items()},
+            "frame_ms": round(ms, 4), "mtris_per_s": round(tris / ms / 1e3, 1),
+            "gfrags_per_s": round(frags / ms / 1e6, 3)}
 
 
 def bench_backward(reps: int = 10) -> dict:
@@ -148,7 +207,7 @@ def bench_backward(reps: int = 10) -> dict:
     from paper_1404_6293_amd import pk, scenes
     sc = scenes.diffgrid()
     r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
-                                        count_frags=True, want_bary=True))
+                                        want_bary=True))
     r.render()
     torch.cuda.synchronize()
     covered = int((r.out_primid >= 0).sum().item())
@@ -216,10 +275,13 @@ def main():
     tpb = wl["tpb"] if args.tpb < 0 else args.tpb
     bary = args.bary or wl["bary"]
     sc.bin_size = B
+    fused = args.fuse_resolve
+    # the frame's raster/shade step runs as two calls (bin kernel, then the
+    # per-pixel pass) so that each kernel is timed on its own
     cfg = pk.RenderConfig(bin_size=B, schedule=sched, threads_per_bin=tpb, count_frags=True,
-                          want_bary=bary, fuse_resolve=args.fuse_resolve)
+                          want_bary=bary, fuse_resolve=fused, defer_shade=not fused)
     print(f"bench: {args.workload} B={B} {sched} tpb={tpb} bary={bary} "
-          f"fused={args.fuse_resolve} steps={args.steps} warmup={args.warmup}",
+          f"fused={fused} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     r = pk.Renderer(sc, cfg)
     r.render()                       # sizes the bin-pair capacity once
@@ -227,19 +289,20 @@ def main():
     frags = int(r.frag_count.item())
     npairs = int(r.pairs_needed.item())
     covered = int((r.out_primid >= 0).sum().item())
+    # the fragment count is a statistic of the (deterministic) frame, taken
+    # once above; the timed frames render without the counter
+    r.count_fragments(False)
     for _ in range(args.warmup):
         r.frame()
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
         e = ev[k]
-        if cfg.count_frags:
-            r.frag_count.zero_()
         e[0].record(stream)
         r.setup()
         e[1].record(stream)
@@ -247,34 +310,44 @@ def main():
         e[2].record(stream)
         r.raster_shade()
         e[3].record(stream)
+        r.shade()
+        e[4].record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert not r.ensure_capacity(), "bin-pair capacity changed during the timed region"
-    stage = {"setup": 0.0, "assign_bin": 0.0, "raster_shade": 0.0}
-    for e in ev:
-        stage["setup"] += e[0].elapsed_time(e[1])
-        stage["assign_bin"] += e[1].elapsed_time(e[2])
-        stage["raster_shade"] += e[2].elapsed_time(e[3])
-    stage = {k: v / K for k, v in stage.items()}
+    names = ("setup", "assign_bin", "raster", "shade")
+    stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in ev) / K for i, n in enumerate(names)}
     ms = dt * 1e3 / K
     S = int(getattr(sc, "num_scenes", 1) or 1)
     tris = int(sc.num_tris) * (S if getattr(sc, "instanced", False) else 1)
     mtris = tris / (ms * 1e-3) / 1e6
     gfrags = frags / (ms * 1e-3) / 1e9
 
-    alg = raster_algorithmic_bytes(sc, npairs, covered, bary)
-    achieved = alg / (stage["raster_shade"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_raster", "achieved": round(achieved, 1),
+    alg_bin = bin_kernel_algorithmic_bytes(sc, npairs)
+    alg_px = shade_pass_algorithmic_bytes(sc, covered, bary)
+    if fused:
+        # one kernel: no key written or read back
+        kern, t_ms = "k_raster (fused resolve)", stage["raster"]
+        alg = alg_bin + alg_px - 16 * S * sc.width * sc.height
+    else:
+        kern, alg, t_ms = "k_raster", alg_bin, stage["raster"]
+    achieved = alg / (t_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "alg_bytes_per_launch": alg,
-                "avg_launch_ms": round(stage["raster_shade"], 4)}
+                "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
+    if not fused:
+        a2 = alg_px / (stage["shade"] * 1e-3) / 1e9
+        roofline["shade_pass"] = {"kernel": "k_resolve" + (" + k_deferred" if sc.shading == "deferred" else ""),
+                                  "achieved": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4),
+                                  "alg_bytes_per_launch": alg_px,
+                                  "avg_launch_ms": round(stage["shade"], 4)}
     out = {
         "metric": "Mtris/s + Gfrags/s at 1080p (binned raster); batched/backward vs plain, 1 GPU",
         "value": round(mtris, 2), "unit": "Mtris/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64+f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "bin_size": B,
-                   "schedule": sched, "threads_per_bin": tpb, "fused_resolve": args.fuse_resolve,
+                   "schedule": sched, "threads_per_bin": tpb, "fused_resolve": fused,
                    "saved_bary": bary, "triangles": tris,
                    "resolution": f"{sc.width}x{sc.height}", "scenes": S},
         "gfrags_per_s": round(gfrags, 3), "fragments_per_frame": frags,
@@ -286,6 +359,8 @@ def main():
         out["batched"] = bench_batched()
         print("bench: backward vs forward", file=sys.stderr, flush=True)
         out["backward"] = bench_backward()
+        print("bench: micropolygons", file=sys.stderr, flush=True)
+        out["micro"] = bench_micro()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(sc)
         cb["host"] = platform.processor() or platform.machine()

@@ -15,11 +15,15 @@
  *                   sum over the per-bin counts and a scatter into CSR bin
  *                   lists (Sec. 6, "Bin Management": prefix sums instead of
  *                   atomically appended lists).
- *   pk_raster_shade Schedule + Process of the per-bin stage: rasterizer,
- *                   depth test, fragment shader and composite fused into one
- *                   kernel per bin (Sec. 5.2.2 kernel fusion; the on-chip
- *                   depth buffer of Sec. 5.2.4 lives in LDS), followed by the
- *                   deferred shading pass when requested.
+ *   pk_raster_shade Schedule + Process of the per-bin stage: rasterizer and
+ *                   depth test in one kernel per bin (the on-chip depth
+ *                   buffer of Sec. 5.2.4 lives in LDS), then composite and
+ *                   fragment shader either in a per-pixel pass over the
+ *                   bins' winning keys or fused into the bin kernel
+ *                   (Sec. 5.2.2 kernel fusion), then the deferred shading
+ *                   pass when requested.
+ *   pk_shade        the per-pixel composite + shading pass on its own, for
+ *                   callers that split the frame (PK_FLAG_DEFER_SHADE).
  *   pk_backward     gradients of an image loss with respect to per-vertex
  *                   colours and texels (not in the paper).
  *
@@ -101,10 +105,14 @@ typedef enum {
 enum {
     PK_FLAG_COUNT_FRAGS = 1,  /* add the number of covered samples (before the
                                  depth test) to *targets.frag_count */
-    PK_FLAG_FUSE_RESOLVE = 2  /* resolve and shade inside the per-bin kernel
+    PK_FLAG_FUSE_RESOLVE = 2, /* resolve and shade inside the per-bin kernel
                                  (Rasterizer and Fragment Shader fused, Sec. 7.2)
                                  instead of in a separate per-pixel pass over the
                                  bins' winning keys; the image is the same */
+    PK_FLAG_DEFER_SHADE = 4   /* pk_raster_shade stops after the depth test and
+                                 leaves every pixel's winning (depth, primitive)
+                                 key in the workspace; pk_shade then resolves and
+                                 shades.  Excludes PK_FLAG_FUSE_RESOLVE. */
 };
 
 typedef struct {               /* [host] */
@@ -114,7 +122,8 @@ typedef struct {               /* [host] */
     int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto */
     int32_t shading;           /* pk_shading */
     int32_t flags;             /* PK_FLAG_* */
-    int32_t num_scenes;        /* S, 1..65535 */
+    int32_t num_scenes;        /* S, 1..65535; S*W*H <= 2^40 pixels and
+                                  S*ceil(W/64)*ceil(H/4) < 2^31 */
     int32_t instanced;         /* S > 1 only: 1 = S views (one MVP each) of the same
                                   mesh; 0 = S concatenated scenes (scene_*_off) */
     int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC workgroup count; 0 = auto */
@@ -154,15 +163,19 @@ typedef struct {                 /* [host] struct of device pointers; outputs [S
 } pk_targets;
 
 /* Size in bytes of the workspace that pk_setup / pk_assign_bin /
- * pk_raster_shade share for one frame: per-triangle setup records and
- * bounding boxes (num_tris triangles, times S when instanced), per-bin
- * counters and offsets, one 64-bit key per output pixel, and room for
- * pair_capacity (bin, triangle) pairs.
- * Returns 0 for invalid parameters.  Host-only; no HIP call. */
-size_t pk_workspace_bytes(const pk_params *p, int32_t num_tris, int64_t pair_capacity);
+ * pk_raster_shade share for one frame: snapped vertex records (indexed
+ * meshes: V per view), per-triangle setup records and bounding boxes
+ * (num_tris triangles, times S when instanced), per-bin counters and
+ * offsets, one 64-bit key per output pixel, and room for pair_capacity
+ * (bin, triangle) pairs.  Reads only the sizes and the indices pointer of
+ * `m` [host struct].  Returns 0 for invalid parameters.  Host-only; no HIP
+ * call. */
+size_t pk_workspace_bytes(const pk_params *p, const pk_mesh *m, int64_t pair_capacity);
 
 /* Vertex transform and triangle setup of every triangle (of every scene),
- * plus the per-bin triangle counts of AssignToBoundingBox.  Writes the
+ * plus the per-bin triangle counts of AssignToBoundingBox.  Indexed meshes
+ * first run the Vertex Shader once per vertex (per view), then setup gathers
+ * the snapped vertices; unindexed ones transform in setup.  Writes the
  * workspace only.  Sec. 7.1 stage list (Vertex Shader, Rasterizer setup);
  * Sec. 5.2.1 basic kernel mapping. */
 pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream);
@@ -184,6 +197,17 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
  * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace. */
 pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
                           const pk_targets *out, void *stream);
+
+/* Second half of a frame rendered with PK_FLAG_DEFER_SHADE: the Composite and
+ * Fragment Shader stages as their own per-pixel pass (Sec. 7.1 stage list;
+ * Sec. 5.2.2 discusses running them fused or apart).  Reads the winning keys
+ * that pk_raster_shade left in `ws`, resolves and shades every pixel, and
+ * writes every non-NULL target exactly as a pk_raster_shade without the flag
+ * would (frag_count is not touched).  `p` must carry PK_FLAG_DEFER_SHADE and
+ * equal the parameters of the pk_raster_shade call; `m`, `a` and `ws` are the
+ * same.  Arguments are validated as for pk_raster_shade. */
+pk_status pk_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
+                   const pk_targets *out, void *stream);
 
 /* Backward pass of Gouraud (or textured) shading: from the forward's saved
  * primid and bary buffers and the upstream gradient grad_color [S][H][W][4]
@@ -207,7 +231,7 @@ typedef struct {
     int64_t num_bins;
 } pk_bin_view;
 
-pk_status pk_bin_lists(const pk_params *p, int32_t num_tris, void *ws, pk_bin_view *out);
+pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_view *out);
 
 /* Static description of a status code.  Host-only. */
 const char *pk_status_string(pk_status s);

@@ -56,22 +56,45 @@ __device__ inline void resolve_fetch(const RasterArgs &a, int32_t s, int64_t ite
     r.t = key == kEmptyKey ? ~0u : (uint32_t)(key & 0xffffffffu);
     r.depth = __uint_as_float((uint32_t)(key >> 32));
     if (r.t == ~0u) return;
+    if (G.idx) {
+        // indexed: the snapped vertices come with the attributes (next
+        // phase), from the per-vertex records shared by neighbouring
+        // triangles, instead of from the 64-byte setup record
+        const int64_t g = G.instanced ? (int64_t)r.t : item_base + r.t;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r.v[k] = (int32_t)(vbase_scene + (int64_t)G.idx[3 * g + k]);
+        return;
+    }
     const TriRec *rp = a.w.rec + (item_base + r.t);
     r.xy = *reinterpret_cast<const uint4 *>(&rp->X0);
     r.xy2 = *reinterpret_cast<const uint2 *>(&rp->X2);
     r.iw[0] = rp->iw0; r.iw[1] = rp->iw1; r.iw[2] = rp->iw2;
     r.sinv = rp->sinv;
-    const int64_t g = G.instanced ? (int64_t)r.t : item_base + r.t;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        r.v[k] = (int32_t)(vbase_scene + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)r.t + k));
+    for (int k = 0; k < 3; ++k) r.v[k] = (int32_t)(vbase_scene + 3 * (int64_t)r.t + k);
 }
 
 template <int SHADE>
-__device__ inline void resolve_attribs(const RasterArgs &a, Resolve &r) {
+__device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &r) {
     if (r.t == ~0u) return;
     const Shade &sh = a.sh;
     const int64_t V = a.G.V;
+    if (a.G.idx) {
+        const int64_t vb = a.G.instanced ? (int64_t)s * V : 0;
+        int4 q[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] = reinterpret_cast<const int4 *>(a.w.vtx)[vb + r.v[k]];
+        r.xy = make_uint4((uint32_t)q[0].x, (uint32_t)q[0].y, (uint32_t)q[1].x, (uint32_t)q[1].y);
+        r.xy2 = make_uint2((uint32_t)q[2].x, (uint32_t)q[2].y);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r.iw[k] = __int_as_float(q[k].w);
+        // 1 / |2 area| with the sign of the winding, computed exactly as setup does
+        const int64_t A2 = (int64_t)(q[1].x - q[0].x) * (q[2].y - q[0].y) -
+                           (int64_t)(q[2].x - q[0].x) * (q[1].y - q[0].y);
+        const int64_t aa = A2 > 0 ? A2 : -A2;
+        const double inv = 1.0 / (double)aa;
+        r.sinv = A2 > 0 ? inv : -inv;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -269,8 +292,12 @@ constexpr int kKeysOnly = -1;
 // word planes of the per-wave staging area (C and inv as float64 hi/lo words)
 enum : int {
     kStA = 0, kStB = 3, kStClo = 6, kStChi = 9, kStZ = 12, kStInvLo = 15, kStInvHi = 16,
-    kStOrg = 17, kStWid = 18, kStMag = 19, kStPrim = 20, kStStart = 21, kStFields = 22
+    kStOrg = 17, kStWid = 18, kStMag = 19, kStPrim = 20, kStStart = 21, kStMark = 22,
+    kStFields = 23
 };
+// Start marks of the expansion mode carry a block tag in their upper bits so
+// that the plane never needs clearing; kNoTag is never a live tag.
+constexpr uint32_t kTagShift = 6, kNoTag = 0xffffffffu >> kTagShift;
 
 template <int TPB, int B, int SHADE>
 __global__ __launch_bounds__(TPB)
@@ -291,6 +318,9 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const int lane = tid & (kWave - 1), wv = tid / kWave;
     unsigned long long frags = 0;
     const bool overflow = a.w.misc[1] != 0;   // pair capacity exceeded: no lists
+    // expansion-mode start marks: no live tag yet
+    uint32_t tag = 0;
+    s_st[wv][kStMark][lane] = 0xffffffffu;
     // Bins are split into kXcd contiguous ranges; workgroup w works in range
     // w mod kXcd (workgroups are dealt to the dies round-robin), so each die's
     // L2 sees a compact screen region.  The mapping is a bijection whatever
@@ -357,9 +387,12 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             if (it > 0 || lane_in_xcd >= r_len) break;
             bin = r_beg + lane_in_xcd;
         }
-        const int32_t s = (int32_t)(bin / G.nbins_scene);
-        const int32_t lb = (int32_t)(bin - (int64_t)s * G.nbins_scene);
-        const int32_t by = lb / G.nbx, bx = lb - by * G.nbx;
+        // bin numbers are below 2^31: 32-bit divides (the 64-bit routine is
+        // a long scalar sequence)
+        const uint32_t ub = (uint32_t)bin;
+        const int32_t s = G.S == 1 ? 0 : (int32_t)(ub / (uint32_t)G.nbins_scene);
+        const int32_t lb = (int32_t)(ub - (uint32_t)s * (uint32_t)G.nbins_scene);
+        const int32_t by = (int32_t)((uint32_t)lb / (uint32_t)G.nbx), bx = lb - by * G.nbx;
         const int32_t px0 = bx * B, py0 = by * B;
         const int32_t pw = min(B, G.W - px0), ph = min(B, G.H - py0);
         const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
@@ -449,7 +482,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 }
             } else {
                 // large triangles: lay the wave's candidates end to end and
-                // give each lane every 64th; find the triangle by binary search
+                // hand them out in blocks of 64, one per lane
                 int total = t.cnt;
 #pragma unroll
                 for (int d = 1; d < kWave; d <<= 1) {
@@ -479,15 +512,35 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int nv = min(kWave, lend - c0);
+                int carry = 0;   // triangle of the last candidate of the previous block
 #pragma unroll 1
-                for (int j = lane; j < total; j += kWave) {
-                    int lo = 0, hi = nv - 1;   // last staged triangle with start <= j
-#pragma unroll 1
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if ((int)st[kStStart][mid] <= j) lo = mid; else hi = mid - 1;
+                for (int b = 0; b < total; b += kWave) {
+                    // Which triangle owns candidate j = b + lane: the last non-empty
+                    // triangle starting at or before j.  Each one starting inside
+                    // this block marks its start position with its lane; a ballot
+                    // of the live marks and a leading-zero count find the nearest
+                    // mark at or below j, a lane shuffle fetches it, and a block
+                    // position before any mark belongs to the previous block's
+                    // last triangle.
+                    if (tag == kNoTag - 1) {           // (never in practice) recycle tags
+                        st[kStMark][lane] = 0xffffffffu;
+                        tag = 0;
                     }
+                    if (t.cnt > 0 && start >= b && start < b + kWave)
+                        st[kStMark][start - b] = (tag << kTagShift) | (uint32_t)lane;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const uint32_t mk = st[kStMark][lane];
+                    const uint64_t live = __ballot((mk >> kTagShift) == tag);
+                    const uint64_t upto = live & ((2ull << lane) - 1ull);
+                    const int from = upto ? 63 - __clzll(upto) : 0;
+                    const int marked = __shfl((int)(mk & (kWave - 1)), from, kWave);
+                    const int lo = upto ? marked : carry;
+                    carry = __shfl(lo, kWave - 1, kWave);
+                    ++tag;
+                    const int j = b + lane;
+                    if (j >= total) continue;
                     const uint32_t local = (uint32_t)(j - (int)st[kStStart][lo]);
                     const int32_t wi = (int32_t)st[kStWid][lo];
                     const uint32_t wdt = (uint32_t)(wi & 0xff);
@@ -565,7 +618,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 }
 #pragma unroll
                 for (int k = 0; k < PPT; ++k)
-                    if (on[k]) resolve_attribs<SHADE>(a, rs[k]);
+                    if (on[k]) resolve_attribs<SHADE>(a, s, rs[k]);
 #pragma unroll
                 for (int k = 0; k < PPT; ++k)
                     if (on[k]) resolve_finish<SHADE>(a, s, px0 + lx[k], py0 + ly[k], rs[k]);
@@ -574,7 +627,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         __syncthreads();
     }
     if (a.sh.frag_count) {
-        // wave reduction, then one atomic per workgroup
+        // wave reduction, then one atomic per workgroup on its partial slot
         unsigned long long f = frags;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) f += __shfl_down(f, d, kWave);
@@ -583,38 +636,66 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         if (tid == 0) {
             unsigned long long tot = 0;
             for (int i = 0; i < NW; ++i) tot += s_frag[i];
-            if (tot) atomicAdd(a.sh.frag_count, tot);
-        }
-    }
-    if (a.schedule == PK_SCHED_DYNAMIC && tid == 0) {
-        // the last workgroup out rewinds the queues for the next launch
-        __threadfence();
-        const uint32_t done = atomicAdd(&a.w.misc[2], 1u);
-        if (done == gridDim.x - 1) {
-            for (int i = 0; i < kXcd; ++i) atomicExch(&a.w.misc[8 + i], 0u);
-            atomicExch(&a.w.misc[2], 0u);
+            unsigned long long *slots = reinterpret_cast<unsigned long long *>(a.w.misc + 64);
+            if (tot) atomicAdd(&slots[blockIdx.x % kFragSlots], tot);
         }
     }
 }
 
+// Runs after a bin kernel that used the misc words (one workgroup): adds the
+// partial fragment counts to the caller's counter and clears them, and
+// rewinds the DYNAMIC queue heads, so the words are zero again for another
+// pk_raster_shade on the same workspace (pk_setup also clears them).
+__global__ __launch_bounds__(kFragSlots) void k_raster_epilogue(uint32_t *misc,
+                                                                unsigned long long *frag_count,
+                                                                int rewind) {
+    __shared__ unsigned long long s_part[kFragSlots / kWave];
+    if (frag_count) {
+        unsigned long long *slots = reinterpret_cast<unsigned long long *>(misc + 64);
+        unsigned long long v = slots[threadIdx.x];
+        slots[threadIdx.x] = 0ull;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_down(v, d, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int i = 0; i < kFragSlots / kWave; ++i) tot += s_part[i];
+            *frag_count += tot;
+        }
+    }
+    if (rewind && threadIdx.x < kXcd) misc[8 + threadIdx.x] = 0u;
+}
+
 // Resolve of every pixel of every scene from the key buffer: one thread per
-// pixel, 64 x 4 pixel tiles per workgroup, the scene on the grid's z axis
-// (no divisions to find a pixel's coordinates).
+// pixel, 64 x 4 pixel tiles per workgroup.  Tiles are numbered row-major
+// (scene by scene) and split into kXcd contiguous ranges like the bins, and
+// workgroup w takes a tile from range w mod kXcd, so a die resolves the same
+// screen band whose triangles its bin kernel just read into its L2.
 constexpr int kResW = 64, kResH = 4;
 
 template <int SHADE>
 __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const Geom &G = a.G;
-    const int px = blockIdx.x * kResW + threadIdx.x;
-    const int py = blockIdx.y * kResH + threadIdx.y;
-    const int32_t s = blockIdx.z;
+    const int ntx = (G.W + kResW - 1) / kResW, nty = (G.H + kResH - 1) / kResH;
+    const int64_t per_scene = (int64_t)ntx * nty;
+    const int64_t ntiles = per_scene * G.S;
+    const int64_t q = ntiles / kXcd, rem = ntiles % kXcd;
+    const int xcd = blockIdx.x % kXcd;
+    // one workgroup per tile, so tile numbers fit the 32-bit grid size
+    const uint32_t tile = (uint32_t)(xcd * q + min<int64_t>(xcd, rem) + blockIdx.x / kXcd);
+    const int32_t s = G.S == 1 ? 0 : (int32_t)(tile / (uint32_t)per_scene);
+    const uint32_t ts = tile - (uint32_t)s * (uint32_t)per_scene;
+    const int ty = (int)(ts / (uint32_t)ntx), tx = (int)(ts - (uint32_t)ty * (uint32_t)ntx);
+    const int px = tx * kResW + (int)(threadIdx.x % kResW);
+    const int py = ty * kResH + (int)(threadIdx.x / kResW);
     if (px >= G.W || py >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
     const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
     Resolve r;
     resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, a.w.keys[p], r);
-    resolve_attribs<SHADE>(a, r);
+    resolve_attribs<SHADE>(a, s, r);
     resolve_finish<SHADE>(a, s, px, py, r);
 }
 
@@ -642,14 +723,27 @@ static hipError_t launch_shade(const RasterArgs &a, int tpb, dim3 grid, hipStrea
 
 template <int SHADE>
 static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
-    const dim3 grid((unsigned)((a.G.W + kResW - 1) / kResW), (unsigned)((a.G.H + kResH - 1) / kResH),
-                    (unsigned)a.G.S);
-    hipLaunchKernelGGL((k_resolve<SHADE>), grid, dim3(kResW, kResH), 0, st, a);
+    // one workgroup per tile; the tile count is a multiple of nothing in
+    // particular, so ranges differ by at most one tile between dies
+    const int64_t ntiles = (int64_t)((a.G.W + kResW - 1) / kResW) *
+                           ((a.G.H + kResH - 1) / kResH) * a.G.S;
+    hipLaunchKernelGGL((k_resolve<SHADE>), dim3((unsigned)ntiles), dim3(kResW * kResH), 0, st, a);
     return hipGetLastError();
 }
 
+hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipStream_t st) {
+    if (G.nbins_total == 0) return hipSuccess;
+    RasterArgs a{G, w, sh, 0, 1};
+    switch (sh.shading) {
+    case PK_SHADE_GOURAUD:  return launch_resolve<PK_SHADE_GOURAUD>(a, st);
+    case PK_SHADE_TEXTURED: return launch_resolve<PK_SHADE_TEXTURED>(a, st);
+    case PK_SHADE_DEFERRED: return launch_resolve<PK_SHADE_DEFERRED>(a, st);
+    default:                return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
-                         int groups, bool fused, hipStream_t st) {
+                         int groups, RasterMode mode, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
     // DYNAMIC pops are device-scope atomics on eight counters; take enough
     // bins per pop that each workgroup pops about four times
@@ -659,22 +753,26 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
     int64_t nblk = G.nbins_total;
     if (schedule != PK_SCHED_LOAD_BALANCE) nblk = groups < G.nbins_total ? groups : G.nbins_total;
     const dim3 grid((unsigned)nblk);
-    if (!fused) {
-        const hipError_t e = launch_shade<kKeysOnly>(a, tpb, grid, st);
-        if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (mode != kRasterFused) {
+        e = launch_shade<kKeysOnly>(a, tpb, grid, st);
+    } else {
         switch (sh.shading) {
-        case PK_SHADE_GOURAUD:  return launch_resolve<PK_SHADE_GOURAUD>(a, st);
-        case PK_SHADE_TEXTURED: return launch_resolve<PK_SHADE_TEXTURED>(a, st);
-        case PK_SHADE_DEFERRED: return launch_resolve<PK_SHADE_DEFERRED>(a, st);
-        default:                return hipErrorInvalidValue;
+        case PK_SHADE_GOURAUD:  e = launch_shade<PK_SHADE_GOURAUD>(a, tpb, grid, st); break;
+        case PK_SHADE_TEXTURED: e = launch_shade<PK_SHADE_TEXTURED>(a, tpb, grid, st); break;
+        case PK_SHADE_DEFERRED: e = launch_shade<PK_SHADE_DEFERRED>(a, tpb, grid, st); break;
+        default:                e = hipErrorInvalidValue;
         }
     }
-    switch (sh.shading) {
-    case PK_SHADE_GOURAUD:  return launch_shade<PK_SHADE_GOURAUD>(a, tpb, grid, st);
-    case PK_SHADE_TEXTURED: return launch_shade<PK_SHADE_TEXTURED>(a, tpb, grid, st);
-    case PK_SHADE_DEFERRED: return launch_shade<PK_SHADE_DEFERRED>(a, tpb, grid, st);
-    default:                return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    const int rewind = schedule == PK_SCHED_DYNAMIC;
+    if (sh.frag_count || rewind) {
+        hipLaunchKernelGGL(k_raster_epilogue, dim3(1), dim3(kFragSlots), 0, st, w.misc,
+                           sh.frag_count, rewind);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (mode == kRasterSplit) return launch_resolve_pass(G, w, sh, st);
+    return hipSuccess;
 }
 
 // Deferred shading pass over the G-buffer: colour = albedo * sum_l max(0, n.l).

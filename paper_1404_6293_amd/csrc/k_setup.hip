@@ -54,22 +54,99 @@ __device__ inline bool group_window(const Geom &G, int64_t first, int32_t &s_lo,
     return nwin <= kHist;
 }
 
-// Setup of one triangle: transform, snap, cull, record.  Returns the packed
-// pixel bbox (kEmptyKey when culled) and the triangle's scene.
-__device__ inline uint64_t setup_one(const Geom &G, const Ws &w, int64_t item, int32_t &s) {
-    s = 0;
+// Vertex Shader stage for indexed meshes: each vertex (of each view when
+// instanced) is transformed and snapped once, instead of once per triangle
+// that uses it.  The same vertex_stage function as the per-triangle path, so
+// the results are identical.
+// It also clears the nzero words at `zero` (the bin counters and misc words
+// that k_setup accumulates into), which saves a fill launch.
+__global__ __launch_bounds__(256) void k_vertex(Geom G, Ws w, uint32_t *zero, int64_t nzero) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t j = i; j < nzero; j += (int64_t)gridDim.x * blockDim.x) zero[j] = 0u;
+    const int64_t nv = G.V * (G.instanced ? G.S : 1);
+    if (i >= nv) return;
+    int32_t s = 0;
+    int64_t v = i;
+    if (G.instanced) {
+        s = (int32_t)((uint64_t)i / (uint64_t)G.V);
+        v = i - (int64_t)s * G.V;
+    } else if (G.S > 1) {
+        int lo = 0, hi = G.S - 1;           // last scene with vtx_off[s] <= v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (G.vtx_off[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+    }
+    const float *m = G.mvp ? G.mvp + 16 * (int64_t)s : nullptr;
+    VtxRec r;
+    if (!vertex_stage(G, v, m, r.X, r.Y, r.z, r.iw)) { r.X = kBadVertex; r.Y = 0; r.z = 0; r.iw = 0; }
+    reinterpret_cast<int4 *>(w.vtx)[i] = make_int4(r.X, r.Y, __float_as_int(r.z), __float_as_int(r.iw));
+}
+
+// Setup of one triangle in three steps, so that a thread can issue the loads
+// of all its triangles before it waits for any: (1) the vertex numbers (the
+// index buffer), (2) the vertices (snapped records of k_vertex, or raw
+// positions), (3) transform if needed, snap, cull and write the record.
+struct TriIn {
+    int64_t v[3];          // vertex numbers
+    int4 q[3];             // indexed: snapped X, Y, z, 1/w; else raw x, y, z
+    int32_t s;             // scene
+    bool ok;
+};
+
+__device__ inline void setup_indices(const Geom &G, int64_t item, TriIn &t) {
+    t.s = 0;
+    t.ok = item < G.items;
+    if (!t.ok) return;
+    const ItemRef r = item_ref(G, item);
+    t.s = r.s;
+    // a triangle may only use the vertices of its own scene
+    const int64_t vlo = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s] : 0;
+    const int64_t vhi = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s + 1] : G.V;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t.v[k] = vertex_of(G, r, k);
+        if (t.v[k] < vlo || t.v[k] >= vhi || t.v[k] >= G.V) t.ok = false;
+    }
+}
+
+__device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
+    if (!t.ok) return;
+    if (G.idx) {
+        const int64_t vb = G.instanced ? (int64_t)t.s * G.V : 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t.q[k] = reinterpret_cast<const int4 *>(w.vtx)[vb + t.v[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            t.q[k] = make_int4(__float_as_int(G.pos[t.v[k]]), __float_as_int(G.pos[G.V + t.v[k]]),
+                               __float_as_int(G.pos[2 * G.V + t.v[k]]), 0);
+    }
+}
+
+// Returns the packed pixel bbox (kEmptyKey when culled).
+__device__ inline uint64_t setup_finish(const Geom &G, const Ws &w, int64_t item,
+                                        const TriIn &t) {
     if (item >= G.items) return kEmptyKey;
     int32_t X[3] = {0, 0, 0}, Y[3] = {0, 0, 0};
     float z[3] = {0, 0, 0}, iw[3] = {0, 0, 0};
-    const ItemRef r = item_ref(G, item);
-    s = r.s;
-    const float *m = G.mvp ? G.mvp + 16 * (int64_t)r.s : nullptr;
-    bool ok = true;
+    bool ok = t.ok;
+    if (ok) {
+        if (G.idx) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int64_t v = vertex_of(G, r, k);
-        if (v < 0 || v >= G.V) { ok = false; continue; }
-        ok = vertex_stage(G, v, m, X[k], Y[k], z[k], iw[k]) && ok;
+            for (int k = 0; k < 3; ++k) {
+                ok = ok && t.q[k].x != kBadVertex;
+                X[k] = t.q[k].x; Y[k] = t.q[k].y;
+                z[k] = __int_as_float(t.q[k].z); iw[k] = __int_as_float(t.q[k].w);
+            }
+        } else {
+            const float *m = G.mvp ? G.mvp + 16 * (int64_t)t.s : nullptr;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                ok = vertex_stage_xyz(G, __int_as_float(t.q[k].x), __int_as_float(t.q[k].y),
+                                      __int_as_float(t.q[k].z), m, X[k], Y[k], z[k], iw[k]) && ok;
+        }
     }
     uint64_t bb = kEmptyKey;
     if (ok) {
@@ -129,18 +206,27 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
         for (int i = tid; i < nwin; i += kGroupThreads) s_hist[i] = 0;
         __syncthreads();
     }
-#pragma unroll 1
+    TriIn tin[kItemsPerThread];
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k)
+        setup_indices(G, first + k * kGroupThreads + tid, tin[k]);
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) setup_fetch(G, w, tin[k]);
+    // (unrolled: tin must stay in registers)
+#pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
         const int64_t item = first + k * kGroupThreads + tid;
-        int32_t s;
-        const uint64_t bb = setup_one(G, w, item, s);
+        const int32_t s = tin[k].s;
+        const uint64_t bb = setup_finish(G, w, item, tin[k]);
         const BinRect br = bin_rect(G, bb);
         // AssignBin counts of the screen-space stage
         if (lds) {
-            uint32_t *h = s_hist + (int64_t)(s - s_lo) * G.nbins_scene;
-            for (int i = 0; i < br.nb; ++i) {
-                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
-                atomicAdd(h + by * G.nbx + bx, 1u);
+            // LDS atomics are cheap enough per lane
+            uint32_t *h = s_hist + (s - s_lo) * G.nbins_scene;
+            int cx = br.bx0, cy = br.by0;
+            for (int r = 0; r < br.nb; ++r) {
+                atomicAdd(h + cy * G.nbx + cx, 1u);
+                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
         } else {
             // one round per bin of the largest bin rectangle in the wave
@@ -165,8 +251,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
 
 hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st) {
     // bin_count and misc are adjacent: one fill clears both (and the padding)
-    const int64_t words = (reinterpret_cast<char *>(w.misc) - reinterpret_cast<char *>(w.bin_count)) / 4 + 64;
-    hipError_t e = launch_fill_u32(w.bin_count, words, 0u, st);
+    const int64_t words = (reinterpret_cast<char *>(w.misc) - reinterpret_cast<char *>(w.bin_count)) / 4 + kMiscWords;
+    hipError_t e = hipSuccess;
+    if (G.idx && G.items > 0) {
+        // the vertex kernel clears them on its way (grid-stride)
+        const int64_t nv = G.V * (G.instanced ? G.S : 1);
+        int64_t blocks = (nv + 255) / 256;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_vertex, dim3((unsigned)blocks), dim3(256), 0, st, G, w, w.bin_count,
+                           words);
+        e = hipGetLastError();
+    } else {
+        e = launch_fill_u32(w.bin_count, words, 0u, st);
+    }
     if (e != hipSuccess || G.items == 0) return e;
     const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), 0, st, G, w);
@@ -267,10 +364,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
 #pragma unroll
         for (int k = 0; k < kItemsPerThread; ++k) {
             const BinRect br = bin_rect(G, bb[k]);
-            uint32_t *h = s_hist + (int64_t)(sc[k] - s_lo) * G.nbins_scene;
-            for (int i = 0; i < br.nb; ++i) {
-                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
-                atomicAdd(h + by * G.nbx + bx, 1u);
+            uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
+            int cx = br.bx0, cy = br.by0;
+            for (int r = 0; r < br.nb; ++r) {
+                atomicAdd(h + cy * G.nbx + cx, 1u);
+                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
         }
         __syncthreads();
@@ -286,11 +384,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         for (int k = 0; k < kItemsPerThread; ++k) {
             const int64_t item = first + k * kGroupThreads + tid;
             const BinRect br = bin_rect(G, bb[k]);
-            uint32_t *h = s_hist + (int64_t)(sc[k] - s_lo) * G.nbins_scene;
-            for (int i = 0; i < br.nb; ++i) {
-                const int by = br.by0 + i / br.nbx_t, bx = br.bx0 + i % br.nbx_t;
-                const uint32_t slot = atomicAdd(h + by * G.nbx + bx, 1u);
+            uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
+            int cx = br.bx0, cy = br.by0;
+            for (int r = 0; r < br.nb; ++r) {
+                const uint32_t slot = atomicAdd(h + cy * G.nbx + cx, 1u);
                 w.pairs[slot] = (int32_t)item;
+                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
         }
         return;

@@ -18,6 +18,7 @@ int ilog2(int b) { int l = 0; while ((1 << l) < b) ++l; return l; }
 // Host-side view of the parameters that every entry point shares.
 struct Frame {
     int64_t items = 0;
+    int64_t vrecs = 0;     // snapped vertex records (indexed meshes)
     int64_t npix = 0;      // S * W * H
     int64_t nbins_scene = 0;
     int64_t nbins_total = 0;
@@ -37,7 +38,10 @@ pk_status check_params(const pk_params *p, Frame &f) {
         return PK_ERR_INVALID_ARGUMENT;
     if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_DEFERRED)
         return PK_ERR_INVALID_ARGUMENT;
-    if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE)) return PK_ERR_INVALID_ARGUMENT;
+    if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE | PK_FLAG_DEFER_SHADE))
+        return PK_ERR_INVALID_ARGUMENT;
+    if ((p->flags & PK_FLAG_FUSE_RESOLVE) && (p->flags & PK_FLAG_DEFER_SHADE))
+        return PK_ERR_INVALID_ARGUMENT;
     if (p->num_scenes < 1 || p->num_scenes > 65535) return PK_ERR_INVALID_ARGUMENT;
     if (p->instanced != 0 && p->instanced != 1) return PK_ERR_INVALID_ARGUMENT;
     if (p->persistent_groups < 0) return PK_ERR_INVALID_ARGUMENT;
@@ -48,6 +52,10 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
     f.npix = (int64_t)p->num_scenes * p->width * p->height;
     if (f.npix > (int64_t)1 << 40) return PK_ERR_INVALID_ARGUMENT;
+    // the per-pixel pass runs one workgroup per 64 x 4 tile
+    if ((int64_t)p->num_scenes * ((p->width + 63) / 64) * ((p->height + 3) / 4) >=
+        (int64_t)INT32_MAX)
+        return PK_ERR_INVALID_ARGUMENT;
     return PK_OK;
 }
 
@@ -59,21 +67,23 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
         return PK_ERR_INVALID_ARGUMENT;
     f.items = p->instanced ? (int64_t)m->num_tris * p->num_scenes : m->num_tris;
     if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    f.vrecs = m->indices ? (int64_t)m->num_vertices * (p->instanced ? p->num_scenes : 1) : 0;
     return PK_OK;
 }
 
 struct Layout {
-    size_t rec, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
+    size_t vtx, rec, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
     Layout L;
     size_t o = 0;
+    L.vtx = o;       o = align_up(o + sizeof(VtxRec) * (size_t)f.vrecs);
     L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
     L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
     // counters and misc words are adjacent so one fill clears both
     L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
-    L.misc = o;      o = align_up(o + sizeof(uint32_t) * 64);
+    L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
     L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix);
@@ -88,6 +98,7 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     const Layout L = layout(f, pair_capacity);
     char *b = static_cast<char *>(ws);
     Ws w;
+    w.vtx = reinterpret_cast<VtxRec *>(b + L.vtx);
     w.rec = reinterpret_cast<TriRec *>(b + L.rec);
     w.bbox = reinterpret_cast<uint64_t *>(b + L.bbox);
     w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
@@ -125,6 +136,33 @@ Geom geom(const pk_params *p, const pk_mesh *m, const Frame &f) {
 
 pk_status hip_status(hipError_t e) { return e == hipSuccess ? PK_OK : PK_ERR_HIP; }
 
+// Validation shared by pk_raster_shade and pk_shade, and the kernels' view of
+// the attributes and targets.
+pk_status shade_args(const pk_params *p, const pk_attribs *a, const pk_targets *out,
+                     const Frame &f, Shade &sh) {
+    if (!a || !out) return PK_ERR_INVALID_ARGUMENT;
+    if (f.items > 0 && !a->color) return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_TEXTURED &&
+        (!a->uv || !a->texture || a->tex_w < 1 || a->tex_h < 1))
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_DEFERRED &&
+        (!a->normal || !out->gbuf_normal || !out->gbuf_albedo || !out->primid || !out->color ||
+         a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
+        return PK_ERR_INVALID_ARGUMENT;
+    if ((p->flags & PK_FLAG_COUNT_FRAGS) && !out->frag_count) return PK_ERR_INVALID_ARGUMENT;
+    sh = Shade{};
+    sh.color = a->color; sh.uv = a->uv; sh.normal = a->normal; sh.texture = a->texture;
+    sh.lights = a->lights; sh.tex_w = a->tex_w; sh.tex_h = a->tex_h;
+    sh.num_lights = a->num_lights; sh.shading = p->shading;
+    sh.out_color = out->color; sh.out_depth = out->depth; sh.out_bary = out->bary;
+    sh.gbuf_n = p->shading == PK_SHADE_DEFERRED ? out->gbuf_normal : nullptr;
+    sh.gbuf_a = p->shading == PK_SHADE_DEFERRED ? out->gbuf_albedo : nullptr;
+    sh.out_primid = out->primid;
+    sh.flags = p->flags;
+    sh.frag_count = (p->flags & PK_FLAG_COUNT_FRAGS) ? out->frag_count : nullptr;
+    return PK_OK;
+}
+
 }  // namespace
 }  // namespace pk
 
@@ -132,13 +170,11 @@ using namespace pk;
 
 extern "C" {
 
-size_t pk_workspace_bytes(const pk_params *p, int32_t num_tris, int64_t pair_capacity) {
+size_t pk_workspace_bytes(const pk_params *p, const pk_mesh *m, int64_t pair_capacity) {
     Frame f;
-    if (check_params(p, f) != PK_OK || num_tris < 0 || pair_capacity < 0 ||
+    if (check_params(p, f) != PK_OK || check_mesh(p, m, f) != PK_OK || pair_capacity < 0 ||
         pair_capacity >= (int64_t)INT32_MAX)
         return 0;
-    f.items = p->instanced ? (int64_t)num_tris * p->num_scenes : num_tris;
-    if (f.items >= (int64_t)INT32_MAX) return 0;
     return layout(f, pair_capacity).total;
 }
 
@@ -173,36 +209,39 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     pk_status st = check_params(p, f);
     if (st != PK_OK) return st;
     if ((st = check_mesh(p, m, f)) != PK_OK) return st;
-    if (!ws || !a || !out) return PK_ERR_INVALID_ARGUMENT;
-    if (f.items > 0 && !a->color) return PK_ERR_INVALID_ARGUMENT;
-    if (p->shading == PK_SHADE_TEXTURED &&
-        (!a->uv || !a->texture || a->tex_w < 1 || a->tex_h < 1))
-        return PK_ERR_INVALID_ARGUMENT;
-    if (p->shading == PK_SHADE_DEFERRED &&
-        (!a->normal || !out->gbuf_normal || !out->gbuf_albedo || !out->primid || !out->color ||
-         a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
-        return PK_ERR_INVALID_ARGUMENT;
-    if ((p->flags & PK_FLAG_COUNT_FRAGS) && !out->frag_count) return PK_ERR_INVALID_ARGUMENT;
-    const Geom G = geom(p, m, f);
+    if (!ws) return PK_ERR_INVALID_ARGUMENT;
     Shade sh;
-    sh.color = a->color; sh.uv = a->uv; sh.normal = a->normal; sh.texture = a->texture;
-    sh.lights = a->lights; sh.tex_w = a->tex_w; sh.tex_h = a->tex_h;
-    sh.num_lights = a->num_lights; sh.shading = p->shading;
-    sh.out_color = out->color; sh.out_depth = out->depth; sh.out_bary = out->bary;
-    sh.gbuf_n = p->shading == PK_SHADE_DEFERRED ? out->gbuf_normal : nullptr;
-    sh.gbuf_a = p->shading == PK_SHADE_DEFERRED ? out->gbuf_albedo : nullptr;
-    sh.out_primid = out->primid;
-    sh.flags = p->flags;
-    sh.frag_count = (p->flags & PK_FLAG_COUNT_FRAGS) ? out->frag_count : nullptr;
+    if ((st = shade_args(p, a, out, f, sh)) != PK_OK) return st;
+    const Geom G = geom(p, m, f);
     int tpb = p->threads_per_bin;
     if (tpb == 0) tpb = p->bin_size <= 8 ? 64 : 256;
     int groups = p->persistent_groups;
     if (groups == 0) groups = 256 * 8;
+    const RasterMode mode = (p->flags & PK_FLAG_FUSE_RESOLVE) ? kRasterFused
+                            : (p->flags & PK_FLAG_DEFER_SHADE) ? kRasterKeysOnly
+                                                               : kRasterSplit;
     // the pair list is the last slice, so its address does not depend on the
     // capacity; the lists are read through bin_off only
     const Ws w = carve(ws, f, 0);
-    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups,
-                                 (p->flags & PK_FLAG_FUSE_RESOLVE) != 0, (hipStream_t)stream);
+    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups, mode, (hipStream_t)stream);
+    if (e == hipSuccess && mode != kRasterKeysOnly && p->shading == PK_SHADE_DEFERRED)
+        e = launch_deferred(G, sh, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+pk_status pk_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
+                   const pk_targets *out, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (!ws || !(p->flags & PK_FLAG_DEFER_SHADE)) return PK_ERR_INVALID_ARGUMENT;
+    Shade sh;
+    if ((st = shade_args(p, a, out, f, sh)) != PK_OK) return st;
+    sh.frag_count = nullptr;
+    const Geom G = geom(p, m, f);
+    const Ws w = carve(ws, f, 0);
+    hipError_t e = launch_resolve_pass(G, w, sh, (hipStream_t)stream);
     if (e == hipSuccess && p->shading == PK_SHADE_DEFERRED)
         e = launch_deferred(G, sh, (hipStream_t)stream);
     return hip_status(e);
@@ -229,13 +268,12 @@ pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
                                       (hipStream_t)stream));
 }
 
-pk_status pk_bin_lists(const pk_params *p, int32_t num_tris, void *ws, pk_bin_view *out) {
+pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_view *out) {
     Frame f;
     pk_status st = check_params(p, f);
     if (st != PK_OK) return st;
-    if (!ws || !out || num_tris < 0) return PK_ERR_INVALID_ARGUMENT;
-    f.items = p->instanced ? (int64_t)num_tris * p->num_scenes : num_tris;
-    if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    if (!ws || !out) return PK_ERR_INVALID_ARGUMENT;
     const Ws w = carve(ws, f, 0);
     out->bin_offsets = w.bin_off;
     out->bin_tris = w.pairs;

@@ -13,6 +13,12 @@ namespace pk {
 constexpr int kWave = 64;
 constexpr int kXcd = 8;       // accelerator complex dies of an MI355X
 constexpr unsigned long long kEmptyKey = ~0ull;
+// Fragment counts are summed per workgroup into kFragSlots partial counters
+// (workgroup w adds to slot w mod kFragSlots) and then reduced by one small
+// kernel: device-scope atomics on a single address serialize, thousands of
+// them cost more than the kernel they count in.
+constexpr int kFragSlots = 256;
+constexpr int kMiscWords = 64 + 2 * kFragSlots;
 
 // Per-triangle setup record, 64 bytes so one aligned record is half of a
 // 128-byte cache line and loads as four dwordx4.
@@ -42,15 +48,27 @@ struct Geom {
     int64_t nbins_total;       // S * nbins_scene
 };
 
+// Snapped vertex of an indexed mesh (the Vertex Shader stage's output),
+// 16 bytes; X == kBadVertex marks a vertex that drops its triangles.
+struct __align__(16) VtxRec {
+    int32_t X, Y;
+    float z, iw;
+};
+constexpr int32_t kBadVertex = (int32_t)0x80000000;
+
 // Workspace slices (device pointers carved out of the caller's buffer).
 struct Ws {
+    VtxRec *vtx;               // [S or 1][V] for indexed meshes, else unused
     TriRec *rec;               // [items]
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
     int32_t *cursor;           // [nbins_total]
-    uint32_t *misc;            // [64], right after bin_count: 1 pair overflow flag,
-                               // 2 workgroups done (DYNAMIC), 8..15 queue heads
+    uint32_t *misc;            // [kMiscWords], right after bin_count: [1] pair
+                               // overflow flag, [8..15] DYNAMIC queue heads,
+                               // [64..) kFragSlots 64-bit fragment partial sums;
+                               // zeroed by pk_setup, heads and sums re-zeroed
+                               // after each bin kernel that used them
     unsigned long long *keys;  // [S][H][W] winning (depth, primitive) keys
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
@@ -104,9 +122,9 @@ __device__ inline int64_t vertex_of(const Geom &G, const ItemRef &r, int k) {
 // Vertex shader stage: clip = MVP (x,y,z,1) with every product rounded and
 // the sums taken left to right, NDC = clip * (1/w) with one correctly
 // rounded reciprocal, viewport, 8-bit sub-pixel snap (round half to even).  Returns false for a vertex that drops its triangle.
-__device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, int32_t &X,
-                                    int32_t &Y, float &z, float &iw) {
-    const float x = G.pos[v], y = G.pos[G.V + v], zz = G.pos[2 * G.V + v];
+__device__ inline bool vertex_stage_xyz(const Geom &G, float x, float y, float zz,
+                                        const float *m, int32_t &X, int32_t &Y, float &z,
+                                        float &iw) {
     float c0, c1, c2, c3;
     if (m) {
         float t;
@@ -133,6 +151,11 @@ __device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, in
     z = zn;
     iw = w1;
     return true;
+}
+
+__device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, int32_t &X,
+                                    int32_t &Y, float &z, float &iw) {
+    return vertex_stage_xyz(G, G.pos[v], G.pos[G.V + v], G.pos[2 * G.V + v], m, X, Y, z, iw);
 }
 
 __device__ inline uint32_t bb_x0(uint64_t b) { return (uint32_t)(b & 0xffff); }
@@ -240,8 +263,15 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st);
 hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
 hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st);
+// What a pk_raster_shade call launches after the bin kernel's depth test.
+enum RasterMode : int {
+    kRasterSplit = 0,      // keys to the workspace, then the per-pixel resolve pass
+    kRasterFused = 1,      // resolve and shade inside the bin kernel
+    kRasterKeysOnly = 2    // keys to the workspace only (pk_shade resolves later)
+};
 hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
-                         int groups, bool fused, hipStream_t st);
+                         int groups, RasterMode mode, hipStream_t st);
+hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipStream_t st);
 hipError_t launch_deferred(const Geom &G, const Shade &sh, hipStream_t st);
 hipError_t launch_backward(const Geom &G, const Shade &sh, const int32_t *primid,
                            const float *bary, const float *grad, float *grad_vcolor,

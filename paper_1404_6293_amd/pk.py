@@ -24,14 +24,15 @@ PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC = range(3)
 PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED = range(3)
 PK_FLAG_COUNT_FRAGS = 1
 PK_FLAG_FUSE_RESOLVE = 2
+PK_FLAG_DEFER_SHADE = 4
 
 SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIRECT_MAP,
              "dynamic": PK_SCHED_DYNAMIC}
 SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
             "deferred": PK_SHADE_DEFERRED}
 
-EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_backward",
-           "pk_bin_lists", "pk_status_string")
+EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_shade",
+           "pk_backward", "pk_bin_lists", "pk_status_string")
 
 
 class PkError(RuntimeError):
@@ -82,17 +83,19 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.pk_workspace_bytes.restype = C.c_size_t
-        L.pk_workspace_bytes.argtypes = [P, C.c_int32, C.c_int64]
+        L.pk_workspace_bytes.argtypes = [P, P, C.c_int64]
         L.pk_setup.restype = C.c_int
         L.pk_setup.argtypes = [P, P, P, P]
         L.pk_assign_bin.restype = C.c_int
         L.pk_assign_bin.argtypes = [P, P, P, C.c_int64, P, P]
         L.pk_raster_shade.restype = C.c_int
         L.pk_raster_shade.argtypes = [P, P, P, P, P, P]
+        L.pk_shade.restype = C.c_int
+        L.pk_shade.argtypes = [P, P, P, P, P, P]
         L.pk_backward.restype = C.c_int
         L.pk_backward.argtypes = [P, P, P, P, P, P, P, P, P]
         L.pk_bin_lists.restype = C.c_int
-        L.pk_bin_lists.argtypes = [P, C.c_int32, P, P]
+        L.pk_bin_lists.argtypes = [P, P, P, P]
         L.pk_status_string.restype = C.c_char_p
         L.pk_status_string.argtypes = [C.c_int]
         _lib = L
@@ -113,8 +116,8 @@ def _ref(x):
 
 
 # --- the four calls of the ABI, same names -------------------------------
-def pk_workspace_bytes(params: Params, num_tris: int, pair_capacity: int) -> int:
-    return int(lib().pk_workspace_bytes(C.byref(params), int(num_tris), int(pair_capacity)))
+def pk_workspace_bytes(params: Params, mesh: Mesh, pair_capacity: int) -> int:
+    return int(lib().pk_workspace_bytes(C.byref(params), C.byref(mesh), int(pair_capacity)))
 
 
 def pk_setup(params: Params, mesh: Mesh, ws: int, stream: int = 0):
@@ -133,15 +136,21 @@ def pk_raster_shade(params: Params, mesh: Mesh, attribs: Attribs, ws: int, targe
                                                     _ref(targets), stream))
 
 
+def pk_shade(params: Params, mesh: Mesh, attribs: Attribs, ws: int, targets: Targets,
+             stream: int = 0):
+    _check("pk_shade", lib().pk_shade(_ref(params), _ref(mesh), _ref(attribs), ws,
+                                      _ref(targets), stream))
+
+
 def pk_backward(params: Params, mesh: Mesh, attribs: Attribs, primid: int, bary: int,
                 grad_color: int, grad_vcolor: int, grad_tex: int, stream: int = 0):
     _check("pk_backward", lib().pk_backward(_ref(params), _ref(mesh), _ref(attribs), primid, bary,
                                             grad_color, grad_vcolor, grad_tex, stream))
 
 
-def pk_bin_lists(params: Params, num_tris: int, ws: int) -> BinView:
+def pk_bin_lists(params: Params, mesh: Mesh, ws: int) -> BinView:
     v = BinView()
-    _check("pk_bin_lists", lib().pk_bin_lists(_ref(params), int(num_tris), ws, C.byref(v)))
+    _check("pk_bin_lists", lib().pk_bin_lists(_ref(params), _ref(mesh), ws, C.byref(v)))
     return v
 
 
@@ -164,6 +173,9 @@ class RenderConfig:
     count_frags: bool = False
     want_bary: bool = True
     fuse_resolve: bool = False
+    # raster_shade() stops after the depth test and shade() resolves; frame()
+    # calls both (lets a caller time or overlap the two passes)
+    defer_shade: bool = False
 
 
 def _light_default():
@@ -254,7 +266,8 @@ class Renderer:
         self.params = Params(self.W, self.H, int(cfg.bin_size), SCHEDULES[cfg.schedule],
                              int(cfg.threads_per_bin), self.shading,
                              (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
-                             | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0), self.S,
+                             | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0)
+                             | (PK_FLAG_DEFER_SHADE if cfg.defer_shade else 0), self.S,
                              int(d.instanced), int(cfg.persistent_groups))
         self.mesh = d.mesh()
         self.attribs = d.attribs()
@@ -278,7 +291,7 @@ class Renderer:
         self._alloc_ws(max(4 * self.items, 1024))
 
     def _alloc_ws(self, capacity: int):
-        nbytes = pk_workspace_bytes(self.params, self.dev.num_tris, capacity)
+        nbytes = pk_workspace_bytes(self.params, self.mesh, capacity)
         if nbytes == 0:
             raise PkError("pk_workspace_bytes", PK_ERR_INVALID_ARGUMENT, "invalid parameters")
         self.capacity = capacity
@@ -297,13 +310,30 @@ class Renderer:
         pk_raster_shade(self.params, self.mesh, self.attribs, self.ws.data_ptr(), self.targets,
                         _stream())
 
+    def shade(self):
+        """Per-pixel resolve and shading of a frame whose raster_shade() ran
+        with ``defer_shade``; a no-op otherwise."""
+        if self.cfg.defer_shade:
+            pk_shade(self.params, self.mesh, self.attribs, self.ws.data_ptr(), self.targets,
+                     _stream())
+
+    def count_fragments(self, on: bool):
+        """Switch the covered-sample counter (PK_FLAG_COUNT_FRAGS) on or off
+        for the following frames; the images do not change."""
+        if on:
+            self.params.flags |= PK_FLAG_COUNT_FRAGS
+        else:
+            self.params.flags &= ~PK_FLAG_COUNT_FRAGS
+        self.graph = None   # a captured graph holds the old flags
+
     def frame(self):
         """Enqueue one whole frame; no synchronization."""
-        if self.cfg.count_frags:
+        if self.params.flags & PK_FLAG_COUNT_FRAGS:
             self.frag_count.zero_()
         self.setup()
         self.assign_bin()
         self.raster_shade()
+        self.shade()
 
     def ensure_capacity(self) -> bool:
         """Read the pair count of the last frame; grow the workspace and return
@@ -355,7 +385,7 @@ class Renderer:
         """CSR bin lists of the last frame, copied to the host for checking:
         (offsets[nbins_total+1], triangle numbers) as NumPy arrays."""
         import torch
-        v = pk_bin_lists(self.params, self.dev.num_tris, self.ws.data_ptr())
+        v = pk_bin_lists(self.params, self.mesh, self.ws.data_ptr())
         base = self.ws.data_ptr()
         o0 = v.bin_offsets - base
         off = self.ws[o0:o0 + 4 * (v.num_bins + 1)].view(torch.int32).cpu().numpy().copy()

@@ -29,8 +29,8 @@ def declared_functions():
 
 def test_header_declares_the_abi():
     names = declared_functions()
-    for n in ("pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_backward", "pk_workspace_bytes",
-              "pk_status_string", "pk_bin_lists"):
+    for n in ("pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_shade", "pk_backward",
+              "pk_workspace_bytes", "pk_status_string", "pk_bin_lists"):
         assert n in names
     assert set(names) == set(pk.EXPORTS)
 
@@ -60,13 +60,13 @@ def _mesh(**kw):
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
     dict(bin_size=-8), dict(schedule=3), dict(schedule=-1), dict(threads_per_bin=32),
-    dict(threads_per_bin=512), dict(shading=3), dict(flags=4), dict(num_scenes=0),
+    dict(threads_per_bin=512), dict(shading=3), dict(flags=8), dict(flags=6), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
     p = _params(**bad)
     assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
     assert L.pk_assign_bin(C.byref(p), C.byref(_mesh()), FAKE, 16, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert L.pk_workspace_bytes(C.byref(p), 10, 100) == 0
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh()), 100) == 0
 
 
 def test_whole_screen_bins_unsupported(L):
@@ -98,6 +98,19 @@ def test_null_and_inconsistent_pointers_rejected(L):
     assert L.pk_raster_shade(C.byref(pd), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
     pf = _params(flags=1)
     assert L.pk_raster_shade(C.byref(pf), C.byref(_mesh()), C.byref(a), FAKE, C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    # the deferred shading pass needs the flag and the same attribute checks
+    assert L.pk_shade(C.byref(p), C.byref(_mesh()), C.byref(pk.Attribs(color=FAKE)), FAKE,
+                      C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    pdef = _params(flags=pk.PK_FLAG_DEFER_SHADE)
+    assert L.pk_shade(C.byref(pdef), C.byref(_mesh()), None, FAKE, C.byref(t),
+                      None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_shade(C.byref(pdef), C.byref(_mesh()), C.byref(pk.Attribs(color=None)), FAKE,
+                      C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_shade(C.byref(pdef), C.byref(_mesh()), C.byref(pk.Attribs(color=FAKE)), None,
+                      C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    pdt = _params(flags=pk.PK_FLAG_DEFER_SHADE, shading=1)
+    assert L.pk_shade(C.byref(pdt), C.byref(_mesh()), C.byref(pk.Attribs(color=FAKE)), FAKE,
+                      C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
     # backward
     assert L.pk_backward(C.byref(p), C.byref(_mesh()), C.byref(a), None, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_INVALID_ARGUMENT
     assert L.pk_backward(C.byref(pd), C.byref(_mesh()), C.byref(a), FAKE, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_UNSUPPORTED
@@ -107,34 +120,41 @@ def test_null_and_inconsistent_pointers_rejected(L):
 def test_workspace_bytes_arithmetic(L):
     p = _params(width=100, height=70, bin_size=16)
     T = 1000
-    b0 = L.pk_workspace_bytes(C.byref(p), T, 0)
-    b1 = L.pk_workspace_bytes(C.byref(p), T, 64)
-    b2 = L.pk_workspace_bytes(C.byref(p), T, 64 + 1)
+    m = _mesh(num_tris=T, num_vertices=3 * T)
+    b0 = L.pk_workspace_bytes(C.byref(p), C.byref(m), 0)
+    b1 = L.pk_workspace_bytes(C.byref(p), C.byref(m), 64)
+    b2 = L.pk_workspace_bytes(C.byref(p), C.byref(m), 64 + 1)
     assert b0 > 0 and b1 - b0 == 256 and b2 - b1 == 256
     nbins = 7 * 5
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     expect = (al(64 * T) + al(8 * T) + al(4 * nbins) + al(4 * (nbins + 1)) + al(4 * nbins)
-              + al(256) + al(8 * 100 * 70))
+              + al(4 * 576) + al(8 * 100 * 70))
     assert b0 == expect
-    # instanced views multiply the per-triangle slices
+    # an indexed mesh adds one 16-byte snapped record per vertex (per view)
+    mi = _mesh(num_tris=T, num_vertices=600, indices=FAKE)
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(mi), 0) == expect + al(16 * 600)
+    # instanced views multiply the per-triangle and per-vertex slices
     pi = _params(width=100, height=70, bin_size=16, num_scenes=3, instanced=1)
     nb3 = 3 * nbins
     expect3 = (al(64 * 3 * T) + al(8 * 3 * T) + al(4 * nb3) + al(4 * (nb3 + 1)) + al(4 * nb3)
-               + al(256) + al(8 * 3 * 100 * 70))
-    assert L.pk_workspace_bytes(C.byref(pi), T, 0) == expect3
-    assert L.pk_workspace_bytes(C.byref(p), -1, 0) == 0
-    assert L.pk_workspace_bytes(C.byref(p), T, -5) == 0
+               + al(4 * 576) + al(8 * 3 * 100 * 70))
+    assert L.pk_workspace_bytes(C.byref(pi), C.byref(m), 0) == expect3
+    assert L.pk_workspace_bytes(C.byref(pi), C.byref(mi), 0) == expect3 + al(16 * 3 * 600)
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh(num_tris=-1)), 0) == 0
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(m), -5) == 0
+    assert L.pk_workspace_bytes(C.byref(p), None, 0) == 0
 
 
 def test_bin_lists_view_points_into_workspace(L):
     p = _params(width=100, height=70, bin_size=16)
+    m = _mesh(num_tris=1000, num_vertices=3000)
     v = pk.BinView()
     base = 1 << 20
-    assert L.pk_bin_lists(C.byref(p), 1000, base, C.byref(v)) == pk.PK_OK
+    assert L.pk_bin_lists(C.byref(p), C.byref(m), base, C.byref(v)) == pk.PK_OK
     assert v.num_bins == 35
-    size = L.pk_workspace_bytes(C.byref(p), 1000, 0)
+    size = L.pk_workspace_bytes(C.byref(p), C.byref(m), 0)
     assert base < v.bin_offsets < v.bin_tris == base + size
-    assert L.pk_bin_lists(C.byref(p), 1000, None, C.byref(v)) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_bin_lists(C.byref(p), C.byref(m), None, C.byref(v)) == pk.PK_ERR_INVALID_ARGUMENT
 
 
 def test_status_strings(L):

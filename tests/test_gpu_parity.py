@@ -82,9 +82,11 @@ def test_metamorphic_bins_schedules_threads():
                               ("dynamic", 7), ("dynamic", 0)):
             for tpb in (64, 128, 256):
                 fused = (tpb == 128)
-                _note(f"metamorphic B={B} {sched} groups={groups} tpb={tpb} fused={fused}")
+                defer = (tpb == 256 and sched == "direct_map")
+                _note(f"metamorphic B={B} {sched} groups={groups} tpb={tpb} fused={fused} "
+                      f"defer={defer}")
                 g = gpu_render(sc, bin_size=B, schedule=sched, threads_per_bin=tpb,
-                               persistent_groups=groups, fuse_resolve=fused)
+                               persistent_groups=groups, fuse_resolve=fused, defer_shade=defer)
                 if ref is None:
                     compare(sc, g, o)
                     ref = g
@@ -119,18 +121,22 @@ def test_grid1080_full_frame():
     launch configuration: full-frame comparison with the oracle."""
     _note("grid1080 full frame")
     sc = scenes.grid()
-    g = gpu_render(sc, bin_size=16)
+    g = gpu_render(sc, bin_size=16, schedule="direct_map", threads_per_bin=128, want_bary=False,
+                   defer_shade=True)
     o = oracle.render(sc)
     assert int(g["frag_count"][0]) == 1920 * 1080
     assert (g["primid"] >= 0).all()
     compare(sc, g, o)
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_deferred_micropolygons_small(fused):
-    _note(f"micro small deferred fused={fused}")
+MODES = {"split": {}, "fused": {"fuse_resolve": True}, "defer": {"defer_shade": True}}
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_deferred_micropolygons_small(mode):
+    _note(f"micro small deferred mode={mode}")
     sc = scenes.micro(seed=11, width=256, height=128, num_tris=60000, num_lights=3)
-    g = gpu_render(sc, bin_size=16, fuse_resolve=fused)
+    g = gpu_render(sc, bin_size=16, **MODES[mode])
     o = oracle.render(sc)
     compare(sc, g, o)
     np.testing.assert_allclose(g["gbuf_normal"], o["gbuf_normal"], rtol=RTOL, atol=ATOL)
@@ -144,11 +150,11 @@ def test_deferred_tie_heavy():
     compare(sc, gpu_render(sc, bin_size=32, schedule="dynamic"), oracle.render(sc))
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_textured_views(fused):
-    _note(f"textured instanced views fused={fused}")
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_textured_views(mode):
+    _note(f"textured instanced views mode={mode}")
     sc = scenes.diffgrid(size=96, num_views=3, nx=32, ny=16, tex_size=16)
-    g = gpu_render(sc, bin_size=16, fuse_resolve=fused)
+    g = gpu_render(sc, bin_size=16, **MODES[mode])
     compare(sc, g, oracle.render(sc))
 
 
