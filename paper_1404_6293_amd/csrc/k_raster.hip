@@ -65,11 +65,16 @@ __device__ inline void resolve_fetch(const RasterArgs &a, int32_t s, int64_t ite
         for (int k = 0; k < 3; ++k) r.v[k] = (int32_t)(vbase_scene + (int64_t)G.idx[3 * g + k]);
         return;
     }
-    const TriRec *rp = a.w.rec + (item_base + r.t);
-    r.xy = *reinterpret_cast<const uint4 *>(&rp->X0);
-    r.xy2 = *reinterpret_cast<const uint2 *>(&rp->X2);
-    r.iw[0] = rp->iw0; r.iw[1] = rp->iw1; r.iw[2] = rp->iw2;
-    r.sinv = rp->sinv;
+    const int64_t item = item_base + r.t;
+    const uint4 q0 = reinterpret_cast<const uint4 *>(a.w.rec + item)[0];
+    const uint32_t w4 = a.w.rec[item].xy[4];
+    int32_t X[3], Y[3];
+    unpack_xy(q0.x, q0.y, q0.z, q0.w, w4, X, Y);
+    r.xy = make_uint4((uint32_t)X[0], (uint32_t)Y[0], (uint32_t)X[1], (uint32_t)Y[1]);
+    r.xy2 = make_uint2((uint32_t)X[2], (uint32_t)Y[2]);
+    const float4 iw = a.w.iw[item];
+    r.iw[0] = iw.x; r.iw[1] = iw.y; r.iw[2] = iw.z;
+    r.sinv = signed_inv_area(area2(X, Y));
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.v[k] = (int32_t)(vbase_scene + 3 * (int64_t)r.t + k);
 }
@@ -89,11 +94,8 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
 #pragma unroll
         for (int k = 0; k < 3; ++k) r.iw[k] = __int_as_float(q[k].w);
         // 1 / |2 area| with the sign of the winding, computed exactly as setup does
-        const int64_t A2 = (int64_t)(q[1].x - q[0].x) * (q[2].y - q[0].y) -
-                           (int64_t)(q[2].x - q[0].x) * (q[1].y - q[0].y);
-        const int64_t aa = A2 > 0 ? A2 : -A2;
-        const double inv = 1.0 / (double)aa;
-        r.sinv = A2 > 0 ? inv : -inv;
+        const int32_t X[3] = {q[0].x, q[1].x, q[2].x}, Y[3] = {q[0].y, q[1].y, q[2].y};
+        r.sinv = signed_inv_area(area2(X, Y));
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -222,24 +224,23 @@ struct EdgeTri {
 };
 
 struct RawTri {
-    uint4 q0, q1, q2, q3;   // the 64-byte setup record
+    uint4 q0, q1;   // the 32-byte setup record
 };
 
 __device__ inline void fetch_tri(const Ws &w, int32_t item, RawTri &r) {
-    const TriRec *rp = w.rec + item;
-    r.q0 = reinterpret_cast<const uint4 *>(rp)[0];
-    r.q1 = reinterpret_cast<const uint4 *>(rp)[1];
-    r.q2 = reinterpret_cast<const uint4 *>(rp)[2];
-    r.q3 = reinterpret_cast<const uint4 *>(rp)[3];
+    const uint4 *rp = reinterpret_cast<const uint4 *>(w.rec + item);
+    r.q0 = rp[0];
+    r.q1 = rp[1];
 }
 
 __device__ inline void decode_tri(const RawTri &r, int32_t item, int64_t item_base, int32_t px0,
-                                  int32_t py0, int32_t pw, int32_t ph, EdgeTri &t) {
-    const uint4 q0 = r.q0, q1 = r.q1, q2 = r.q2, q3 = r.q3;
-    const int32_t X[3] = {(int32_t)q0.x, (int32_t)q0.z, (int32_t)q1.x};
-    const int32_t Y[3] = {(int32_t)q0.y, (int32_t)q0.w, (int32_t)q1.y};
-    const double sinv = __hiloint2double((int)q3.w, (int)q3.z);
-    const int sgn = sinv > 0.0 ? 1 : -1;
+                                  int32_t py0, int32_t pw, int32_t ph, int32_t W, int32_t H,
+                                  EdgeTri &t) {
+    int32_t X[3], Y[3];
+    unpack_xy(r.q0.x, r.q0.y, r.q0.z, r.q0.w, r.q1.x, X, Y);
+    const int64_t A2 = area2(X, Y);
+    const double sinv = signed_inv_area(A2);
+    const int sgn = A2 > 0 ? 1 : -1;
     t.own = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -252,15 +253,16 @@ __device__ inline void decode_tri(const RawTri &r, int32_t item, int64_t item_ba
         t.Bc[k] = Bk;
         t.C[k] = (double)(-((int64_t)Ak * X[ka] + (int64_t)Bk * Y[ka]) + own);
     }
-    t.z[0] = __uint_as_float(q1.z);
-    t.z[1] = __uint_as_float(q1.w);
-    t.z[2] = __uint_as_float(q2.x);
+    t.z[0] = __uint_as_float(r.q1.y);
+    t.z[1] = __uint_as_float(r.q1.z);
+    t.z[2] = __uint_as_float(r.q1.w);
     t.inv = sinv > 0.0 ? sinv : -sinv;
-    const uint64_t bb = ((uint64_t)q3.y << 32) | q3.x;
-    t.x0 = max((int32_t)bb_x0(bb), px0);
-    t.y0 = max((int32_t)bb_y0(bb), py0);
-    const int32_t x1 = min((int32_t)bb_x1(bb), px0 + pw - 1);
-    const int32_t y1 = min((int32_t)bb_y1(bb), py0 + ph - 1);
+    int32_t bx0, bx1, by0, by1;
+    sample_bbox(X, Y, W, H, bx0, bx1, by0, by1);
+    t.x0 = max(bx0, px0);
+    t.y0 = max(by0, py0);
+    const int32_t x1 = min(bx1, px0 + pw - 1);
+    const int32_t y1 = min(by1, py0 + ph - 1);
     t.wdt = x1 - t.x0 + 1;
     const int32_t hgt = y1 - t.y0 + 1;
     t.cnt = (t.wdt > 0 && hgt > 0) ? t.wdt * hgt : 0;
@@ -434,7 +436,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     item = a.w.pairs[c0 + lane];
                     fetch_tri(a.w, item, raw);
                 }
-                decode_tri(raw, item, item_base, px0, py0, pw, ph, t);
+                decode_tri(raw, item, item_base, px0, py0, pw, ph, G.W, G.H, t);
             }
             use_pf = false;
             if (c0 == first && b_next >= 0) {

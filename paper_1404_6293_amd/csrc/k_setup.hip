@@ -150,30 +150,19 @@ __device__ inline uint64_t setup_finish(const Geom &G, const Ws &w, int64_t item
     }
     uint64_t bb = kEmptyKey;
     if (ok) {
-        const int64_t A2 = (int64_t)(X[1] - X[0]) * (Y[2] - Y[0]) -
-                           (int64_t)(X[2] - X[0]) * (Y[1] - Y[0]);
-        if (A2 != 0) {
-            const int32_t mnx = min(X[0], min(X[1], X[2])), mxx = max(X[0], max(X[1], X[2]));
-            const int32_t mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
-            // pixel p is sampled at 256 p + 128 (arithmetic shifts floor)
-            const int32_t x0 = max((mnx + 127) >> 8, 0), x1 = min((mxx - 128) >> 8, G.W - 1);
-            const int32_t y0 = max((mny + 127) >> 8, 0), y1 = min((mxy - 128) >> 8, G.H - 1);
-            if (x0 <= x1 && y0 <= y1) {
-                bb = (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) |
-                     ((uint64_t)y1 << 48);
-                TriRec rec;
-                rec.X0 = X[0]; rec.Y0 = Y[0]; rec.X1 = X[1]; rec.Y1 = Y[1];
-                rec.X2 = X[2]; rec.Y2 = Y[2];
-                rec.z0 = z[0]; rec.z1 = z[1]; rec.z2 = z[2];
-                rec.iw0 = iw[0]; rec.iw1 = iw[1]; rec.iw2 = iw[2];
-                rec.bbox = bb;
-                const int64_t a = A2 > 0 ? A2 : -A2;
-                const double inv = 1.0 / (double)a;
-                rec.sinv = A2 > 0 ? inv : -inv;
-                const uint4 *src = reinterpret_cast<const uint4 *>(&rec);
-                uint4 *dst = reinterpret_cast<uint4 *>(w.rec + item);
-                dst[0] = src[0]; dst[1] = src[1]; dst[2] = src[2]; dst[3] = src[3];
-            }
+        const int64_t A2 = area2(X, Y);
+        int32_t x0, x1, y0, y1;
+        sample_bbox(X, Y, G.W, G.H, x0, x1, y0, y1);
+        if (A2 != 0 && x0 <= x1 && y0 <= y1) {
+            bb = (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) |
+                 ((uint64_t)y1 << 48);
+            uint32_t xy[5];
+            pack_xy(X, Y, xy);
+            uint4 *dst = reinterpret_cast<uint4 *>(w.rec + item);
+            dst[0] = make_uint4(xy[0], xy[1], xy[2], xy[3]);
+            dst[1] = make_uint4(xy[4], __float_as_uint(z[0]), __float_as_uint(z[1]),
+                                __float_as_uint(z[2]));
+            if (!G.idx) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
         }
     }
     w.bbox[item] = bb;

@@ -19,6 +19,7 @@ int ilog2(int b) { int l = 0; while ((1 << l) < b) ++l; return l; }
 struct Frame {
     int64_t items = 0;
     int64_t vrecs = 0;     // snapped vertex records (indexed meshes)
+    bool indexed = false;
     int64_t npix = 0;      // S * W * H
     int64_t nbins_scene = 0;
     int64_t nbins_total = 0;
@@ -67,12 +68,13 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
         return PK_ERR_INVALID_ARGUMENT;
     f.items = p->instanced ? (int64_t)m->num_tris * p->num_scenes : m->num_tris;
     if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
+    f.indexed = m->indices != nullptr;
     f.vrecs = m->indices ? (int64_t)m->num_vertices * (p->instanced ? p->num_scenes : 1) : 0;
     return PK_OK;
 }
 
 struct Layout {
-    size_t vtx, rec, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
+    size_t vtx, rec, iw, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
@@ -80,6 +82,7 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     size_t o = 0;
     L.vtx = o;       o = align_up(o + sizeof(VtxRec) * (size_t)f.vrecs);
     L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
+    L.iw = o;        o = align_up(o + sizeof(float4) * (size_t)(f.indexed ? 0 : f.items));
     L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
     // counters and misc words are adjacent so one fill clears both
     L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
@@ -100,6 +103,7 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     Ws w;
     w.vtx = reinterpret_cast<VtxRec *>(b + L.vtx);
     w.rec = reinterpret_cast<TriRec *>(b + L.rec);
+    w.iw = reinterpret_cast<float4 *>(b + L.iw);
     w.bbox = reinterpret_cast<uint64_t *>(b + L.bbox);
     w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
     w.bin_off = reinterpret_cast<int32_t *>(b + L.bin_off);

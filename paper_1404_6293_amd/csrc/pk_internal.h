@@ -20,17 +20,65 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr int kFragSlots = 256;
 constexpr int kMiscWords = 64 + 2 * kFragSlots;
 
-// Per-triangle setup record, 64 bytes so one aligned record is half of a
-// 128-byte cache line and loads as four dwordx4.
+// Per-triangle setup record, 32 bytes (a quarter of a 128-byte cache line,
+// two dwordx4 loads): the six fixed-point screen coordinates X0 Y0 X1 Y1 X2
+// Y2 as 24-bit two's-complement fields packed end to end into xy[0..4]
+// (vertex_stage bounds them by 2^22 in magnitude), then the three NDC depths.
+// The pixel bbox and 1/|A2| are recomputed from the coordinates where they
+// are needed, with the same expressions as setup, so they are the same bits.
 struct __align__(16) TriRec {
-    int32_t X0, Y0, X1, Y1;   // fixed-point screen vertices (8 fractional bits)
-    int32_t X2, Y2;
-    float z0, z1;             // NDC depth per vertex
-    float z2, iw0, iw1, iw2;  // 1/w per vertex
-    uint64_t bbox;            // x0 | x1 << 16 | y0 << 32 | y1 << 48 (inclusive pixels)
-    double sinv;              // sign(A2) / |A2|
+    uint32_t xy[5];
+    float z0, z1, z2;
 };
-static_assert(sizeof(TriRec) == 64, "setup record must stay 64 bytes");
+static_assert(sizeof(TriRec) == 32, "setup record must stay 32 bytes");
+
+__device__ inline void pack_xy(const int32_t X[3], const int32_t Y[3], uint32_t w[5]) {
+    const uint32_t f0 = (uint32_t)X[0] & 0xffffffu, f1 = (uint32_t)Y[0] & 0xffffffu;
+    const uint32_t f2 = (uint32_t)X[1] & 0xffffffu, f3 = (uint32_t)Y[1] & 0xffffffu;
+    const uint32_t f4 = (uint32_t)X[2] & 0xffffffu, f5 = (uint32_t)Y[2] & 0xffffffu;
+    w[0] = f0 | (f1 << 24);
+    w[1] = (f1 >> 8) | (f2 << 16);
+    w[2] = (f2 >> 16) | (f3 << 8);
+    w[3] = f4 | (f5 << 24);
+    w[4] = f5 >> 8;
+}
+
+__device__ inline int32_t sext24(uint32_t v) { return ((int32_t)(v << 8)) >> 8; }
+
+__device__ inline void unpack_xy(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                 uint32_t w4, int32_t X[3], int32_t Y[3]) {
+    X[0] = sext24(w0);
+    Y[0] = sext24((w0 >> 24) | (w1 << 8));
+    X[1] = sext24((w1 >> 16) | (w2 << 16));
+    Y[1] = sext24(w2 >> 8);
+    X[2] = sext24(w3);
+    Y[2] = sext24((w3 >> 24) | (w4 << 8));
+}
+
+// Twice the signed area of the snapped triangle (exact in int64) and the
+// float64 1/|A2| with the sign of A2 (a correctly rounded division).
+__device__ inline int64_t area2(const int32_t X[3], const int32_t Y[3]) {
+    return (int64_t)(X[1] - X[0]) * (Y[2] - Y[0]) - (int64_t)(X[2] - X[0]) * (Y[1] - Y[0]);
+}
+
+__device__ inline double signed_inv_area(int64_t A2) {
+    const int64_t a = A2 > 0 ? A2 : -A2;
+    const double inv = 1.0 / (double)a;
+    return A2 > 0 ? inv : -inv;
+}
+
+// Inclusive pixel bbox of the samples (pixel p is sampled at 256 p + 128) a
+// snapped triangle can cover, clipped to the W x H screen; x0 > x1 or y0 > y1
+// when there is none.  Arithmetic shifts floor.
+__device__ inline void sample_bbox(const int32_t X[3], const int32_t Y[3], int32_t W, int32_t H,
+                                   int32_t &x0, int32_t &x1, int32_t &y0, int32_t &y1) {
+    const int32_t mnx = min(X[0], min(X[1], X[2])), mxx = max(X[0], max(X[1], X[2]));
+    const int32_t mny = min(Y[0], min(Y[1], Y[2])), mxy = max(Y[0], max(Y[1], Y[2]));
+    x0 = max((mnx + 127) >> 8, 0);
+    x1 = min((mxx - 128) >> 8, W - 1);
+    y0 = max((mny + 127) >> 8, 0);
+    y1 = min((mxy - 128) >> 8, H - 1);
+}
 
 // Everything the geometry kernels need about the mesh and the bin grid.
 struct Geom {
@@ -60,6 +108,8 @@ constexpr int32_t kBadVertex = (int32_t)0x80000000;
 struct Ws {
     VtxRec *vtx;               // [S or 1][V] for indexed meshes, else unused
     TriRec *rec;               // [items]
+    float4 *iw;                // [items] 1/w0, 1/w1, 1/w2 (unindexed meshes; indexed
+                               // ones read 1/w from the vertex records)
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]

@@ -127,19 +127,23 @@ def test_workspace_bytes_arithmetic(L):
     assert b0 > 0 and b1 - b0 == 256 and b2 - b1 == 256
     nbins = 7 * 5
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    expect = (al(64 * T) + al(8 * T) + al(4 * nbins) + al(4 * (nbins + 1)) + al(4 * nbins)
-              + al(4 * 576) + al(8 * 100 * 70))
-    assert b0 == expect
-    # an indexed mesh adds one 16-byte snapped record per vertex (per view)
+    # 32-byte setup records, 16 bytes of 1/w per triangle (unindexed only),
+    # 8-byte bboxes, counts, misc words, offsets, cursors, keys
+    common = (al(8 * T) + al(4 * nbins) + al(4 * 576) + al(4 * (nbins + 1)) + al(4 * nbins)
+              + al(8 * 100 * 70))
+    assert b0 == al(32 * T) + al(16 * T) + common
+    # an indexed mesh has one 16-byte snapped record per vertex (per view)
+    # instead of the per-triangle 1/w slice
     mi = _mesh(num_tris=T, num_vertices=600, indices=FAKE)
-    assert L.pk_workspace_bytes(C.byref(p), C.byref(mi), 0) == expect + al(16 * 600)
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(mi), 0) == al(16 * 600) + al(32 * T) + common
     # instanced views multiply the per-triangle and per-vertex slices
     pi = _params(width=100, height=70, bin_size=16, num_scenes=3, instanced=1)
     nb3 = 3 * nbins
-    expect3 = (al(64 * 3 * T) + al(8 * 3 * T) + al(4 * nb3) + al(4 * (nb3 + 1)) + al(4 * nb3)
-               + al(4 * 576) + al(8 * 3 * 100 * 70))
-    assert L.pk_workspace_bytes(C.byref(pi), C.byref(m), 0) == expect3
-    assert L.pk_workspace_bytes(C.byref(pi), C.byref(mi), 0) == expect3 + al(16 * 3 * 600)
+    common3 = (al(8 * 3 * T) + al(4 * nb3) + al(4 * 576) + al(4 * (nb3 + 1)) + al(4 * nb3)
+               + al(8 * 3 * 100 * 70))
+    assert L.pk_workspace_bytes(C.byref(pi), C.byref(m), 0) == al(32 * 3 * T) + al(16 * 3 * T) + common3
+    assert L.pk_workspace_bytes(C.byref(pi), C.byref(mi), 0) == (al(16 * 3 * 600) + al(32 * 3 * T)
+                                                                 + common3)
     assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh(num_tris=-1)), 0) == 0
     assert L.pk_workspace_bytes(C.byref(p), C.byref(m), -5) == 0
     assert L.pk_workspace_bytes(C.byref(p), None, 0) == 0
