@@ -27,13 +27,13 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 WORKLOADS = {
     "grid1080": dict(desc="1920x1080 displaced grid, 1024x512 quads (1,048,576 triangles, "
                           "shared vertices), perspective camera, Gouraud, 16x16 bins",
-                     bin=16, schedule="direct_map", tpb=128, bary=False),
+                     bin=16, schedule="direct_map", tpb=0, bary=False),
     "micro8m": dict(desc="1920x1080, 8,388,608 independent micropolygons (log-normal area "
                          "around 0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
-                    bin=16, schedule="direct_map", tpb=128, bary=False),
+                    bin=16, schedule="direct_map", tpb=0, bary=False),
     "batch256": dict(desc="256 scenes at 256x256, log-uniform 1K-200K random triangles each "
                           "(edge ~ log-normal around 4 px), one batched launch",
-                     bin=16, schedule="direct_map", tpb=128, bary=False),
+                     bin=16, schedule="direct_map", tpb=0, bary=False),
     "tiny64": dict(desc="64x64, 256 random triangles, Gouraud, 8x8 bins", bin=8,
                    schedule="direct_map", tpb=64, bary=False),
 }
@@ -136,7 +136,7 @@ def bench_batched(reps: int = 10) -> dict:
     sc = scenes.batch()
     dev = pk.DeviceScene(sc)
     cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map", "dynamic"),
-                                     threads=(128,), fused=(False,)))
+                                     threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True
     rb = pk.Renderer(dev, cfg)
@@ -180,7 +180,7 @@ def bench_micro(reps: int = 10) -> dict:
     sc = scenes.micro()
     dev = pk.DeviceScene(sc)
     cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map",),
-                                     threads=(128,), fused=(False,)))
+                                     threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True
     r = pk.Renderer(dev, cfg)
@@ -206,7 +206,7 @@ def bench_backward(reps: int = 10) -> dict:
     import torch
     from paper_1404_6293_amd import pk, scenes
     sc = scenes.diffgrid()
-    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=0,
                                         want_bary=True))
     r.render()
     torch.cuda.synchronize()
@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--bin", type=int, default=0)
     ap.add_argument("--schedule", default="")
     ap.add_argument("--tpb", type=int, default=-1)
+    ap.add_argument("--groups", type=int, default=0,
+                    help="persistent workgroups of the bin kernel (0 = library default)")
     ap.add_argument("--bary", action="store_true", help="also save barycentrics")
     ap.add_argument("--fuse-resolve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -279,7 +281,8 @@ def main():
     # the frame's raster/shade step runs as two calls (bin kernel, then the
     # per-pixel pass) so that each kernel is timed on its own
     cfg = pk.RenderConfig(bin_size=B, schedule=sched, threads_per_bin=tpb, count_frags=True,
-                          want_bary=bary, fuse_resolve=fused, defer_shade=not fused)
+                          want_bary=bary, fuse_resolve=fused, defer_shade=not fused,
+                          persistent_groups=args.groups)
     print(f"bench: {args.workload} B={B} {sched} tpb={tpb} bary={bary} "
           f"fused={fused} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
@@ -297,10 +300,20 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
     stream = torch.cuda.current_stream()
+    # headline: K whole frames, no event inside a frame (an event record costs
+    # the queue a few microseconds, which would inflate the frame)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for _ in range(K):
+        r.frame()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert not r.ensure_capacity(), "bin-pair capacity changed during the timed region"
+    # the same K frames again with HIP events around each stage on the launch
+    # stream: per-stage (per-kernel) durations for the roofline
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    torch.cuda.synchronize()
     for k in range(K):
         e = ev[k]
         e[0].record(stream)
@@ -313,8 +326,6 @@ def main():
         r.shade()
         e[4].record(stream)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert not r.ensure_capacity(), "bin-pair capacity changed during the timed region"
     names = ("setup", "assign_bin", "raster", "shade")
     stage = {n: sum(e[i].elapsed_time(e[i + 1]) for e in ev) / K for i, n in enumerate(names)}
     ms = dt * 1e3 / K

@@ -109,10 +109,12 @@ enum {
                                  (Rasterizer and Fragment Shader fused, Sec. 7.2)
                                  instead of in a separate per-pixel pass over the
                                  bins' winning keys; the image is the same */
-    PK_FLAG_DEFER_SHADE = 4   /* pk_raster_shade stops after the depth test and
-                                 leaves every pixel's winning (depth, primitive)
-                                 key in the workspace; pk_shade then resolves and
-                                 shades.  Excludes PK_FLAG_FUSE_RESOLVE. */
+    PK_FLAG_DEFER_SHADE = 4   /* pk_raster_shade stops after the depth test:
+                                 every pixel's winning (depth, primitive) key
+                                 goes to the depth and primid targets when both
+                                 are given (they are then final), else to the
+                                 workspace; pk_shade then resolves and shades.
+                                 Excludes PK_FLAG_FUSE_RESOLVE. */
 };
 
 typedef struct {               /* [host] */
@@ -201,11 +203,13 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
 /* Second half of a frame rendered with PK_FLAG_DEFER_SHADE: the Composite and
  * Fragment Shader stages as their own per-pixel pass (Sec. 7.1 stage list;
  * Sec. 5.2.2 discusses running them fused or apart).  Reads the winning keys
- * that pk_raster_shade left in `ws`, resolves and shades every pixel, and
+ * that pk_raster_shade left (in the depth and primid targets, or in `ws`),
+ * resolves and shades every pixel, and
  * writes every non-NULL target exactly as a pk_raster_shade without the flag
  * would (frag_count is not touched).  `p` must carry PK_FLAG_DEFER_SHADE and
- * equal the parameters of the pk_raster_shade call; `m`, `a` and `ws` are the
- * same.  Arguments are validated as for pk_raster_shade. */
+ * equal the parameters of the pk_raster_shade call; `m`, `a`, `ws` and the
+ * depth and primid targets of `out` (or their absence) are the same.
+ * Arguments are validated as for pk_raster_shade. */
 pk_status pk_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
                    const pk_targets *out, void *stream);
 

@@ -114,13 +114,13 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
 
 template <int SHADE>
 __device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, int py,
-                                      const Resolve &r) {
+                                      const Resolve &r, bool write_dp = true) {
     const Shade &sh = a.sh;
     const int64_t p = ((int64_t)s * a.G.H + py) * a.G.W + px;
     if (r.t == ~0u) {
         if (sh.out_color) reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(0, 0, 0, 0);
-        if (sh.out_depth) sh.out_depth[p] = 1.0f;
-        if (sh.out_primid) sh.out_primid[p] = -1;
+        if (write_dp && sh.out_depth) sh.out_depth[p] = 1.0f;
+        if (write_dp && sh.out_primid) sh.out_primid[p] = -1;
         if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(0, 0);
         if (SHADE == PK_SHADE_DEFERRED) {
             sh.gbuf_n[3 * p] = 0; sh.gbuf_n[3 * p + 1] = 0; sh.gbuf_n[3 * p + 2] = 0;
@@ -203,8 +203,8 @@ __device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, in
     } else if (sh.out_color) {
         reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
     }
-    if (sh.out_depth) sh.out_depth[p] = r.depth;
-    if (sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
+    if (write_dp && sh.out_depth) sh.out_depth[p] = r.depth;
+    if (write_dp && sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
     if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(b1, b2);
 }
 
@@ -343,16 +343,56 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         const int64_t l = lane_in_xcd + i * groups_in_xcd;
         return l < r_len ? r_beg + l : -1;
     };
-    // Software pipeline (DIRECT_MAP): while bin i is processed, the CSR
-    // offsets of bin i+2, the first pair numbers of bin i+1 and, once bin i's
-    // tests are done, their setup records are fetched, so each bin starts
-    // with its first chunk already in registers.
+    // Software pipeline (DIRECT_MAP).  A wave's work is a stream of chunks
+    // (64 consecutive entries of a bin list) in bin order, known in advance.
+    // While chunk n is tested, the setup records of chunk n+1 and the pair
+    // numbers of chunk n+2 are in flight, and the CSR offsets of the bin
+    // after chunk n+2's bin are loaded, so no chunk waits for memory unless a
+    // bin without chunks for this wave is skipped.
     const bool piped = a.schedule == PK_SCHED_DIRECT_MAP;
-    int32_t nx_beg = 0, nx_end = 0;         // offsets of bin i+1
-    int32_t nx_item = -1;                   // bin i+1: this lane's first pair
-    RawTri pf;                              // current bin, first chunk: this lane's
-    int32_t pf_item = -1;                   //   setup record and pair number
-    bool pf_ok = false;
+    const int32_t wbase = __builtin_amdgcn_readfirstlane(wv) * kWave;
+    int64_t n_it = -1;                 // chunk n+1: iteration (bin) of the stream, -1 = none
+    int32_t id_n = -1;                 //   this lane's pair number (-1 = past the list end)
+    RawTri raw_n;                      //   its setup record (in flight)
+    int64_t nn_it = -1;                // chunk n+2: iteration, first entry, list end
+    int32_t nn_c0 = 0, nn_end = 0;
+    int32_t id_nn = -1;                //   this lane's pair number (in flight)
+    int64_t pre_it = -1;               // offsets of bin dm_bin(pre_it) (pre_it = nn_it + 1)
+    int32_t pre_beg = 0, pre_end = 0;
+    auto load_offsets = [&](int64_t it, int64_t &o_it, int32_t &o_beg, int32_t &o_end) {
+        const int64_t b = dm_bin(it);
+        o_it = b >= 0 ? it : -1;
+        o_beg = 0;
+        o_end = 0;
+        if (b >= 0 && !overflow) { o_beg = a.w.bin_off[b]; o_end = a.w.bin_off[b + 1]; }
+    };
+    // move chunk n+2 one chunk on, and start loading its pair numbers
+    auto advance_nn = [&]() {
+        if (nn_it >= 0) {
+            nn_c0 += TPB;
+            while (nn_c0 >= nn_end) {
+                if (pre_it < 0) { nn_it = -1; break; }
+                nn_it = pre_it;
+                nn_c0 = pre_beg + wbase;
+                nn_end = pre_end;
+                load_offsets(nn_it + 1, pre_it, pre_beg, pre_end);
+            }
+        }
+        const int32_t j = nn_c0 + lane;
+        id_nn = (nn_it >= 0 && j < nn_end) ? a.w.pairs[j] : -1;
+    };
+    if (piped) {
+        // prologue: chunk 0 becomes "n+1", chunk 1 "n+2"
+        load_offsets(0, pre_it, pre_beg, pre_end);
+        nn_it = 0;                       // just before the stream's first chunk
+        nn_c0 = -TPB;
+        nn_end = -TPB;
+        advance_nn();
+        n_it = nn_it;
+        id_n = id_nn;
+        if (id_n >= 0) fetch_tri(a.w, id_n, raw_n);
+        advance_nn();
+    }
     // DYNAMIC: current queue (range) and the bins of the last batch taken
     int qx = xcd, q_tried = 0;
     int64_t batch_beg = 0, batch_end = 0;
@@ -402,48 +442,34 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
 
         for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
-        if (!overflow) {
-            if (piped && it > 0) {
-                lbeg = nx_beg;
-                lend = nx_end;
-            } else {
-                lbeg = a.w.bin_off[bin];
-                lend = a.w.bin_off[bin + 1];
-            }
-        }
-        // pipeline stage 1: the next bin's offsets (first use after this bin)
-        int64_t b_next = -1;
-        if (piped && !overflow) {
-            b_next = dm_bin(it + 1);
-            if (b_next >= 0) { nx_beg = a.w.bin_off[b_next]; nx_end = a.w.bin_off[b_next + 1]; }
+        if (!overflow && !piped) {
+            lbeg = a.w.bin_off[bin];
+            lend = a.w.bin_off[bin + 1];
         }
         __syncthreads();
 
         // Process: every wave takes chunks of 64 triangles of the bin list
-        const int32_t first = lbeg + wv * kWave;
-        bool use_pf = pf_ok;
 #pragma unroll 1
-        for (int32_t c0 = first; c0 < lend; c0 += TPB) {
+        for (int32_t c0 = lbeg + wbase;; c0 += TPB) {
+            RawTri raw;
+            int32_t item;
+            if (piped) {
+                if (n_it != it) break;          // the stream has left this bin
+                raw = raw_n;
+                item = id_n;
+                // chunk n+2 becomes n+1: fetch its records; load the next pair numbers
+                n_it = nn_it;
+                id_n = id_nn;
+                if (id_n >= 0) fetch_tri(a.w, id_n, raw_n);
+                advance_nn();
+            } else {
+                if (c0 >= lend) break;
+                item = c0 + lane < lend ? a.w.pairs[c0 + lane] : -1;
+                if (item >= 0) fetch_tri(a.w, item, raw);
+            }
             EdgeTri t;
             t.cnt = 0;
-            if (c0 + lane < lend) {
-                RawTri raw;
-                int32_t item;
-                if (use_pf) {
-                    raw = pf;
-                    item = pf_item;
-                } else {
-                    item = a.w.pairs[c0 + lane];
-                    fetch_tri(a.w, item, raw);
-                }
-                decode_tri(raw, item, item_base, px0, py0, pw, ph, G.W, G.H, t);
-            }
-            use_pf = false;
-            if (c0 == first && b_next >= 0) {
-                // pipeline stage 2: the next bin's first pair numbers
-                const int32_t j = nx_beg + wv * kWave + lane;
-                nx_item = j < nx_end ? a.w.pairs[j] : -1;
-            }
+            if (item >= 0) decode_tri(raw, item, item_base, px0, py0, pw, ph, G.W, G.H, t);
             const int mx = wave_max(t.cnt);
             if (mx <= kLoopMax) {
                 // small triangles: each lane walks its own candidates with
@@ -576,28 +602,27 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        // pipeline stage 3: setup records of the next bin's first chunk
-        pf_ok = false;
-        if (b_next >= 0) {
-            if (first >= lend) {
-                // this wave had no chunk in this bin: stage 2 still to do
-                const int32_t j = nx_beg + wv * kWave + lane;
-                nx_item = j < nx_end ? a.w.pairs[j] : -1;
-            }
-            if (nx_item >= 0) fetch_tri(a.w, nx_item, pf);
-            pf_item = nx_item;
-            pf_ok = true;
-        }
         __syncthreads();
         // EndBin: every fragment of this bin has been tested
         if (SHADE == kKeysOnly) {
-            // hand the tile's winning keys to the per-pixel resolve kernel
-            unsigned long long *keys = a.w.keys + (int64_t)s * G.W * G.H;
+            // hand the tile's winning keys to the per-pixel resolve kernel:
+            // as the final depth and primitive-ID targets when the caller
+            // has both (the two halves of the key), else as keys
+            const int64_t sb = (int64_t)s * G.W * G.H;
+            const bool split = a.sh.out_depth && a.sh.out_primid;
 #pragma unroll 1
             for (int i = tid; i < NPIX; i += TPB) {
                 const int lx = i % B, ly = i / B;
-                if (lx < pw && ly < ph)
-                    keys[(int64_t)(py0 + ly) * G.W + px0 + lx] = s_key[i];
+                if (lx < pw && ly < ph) {
+                    const int64_t p = sb + (int64_t)(py0 + ly) * G.W + px0 + lx;
+                    const unsigned long long k = s_key[i];
+                    if (split) {
+                        a.sh.out_depth[p] = k == kEmptyKey ? 1.0f : __uint_as_float((uint32_t)(k >> 32));
+                        a.sh.out_primid[p] = k == kEmptyKey ? -1 : (int32_t)(uint32_t)k;
+                    } else {
+                        a.w.keys[p] = k;
+                    }
+                }
             }
         } else {
             // resolve in place, two pixels per thread at a time so their
@@ -695,10 +720,20 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
     const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
+    const bool split = a.sh.out_depth && a.sh.out_primid;
+    unsigned long long key;
+    if (split) {
+        // the bin kernel already wrote the depth and primitive-ID targets
+        const int32_t prim = a.sh.out_primid[p];
+        key = prim < 0 ? kEmptyKey
+                       : ((unsigned long long)__float_as_uint(a.sh.out_depth[p]) << 32) | (uint32_t)prim;
+    } else {
+        key = a.w.keys[p];
+    }
     Resolve r;
-    resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, a.w.keys[p], r);
+    resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, key, r);
     resolve_attribs<SHADE>(a, s, r);
-    resolve_finish<SHADE>(a, s, px, py, r);
+    resolve_finish<SHADE>(a, s, px, py, r, !split);
 }
 
 template <int TPB, int SHADE>

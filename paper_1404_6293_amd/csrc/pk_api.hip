@@ -217,10 +217,12 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     Shade sh;
     if ((st = shade_args(p, a, out, f, sh)) != PK_OK) return st;
     const Geom G = geom(p, m, f);
+    // defaults: one wave per bin up to 16x16 bins (no cross-wave barriers),
+    // and 16 resident waves per compute unit for the persistent schedules
     int tpb = p->threads_per_bin;
-    if (tpb == 0) tpb = p->bin_size <= 8 ? 64 : 256;
+    if (tpb == 0) tpb = p->bin_size <= 16 ? 64 : 256;
     int groups = p->persistent_groups;
-    if (groups == 0) groups = 256 * 8;
+    if (groups == 0) groups = 256 * 16 * kWave / tpb;
     const RasterMode mode = (p->flags & PK_FLAG_FUSE_RESOLVE) ? kRasterFused
                             : (p->flags & PK_FLAG_DEFER_SHADE) ? kRasterKeysOnly
                                                                : kRasterSplit;

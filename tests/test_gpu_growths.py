@@ -140,7 +140,7 @@ def test_micro8m_full_frame_deferred():
     import torch
     _note("micro8m full frame")
     sc = scenes.micro()
-    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=0,
                                         count_frags=True, want_bary=False))
     out = r.render()
     torch.cuda.synchronize()
@@ -158,7 +158,7 @@ def test_batch256_sampled_scenes_and_plain_equivalence():
     import torch
     _note("batch256 full")
     sc = scenes.batch()
-    rb = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=128,
+    rb = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=0,
                                          want_bary=False))
     ob = rb.render()
     torch.cuda.synchronize()

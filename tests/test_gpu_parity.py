@@ -121,7 +121,7 @@ def test_grid1080_full_frame():
     launch configuration: full-frame comparison with the oracle."""
     _note("grid1080 full frame")
     sc = scenes.grid()
-    g = gpu_render(sc, bin_size=16, schedule="direct_map", threads_per_bin=128, want_bary=False,
+    g = gpu_render(sc, bin_size=16, schedule="direct_map", threads_per_bin=0, want_bary=False,
                    defer_shade=True)
     o = oracle.render(sc)
     assert int(g["frag_count"][0]) == 1920 * 1080
@@ -248,3 +248,21 @@ def test_backward_matches_oracle_gradient():
     eps = 2.0 ** -24
     assert (np.abs(gv.cpu().numpy() - ov) <= 1e-4 * np.abs(ov) + n * eps * av + 1e-7).all()
     assert (np.abs(gt.cpu().numpy() - ot) <= 1e-4 * np.abs(ot) + n * eps * at + 1e-7).all()
+
+
+@pytest.mark.parametrize("drop", ["depth", "primid"])
+def test_defer_shade_keys_in_workspace(drop):
+    """Without both the depth and primid targets the deferred pass hands the
+    keys over in the workspace; the remaining targets are unchanged."""
+    import torch
+    _note(f"defer shade without {drop}")
+    sc = scenes.tiny(seed=21, width=150, height=90, num_tris=700)
+    ref = gpu_render(sc, bin_size=16, defer_shade=True)
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, defer_shade=True))
+    setattr(r.targets, drop, None)
+    r.render()
+    torch.cuda.synchronize()
+    for k in ("color", "depth", "primid", "bary"):
+        if k == drop:
+            continue
+        assert (getattr(r, "out_" + k).cpu().numpy() == ref[k]).all(), k
