@@ -68,18 +68,49 @@ def bin_kernel_algorithmic_bytes(sc, npairs: int) -> int:
 
 
 def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
-    """Algorithmic bytes of the per-pixel resolve + shade pass: the 8-byte
-    key of every pixel read once, every output pixel written once (colour
-    16 B, depth 4 B, primid 4 B, bary 8 B when saved; for deferred the
-    G-buffer 24 B instead of the colour), and the attributes of the visible
-    triangle gathered once per covered pixel (3 vertex indices 12 B when
-    indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for deferred)."""
+    """Algorithmic bytes of the per-pixel resolve + shade pass (k_resolve):
+    every pixel's depth and primitive ID read once (8 B, written by the bin
+    kernel), the colour written once (16 B; for deferred the G-buffer 24 B
+    instead), the barycentrics (8 B) when saved, and the attributes of the
+    visible triangle gathered once per covered pixel (3 vertex indices 12 B
+    when indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for
+    deferred)."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
     npix = S * sc.width * sc.height
     deferred = getattr(sc, "shading", "gouraud") == "deferred"
-    per_px = 8 + (24 if deferred else 16) + 4 + 4 + (8 if want_bary else 0)
+    per_px = 8 + (24 if deferred else 16) + (8 if want_bary else 0)
     per_cov = (12 if sc.idx is not None else 0) + 36 + (36 if deferred else 0)
     return per_px * npix + per_cov * covered_px
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the HIP sources and the public header, so that a profiled
+    traffic figure is only reported for the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1404_6293_amd", "csrc")
+    for path in sorted(os.listdir(csrc)) + ["../../include/pk.h"]:
+        with open(os.path.join(csrc, path), "rb") as f:
+            h.update(os.path.basename(path).encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    of `workload` (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when there is none or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernels.md")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    for line in open(path):
+        # "traffic <kernel> <bytes> bytes/launch sources <sha256>"
+        parts = line.split()
+        if (len(parts) == 6 and parts[0] == "traffic" and parts[1] == kernel
+                and parts[5] == want):
+            return int(parts[2])
+    return None
 
 
 def cpu_baseline(sc, budget_s: float = 12.0):
@@ -345,7 +376,8 @@ def main():
     achieved = alg / (t_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
+                "traffic": None if fused else profiled_traffic(args.workload, "k_raster"),
+                "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
     if not fused:
         a2 = alg_px / (stage["shade"] * 1e-3) / 1e9
         roofline["shade_pass"] = {"kernel": "k_resolve" + (" + k_deferred" if sc.shading == "deferred" else ""),
