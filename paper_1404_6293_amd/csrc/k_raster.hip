@@ -407,8 +407,15 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     while (q_tried < kXcd) {
                         const int64_t qb = qx * q + min<int64_t>(qx, rem);
                         const int64_t ql = q + (qx < rem ? 1 : 0);
-                        const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)a.dyn_batch);
-                        if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + a.dyn_batch, ql); break; }
+                        // look before popping: once a queue is drained every
+                        // workgroup would otherwise add to its head, and
+                        // read-modify-writes on one address serialize
+                        const uint32_t seen = __hip_atomic_load(&a.w.misc[8 + qx], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                        if ((int64_t)seen < ql) {
+                            const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)a.dyn_batch);
+                            if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + a.dyn_batch, ql); break; }
+                        }
                         qx = (qx + 1) % kXcd;
                         ++q_tried;
                     }

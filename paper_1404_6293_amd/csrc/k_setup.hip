@@ -8,6 +8,8 @@
 //   k_scan     exclusive prefix sum of the per-bin counts into CSR offsets.
 //   k_scatter  one thread per triangle: append the triangle to each of its
 //              bins' lists at a slot taken from the bin's cursor.
+#include <climits>
+
 #include "pk_internal.h"
 
 #pragma clang fp contract(off)
@@ -37,7 +39,8 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 constexpr int kGroupThreads = 256;
 constexpr int kItemsPerThread = 4;
 constexpr int kGroupItems = kGroupThreads * kItemsPerThread;
-constexpr int kHist = 8192;
+// (with the 8 reduction words, one workgroup takes exactly 32 KiB of LDS: 5 per CU)
+constexpr int kHist = 8192 - 2 * kGroupThreads / 64;
 
 __device__ inline int32_t scene_of(const Geom &G, int64_t item) {
     if (G.S == 1) return 0;
@@ -184,54 +187,97 @@ __device__ inline BinRect bin_rect(const Geom &G, uint64_t bb) {
     return r;
 }
 
+// Range [lo, hi] of LDS window indices ((scene - s_lo) * bins per scene +
+// bin) that a triangle's bin rectangle touches; lo > hi when it touches none.
+__device__ inline void window_span(const Geom &G, const BinRect &br, int32_t s, int32_t s_lo,
+                                   int &lo, int &hi) {
+    if (br.nb == 0) { lo = INT_MAX; hi = INT_MIN; return; }
+    const int base = (s - s_lo) * G.nbins_scene;
+    const int rows = br.nb / br.nbx_t;
+    lo = base + br.by0 * G.nbx + br.bx0;
+    hi = base + (br.by0 + rows - 1) * G.nbx + br.bx0 + br.nbx_t - 1;
+}
+
+// Smallest lo and largest hi over the workgroup.  Contains barriers: call
+// from uniform control flow.  s_red holds 2 ints per wave.
+__device__ inline void group_span(int lo, int hi, int *s_red, int &glo, int &ghi) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        lo = min(lo, __shfl_xor(lo, d, kWave));
+        hi = max(hi, __shfl_xor(hi, d, kWave));
+    }
+    const int wid = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) { s_red[2 * wid] = lo; s_red[2 * wid + 1] = hi; }
+    __syncthreads();
+    glo = INT_MAX;
+    ghi = INT_MIN;
+#pragma unroll
+    for (int i = 0; i < kGroupThreads / kWave; ++i) {
+        glo = min(glo, s_red[2 * i]);
+        ghi = max(ghi, s_red[2 * i + 1]);
+    }
+}
+
 __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
     __shared__ uint32_t s_hist[kHist];
+    __shared__ int s_red[2 * kGroupThreads / kWave];
     const int tid = threadIdx.x;
     const int64_t first = blockIdx.x * (int64_t)kGroupItems;
     int32_t s_lo;
     int64_t nwin;
     const bool lds = group_window(G, first, s_lo, nwin);
-    if (lds) {
-        for (int i = tid; i < nwin; i += kGroupThreads) s_hist[i] = 0;
-        __syncthreads();
-    }
     TriIn tin[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k)
         setup_indices(G, first + k * kGroupThreads + tid, tin[k]);
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) setup_fetch(G, w, tin[k]);
-    // (unrolled: tin must stay in registers)
+    // (unrolled: tin and the rectangles must stay in registers)
+    BinRect br[kItemsPerThread];
+    int lo = INT_MAX, hi = INT_MIN;
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
         const int64_t item = first + k * kGroupThreads + tid;
+        br[k] = bin_rect(G, setup_finish(G, w, item, tin[k]));
+        int l, h;
+        window_span(G, br[k], tin[k].s, s_lo, l, h);
+        lo = min(lo, l);
+        hi = max(hi, h);
+    }
+    // AssignBin counts of the screen-space stage.  In LDS, only over the
+    // span of bins this workgroup touches (a row strip for coherent meshes)
+    int glo = 0, ghi = -1;
+    if (lds) {
+        group_span(lo, hi, s_red, glo, ghi);
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i] = 0;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
         const int32_t s = tin[k].s;
-        const uint64_t bb = setup_finish(G, w, item, tin[k]);
-        const BinRect br = bin_rect(G, bb);
-        // AssignBin counts of the screen-space stage
         if (lds) {
             // LDS atomics are cheap enough per lane
             uint32_t *h = s_hist + (s - s_lo) * G.nbins_scene;
-            int cx = br.bx0, cy = br.by0;
-            for (int r = 0; r < br.nb; ++r) {
+            int cx = br[k].bx0, cy = br[k].by0;
+            for (int r = 0; r < br[k].nb; ++r) {
                 atomicAdd(h + cy * G.nbx + cx, 1u);
-                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
+                if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
         } else {
             // one round per bin of the largest bin rectangle in the wave
-            const int rounds = wave_max(br.nb);
+            const int rounds = wave_max(br[k].nb);
             const int base = s * G.nbins_scene;
-            int cx = br.bx0, cy = br.by0;
+            int cx = br[k].bx0, cy = br[k].by0;
             for (int r = 0; r < rounds; ++r) {
-                agg_count(w.bin_count, r < br.nb ? base + cy * G.nbx + cx : -1);
-                if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
+                agg_count(w.bin_count, r < br[k].nb ? base + cy * G.nbx + cx : -1);
+                if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
         }
     }
     if (lds) {
         __syncthreads();
         uint32_t *dst = w.bin_count + (int64_t)s_lo * G.nbins_scene;
-        for (int i = tid; i < nwin; i += kGroupThreads) {
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) {
             const uint32_t c = s_hist[i];
             if (c) atomicAdd(dst + i, c);
         }
@@ -332,6 +378,7 @@ hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStr
 
 __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
     __shared__ uint32_t s_hist[kHist];
+    __shared__ int s_red[2 * kGroupThreads / kWave];
     if (w.misc[1]) return;   // pair capacity exceeded: lists stay unwritten
     const int tid = threadIdx.x;
     const int64_t first = blockIdx.x * (int64_t)kGroupItems;
@@ -347,7 +394,18 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         sc[k] = bb[k] != kEmptyKey ? scene_of(G, item) : 0;
     }
     if (lds) {
-        for (int i = tid; i < nwin; i += kGroupThreads) s_hist[i] = 0;
+        // only the span of bins this workgroup touches
+        int lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < kItemsPerThread; ++k) {
+            int l, h;
+            window_span(G, bin_rect(G, bb[k]), sc[k], s_lo, l, h);
+            lo = min(lo, l);
+            hi = max(hi, h);
+        }
+        int glo, ghi;
+        group_span(lo, hi, s_red, glo, ghi);
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i] = 0;
         __syncthreads();
         // count this workgroup's pairs per bin
 #pragma unroll
@@ -363,7 +421,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         __syncthreads();
         // reserve one contiguous range per touched bin
         int32_t *cur = w.cursor + (int64_t)s_lo * G.nbins_scene;
-        for (int i = tid; i < nwin; i += kGroupThreads) {
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) {
             const uint32_t c = s_hist[i];
             if (c) s_hist[i] = (uint32_t)atomicAdd(cur + i, (int32_t)c);
         }
