@@ -291,12 +291,15 @@ __device__ inline bool depth_key(double e0, double e1, double e2, int own, doubl
 // for the per-pixel resolve kernel instead of resolving in place
 constexpr int kKeysOnly = -1;
 
-// word planes of the per-wave staging area (C and inv as float64 hi/lo words)
-enum : int {
-    kStA = 0, kStB = 3, kStClo = 6, kStChi = 9, kStZ = 12, kStInvLo = 15, kStInvHi = 16,
-    kStOrg = 17, kStWid = 18, kStMag = 19, kStPrim = 20, kStStart = 21, kStMark = 22,
-    kStFields = 23
-};
+// Per-triangle staging record of the expansion mode, in 32-bit words, read
+// with 128-bit LDS loads: [0..3] first candidate, width | own << 8, divide
+// magic, origin x | y << 16; [4..9] 256 A_k as float64 (the edge step per
+// pixel in x); [10..15] 256 B_k (in y); [16..21] the edge values e_k at the
+// origin pixel centre (float64, own bias included); [22..23] 1/|A2|;
+// [24..26] z_k; [27] primitive.  With a stride of 28 words the 128-bit
+// reads of up to eight consecutive triangles' records touch disjoint LDS
+// banks, and a one-wave workgroup with 16x16 bins fits 16 per CU.
+constexpr int kStRec = 28;
 // Start marks of the expansion mode carry a block tag in their upper bits so
 // that the plane never needs clearing; kNoTag is never a live tag.
 constexpr uint32_t kTagShift = 6, kNoTag = 0xffffffffu >> kTagShift;
@@ -308,10 +311,10 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     constexpr int NW = TPB / kWave;
     constexpr int kLoopMax = 12;   // wave-max candidates for the per-lane loop
     __shared__ unsigned long long s_key[NPIX];
-    // per-wave staging for the expansion mode (large triangles): one word
-    // plane per field so every field sits at a constant offset from the
-    // wave's base and the lane's slot
-    __shared__ uint32_t s_st[NW][kStFields][kWave];
+    // per-wave staging for the expansion mode (large triangles): one record
+    // per lane's triangle, and a plane of start marks
+    __shared__ __align__(16) uint32_t s_rec[NW][kWave * kStRec];
+    __shared__ uint32_t s_mark[NW][kWave];
     __shared__ int64_t s_bin, s_bin_end;
     __shared__ unsigned long long s_frag[NW];
 
@@ -322,7 +325,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const bool overflow = a.w.misc[1] != 0;   // pair capacity exceeded: no lists
     // expansion-mode start marks: no live tag yet
     uint32_t tag = 0;
-    s_st[wv][kStMark][lane] = 0xffffffffu;
+    s_mark[wv][lane] = 0xffffffffu;
     // Bins are split into kXcd contiguous ranges; workgroup w works in range
     // w mod kXcd (workgroups are dealt to the dies round-robin), so each die's
     // L2 sees a compact screen region.  The mapping is a bijection whatever
@@ -526,28 +529,43 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 }
                 const int start = total - t.cnt;
                 total = __shfl(total, kWave - 1, kWave);
-                uint32_t (*st)[kWave] = s_st[wv];
+                uint32_t *rec = s_rec[wv];
+                uint32_t *mark = s_mark[wv];
+                {
+                    // stage this lane's triangle
+                    uint32_t *r = rec + lane * kStRec;
+                    // m = ceil(2^18 / width) makes (c * m) >> 18 an exact divide
+                    // for candidate numbers c < 2^12 (c * (m * width - 2^18) <
+                    // 2^12 * width <= 2^18), all in full-rate 24-bit multiplies
+                    const uint32_t mag = ((1u << 18) + (uint32_t)max(t.wdt, 1) - 1u) / (uint32_t)max(t.wdt, 1);
+                    *reinterpret_cast<uint4 *>(r) =
+                        make_uint4((uint32_t)start, (uint32_t)(max(t.wdt, 1) | (t.own << 8)), mag,
+                                   (uint32_t)(t.x0 | (t.y0 << 16)));
+                    const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
+                    double st[12];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    st[kStA + k][lane] = (uint32_t)t.A[k];
-                    st[kStB + k][lane] = (uint32_t)t.Bc[k];
-                    st[kStClo + k][lane] = (uint32_t)__double2loint(t.C[k]);
-                    st[kStChi + k][lane] = (uint32_t)__double2hiint(t.C[k]);
-                    st[kStZ + k][lane] = __float_as_uint(t.z[k]);
+                    for (int k = 0; k < 3; ++k) {
+                        st[k] = (double)(256 * t.A[k]);
+                        st[3 + k] = (double)(256 * t.Bc[k]);
+                        // exact: integers below 2^53
+                        st[6 + k] = (double)t.A[k] * Px + (double)t.Bc[k] * Py + t.C[k];
+                    }
+                    st[9] = t.inv;
+                    st[10] = __hiloint2double((int)__float_as_uint(t.z[1]), (int)__float_as_uint(t.z[0]));
+                    st[11] = __hiloint2double((int)t.prim, (int)__float_as_uint(t.z[2]));
+                    double2 *r2 = reinterpret_cast<double2 *>(r + 4);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) r2[k] = make_double2(st[2 * k], st[2 * k + 1]);
                 }
-                st[kStInvLo][lane] = (uint32_t)__double2loint(t.inv);
-                st[kStInvHi][lane] = (uint32_t)__double2hiint(t.inv);
-                st[kStOrg][lane] = (uint32_t)(t.x0 | (t.y0 << 16));
-                st[kStWid][lane] = (uint32_t)(max(t.wdt, 1) | (t.own << 8));
-                // ceil(2^32 / width) makes umulhi an exact divide for the
-                // candidate counts of one bin (< 2^12); width 1 needs no divide
-                st[kStMag][lane] = t.wdt > 1 ? 0xffffffffu / (uint32_t)t.wdt + 1u : 0u;
-                st[kStPrim][lane] = (uint32_t)t.prim;
-                st[kStStart][lane] = (uint32_t)start;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 int carry = 0;   // triangle of the last candidate of the previous block
+                if (tag + (uint32_t)(total / kWave + 1) >= kNoTag) {
+                    // (never in practice) recycle the tags before they run out
+                    mark[lane] = 0xffffffffu;
+                    tag = 0;
+                }
 #pragma unroll 1
                 for (int b = 0; b < total; b += kWave) {
                     // Which triangle owns candidate j = b + lane: the last non-empty
@@ -557,16 +575,12 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     // mark at or below j, a lane shuffle fetches it, and a block
                     // position before any mark belongs to the previous block's
                     // last triangle.
-                    if (tag == kNoTag - 1) {           // (never in practice) recycle tags
-                        st[kStMark][lane] = 0xffffffffu;
-                        tag = 0;
-                    }
                     if (t.cnt > 0 && start >= b && start < b + kWave)
-                        st[kStMark][start - b] = (tag << kTagShift) | (uint32_t)lane;
+                        mark[start - b] = (tag << kTagShift) | (uint32_t)lane;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    const uint32_t mk = st[kStMark][lane];
+                    const uint32_t mk = mark[lane];
                     const uint64_t live = __ballot((mk >> kTagShift) == tag);
                     const uint64_t upto = live & ((2ull << lane) - 1ull);
                     const int from = upto ? 63 - __clzll(upto) : 0;
@@ -576,30 +590,35 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     ++tag;
                     const int j = b + lane;
                     if (j >= total) continue;
-                    const uint32_t local = (uint32_t)(j - (int)st[kStStart][lo]);
-                    const int32_t wi = (int32_t)st[kStWid][lo];
+                    const uint32_t *r = rec + __umul24((uint32_t)lo, (uint32_t)kStRec);
+                    const uint4 hd = *reinterpret_cast<const uint4 *>(r);
+                    const double2 *r2 = reinterpret_cast<const double2 *>(r + 4);
+                    const double2 a01 = r2[0], a2b0 = r2[1], b12 = r2[2];
+                    const double2 e01 = r2[3], e2i = r2[4];
+                    const uint32_t local = (uint32_t)j - hd.x;
+                    const int32_t wi = (int32_t)hd.y;
                     const uint32_t wdt = (uint32_t)(wi & 0xff);
-                    const uint32_t mag = st[kStMag][lo];
-                    const uint32_t row = mag ? __umulhi(local, mag) : local;
-                    const uint32_t col = local - row * wdt;
-                    const int32_t org = (int32_t)st[kStOrg][lo];
-                    const int32_t px = (org & 0xffff) + (int32_t)col;
-                    const int32_t py = (org >> 16) + (int32_t)row;
-                    const double Px = (double)(256 * px + 128), Py = (double)(256 * py + 128);
-                    double e[3];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const double Ck = __hiloint2double((int)st[kStChi + k][lo], (int)st[kStClo + k][lo]);
-                        e[k] = (double)(int32_t)st[kStA + k][lo] * Px +
-                               (double)(int32_t)st[kStB + k][lo] * Py + Ck;
-                    }
-                    if (e[0] > 0.0 && e[1] > 0.0 && e[2] > 0.0) {
+                    const uint32_t row = __umul24(local, hd.z) >> 18;
+                    const uint32_t col = local - __umul24(row, wdt);
+                    const double dc = (double)col, dr = (double)row;
+                    // e_k at (col, row) from the origin value and the steps:
+                    // every product and sum is an integer below 2^53, so the
+                    // fused and unfused forms are the same exact value
+                    const double e0 = fma(dr, a2b0.y, fma(dc, a01.x, e01.x));
+                    const double e1 = fma(dr, b12.x, fma(dc, a01.y, e01.y));
+                    const double e2 = fma(dr, b12.y, fma(dc, a2b0.x, e2i.x));
+                    if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
                         ++frags;
+                        const double2 zz = r2[5];
                         unsigned long long key;
-                        const double inv = __hiloint2double((int)st[kStInvHi][lo], (int)st[kStInvLo][lo]);
-                        if (depth_key(e[0], e[1], e[2], wi >> 8, inv, __uint_as_float(st[kStZ][lo]),
-                                      __uint_as_float(st[kStZ + 1][lo]), __uint_as_float(st[kStZ + 2][lo]),
-                                      st[kStPrim][lo], key))
+                        const int32_t org = (int32_t)hd.w;
+                        const int32_t px = (org & 0xffff) + (int32_t)col;
+                        const int32_t py = (org >> 16) + (int32_t)row;
+                        if (depth_key(e0, e1, e2, wi >> 8, e2i.y,
+                                      __uint_as_float((uint32_t)__double2loint(zz.x)),
+                                      __uint_as_float((uint32_t)__double2hiint(zz.x)),
+                                      __uint_as_float((uint32_t)__double2loint(zz.y)),
+                                      (uint32_t)__double2hiint(zz.y), key))
                             atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
                     }
                 }
@@ -707,11 +726,18 @@ __global__ __launch_bounds__(kFragSlots) void k_raster_epilogue(uint32_t *misc,
 // workgroup w takes a tile from range w mod kXcd, so a die resolves the same
 // screen band whose triangles its bin kernel just read into its L2.
 constexpr int kResW = 64, kResH = 4;
+// Pixels per thread: each thread resolves kResPPT pixels of one column
+// (kResH rows apart) phase by phase, so that the dependent gathers of all of
+// them are in flight together.  One is fastest on the grid and batched
+// workloads (measured 25.2 / 27.8 / 33.0 us at 1 / 2 / 4 on the 1080p grid):
+// the gathers are bound by address processing, not by latency.
+constexpr int kResPPT = 1;
+constexpr int kResRows = kResH * kResPPT;   // rows of a tile
 
 template <int SHADE>
 __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const Geom &G = a.G;
-    const int ntx = (G.W + kResW - 1) / kResW, nty = (G.H + kResH - 1) / kResH;
+    const int ntx = (G.W + kResW - 1) / kResW, nty = (G.H + kResRows - 1) / kResRows;
     const int64_t per_scene = (int64_t)ntx * nty;
     const int64_t ntiles = per_scene * G.S;
     const int64_t q = ntiles / kXcd, rem = ntiles % kXcd;
@@ -722,25 +748,37 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const uint32_t ts = tile - (uint32_t)s * (uint32_t)per_scene;
     const int ty = (int)(ts / (uint32_t)ntx), tx = (int)(ts - (uint32_t)ty * (uint32_t)ntx);
     const int px = tx * kResW + (int)(threadIdx.x % kResW);
-    const int py = ty * kResH + (int)(threadIdx.x / kResW);
-    if (px >= G.W || py >= G.H) return;
+    const int py0 = ty * kResRows + (int)(threadIdx.x / kResW);
+    if (px >= G.W || py0 >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
-    const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
     const bool split = a.sh.out_depth && a.sh.out_primid;
-    unsigned long long key;
-    if (split) {
-        // the bin kernel already wrote the depth and primitive-ID targets
-        const int32_t prim = a.sh.out_primid[p];
-        key = prim < 0 ? kEmptyKey
-                       : ((unsigned long long)__float_as_uint(a.sh.out_depth[p]) << 32) | (uint32_t)prim;
-    } else {
-        key = a.w.keys[p];
+    Resolve r[kResPPT];
+    bool on[kResPPT];
+#pragma unroll
+    for (int k = 0; k < kResPPT; ++k) {
+        const int py = py0 + k * kResH;
+        on[k] = py < G.H;
+        if (!on[k]) continue;
+        const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
+        unsigned long long key;
+        if (split) {
+            // the bin kernel already wrote the depth and primitive-ID targets
+            const int32_t prim = a.sh.out_primid[p];
+            key = prim < 0 ? kEmptyKey
+                           : ((unsigned long long)__float_as_uint(a.sh.out_depth[p]) << 32) |
+                                 (uint32_t)prim;
+        } else {
+            key = a.w.keys[p];
+        }
+        resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, key, r[k]);
     }
-    Resolve r;
-    resolve_fetch<SHADE>(a, s, item_base, vbase, px, py, key, r);
-    resolve_attribs<SHADE>(a, s, r);
-    resolve_finish<SHADE>(a, s, px, py, r, !split);
+#pragma unroll
+    for (int k = 0; k < kResPPT; ++k)
+        if (on[k]) resolve_attribs<SHADE>(a, s, r[k]);
+#pragma unroll
+    for (int k = 0; k < kResPPT; ++k)
+        if (on[k]) resolve_finish<SHADE>(a, s, px, py0 + k * kResH, r[k], !split);
 }
 
 template <int TPB, int SHADE>
@@ -770,7 +808,7 @@ static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
     // one workgroup per tile; the tile count is a multiple of nothing in
     // particular, so ranges differ by at most one tile between dies
     const int64_t ntiles = (int64_t)((a.G.W + kResW - 1) / kResW) *
-                           ((a.G.H + kResH - 1) / kResH) * a.G.S;
+                           ((a.G.H + kResRows - 1) / kResRows) * a.G.S;
     hipLaunchKernelGGL((k_resolve<SHADE>), dim3((unsigned)ntiles), dim3(kResW * kResH), 0, st, a);
     return hipGetLastError();
 }

@@ -464,4 +464,14 @@ hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st) {
     return hipGetLastError();
 }
 
+// (A variant that folded the prefix sum into the scatter, every workgroup
+// scanning all counts with each thread owning consecutive bins, measured 2x
+// slower on the 1080p grid: the per-thread runs make the count loads
+// uncoalesced.  The one-workgroup scan stays.)
+hipError_t launch_assign(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st) {
+    hipError_t e = launch_scan(G, w, pairs_needed, st);
+    if (e == hipSuccess) e = launch_scatter(G, w, st);
+    return e;
+}
+
 }  // namespace pk

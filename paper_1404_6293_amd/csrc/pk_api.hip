@@ -84,11 +84,11 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
     L.iw = o;        o = align_up(o + sizeof(float4) * (size_t)(f.indexed ? 0 : f.items));
     L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
-    // counters and misc words are adjacent so one fill clears both
+    // counters, cursors and misc words are adjacent so one clear covers them
     L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
+    L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
-    L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
     L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix);
     L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
     L.total = o;
@@ -202,9 +202,7 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
         return PK_ERR_INVALID_ARGUMENT;
     const Geom G = geom(p, m, f);
     const Ws w = carve(ws, f, pair_capacity);
-    hipError_t e = launch_scan(G, w, pairs_needed, (hipStream_t)stream);
-    if (e == hipSuccess) e = launch_scatter(G, w, (hipStream_t)stream);
-    return hip_status(e);
+    return hip_status(launch_assign(G, w, pairs_needed, (hipStream_t)stream));
 }
 
 pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,

@@ -113,7 +113,8 @@ struct Ws {
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
-    int32_t *cursor;           // [nbins_total]
+    int32_t *cursor;           // [nbins_total], between bin_count and misc: next
+                               // free slot of each bin (set by the scan)
     uint32_t *misc;            // [kMiscWords], right after bin_count: [1] pair
                                // overflow flag, [8..15] DYNAMIC queue heads,
                                // [64..) kFragSlots 64-bit fragment partial sums;
@@ -313,6 +314,7 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st);
 hipError_t launch_scan(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
 hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st);
+hipError_t launch_assign(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
 // What a pk_raster_shade call launches after the bin kernel's depth test.
 enum RasterMode : int {
     kRasterSplit = 0,      // keys to the workspace, then the per-pixel resolve pass
