@@ -229,6 +229,56 @@ def bench_micro(reps: int = 10) -> dict:
             "gfrags_per_s": round(frags / ms / 1e6, 3)}
 
 
+def measured_stream_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:
+    """GB/s of a plain device-to-device copy of `mib` MiB (read + write bytes
+    over time), buffers far larger than the 256 MB MALL: the achievable HBM
+    stream rate beside the 8 TB/s spec."""
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    ms = _median_ms(torch, lambda: b.copy_(a), reps)
+    del a, b
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
+def plain_scatter_rate(torch, r, sc, reps: int = 3) -> float:
+    """Rate (G/s) of a plain float32 atomic scatter (torch index_add_) over the
+    same addresses as the textured backward: 3 vertices x 3 channels of the
+    winning triangle and 4 bilinear taps x 3 channels of the texture per
+    covered pixel.  The reference rate for the backward's atomics."""
+    prim = r.out_primid.reshape(-1)
+    cov = prim >= 0
+    t = prim[cov].long()
+    V = sc.pos.shape[1]
+    idx = torch.as_tensor(sc.idx, device="cuda").long().reshape(-1, 3)
+    tri = idx[t]                                     # [N, 3] vertex numbers
+    parts = [tri[:, k] + ch * V for ch in range(3) for k in range(3)]
+    bary = r.out_bary.reshape(-1, 2)[cov]
+    b1, b2 = bary[:, 0], bary[:, 1]
+    b0 = 1.0 - b1 - b2
+    uv = torch.as_tensor(sc.uv, device="cuda")
+    th, tw = sc.texture.shape[0], sc.texture.shape[1]
+    u = b0 * uv[0][tri[:, 0]] + b1 * uv[0][tri[:, 1]] + b2 * uv[0][tri[:, 2]]
+    v = b0 * uv[1][tri[:, 0]] + b1 * uv[1][tri[:, 1]] + b2 * uv[1][tri[:, 2]]
+    i0 = torch.clamp(torch.floor(u * tw - 0.5), -1, tw).long()
+    j0 = torch.clamp(torch.floor(v * th - 0.5), -1, th).long()
+    base = 3 * V
+    for di in (0, 1):
+        for dj in (0, 1):
+            ii = torch.clamp(i0 + di, 0, tw - 1)
+            jj = torch.clamp(j0 + dj, 0, th - 1)
+            for ch in range(3):
+                parts.append(base + (jj * tw + ii) * 3 + ch)
+    addr = torch.cat(parts)
+    del parts, tri, bary, u, v, i0, j0
+    vals = torch.ones(addr.numel(), dtype=torch.float32, device="cuda")
+    dst = torch.zeros(3 * V + th * tw * 3, dtype=torch.float32, device="cuda")
+    ms = _median_ms(torch, lambda: dst.index_add_(0, addr, vals), reps)
+    rate = addr.numel() / (ms * 1e-3) / 1e9
+    del addr, vals, dst
+    return rate
+
+
 def bench_backward(reps: int = 10) -> dict:
     """64 views at 512x512 of the 1024x512-quad grid, textured (512x512x3):
     forward with saved barycentrics against the backward pass to vertex
@@ -254,12 +304,17 @@ def bench_backward(reps: int = 10) -> dict:
         r.backward(g, gv, gt)
     ms_b = _median_ms(torch, bwd, reps)
     atomics = covered * 21
+    ref_rate = plain_scatter_rate(torch, r, sc)
     return {"workload": "diff64: 64 views at 512x512 of a 1024x512-quad grid (1,048,576 "
                         "triangles), per-vertex RGB modulated by a bilinear 512x512x3 texture",
             "covered_pixels": covered, "forward_ms": round(ms_f, 4),
             "backward_ms": round(ms_b, 4), "backward_over_forward": round(ms_b / ms_f, 3),
             "fp32_atomics": atomics,
-            "atomic_rate_g_per_s": round(atomics / ms_b / 1e6, 2)}
+            "atomic_rate_g_per_s": round(atomics / ms_b / 1e6, 2),
+            "atomic_roofline": {"peak_g_per_s": round(ref_rate, 2),
+                                "peak_kind": "torch index_add_ over the same 21 addresses "
+                                             "per covered pixel",
+                                "frac": round(atomics / ms_b / 1e6 / ref_rate, 4)}}
 
 
 def main():
@@ -378,6 +433,11 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if fused else profiled_traffic(args.workload, "k_raster"),
                 "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
+    try:
+        roofline["measured_stream_gbs"] = round(measured_stream_bandwidth(torch), 1)
+        roofline["frac_of_measured"] = round(achieved / roofline["measured_stream_gbs"], 4)
+    except RuntimeError:      # not enough free memory for the probe
+        roofline["measured_stream_gbs"] = None
     if not fused:
         a2 = alg_px / (stage["shade"] * 1e-3) / 1e9
         roofline["shade_pass"] = {"kernel": "k_resolve" + (" + k_deferred" if sc.shading == "deferred" else ""),
