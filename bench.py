@@ -69,16 +69,16 @@ def bin_kernel_algorithmic_bytes(sc, npairs: int) -> int:
 
 def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
     """Algorithmic bytes of the per-pixel resolve + shade pass (k_resolve):
-    every pixel's depth and primitive ID read once (8 B, written by the bin
-    kernel), the colour written once (16 B; for deferred the G-buffer 24 B
-    instead), the barycentrics (8 B) when saved, and the attributes of the
-    visible triangle gathered once per covered pixel (3 vertex indices 12 B
-    when indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for
+    every pixel's primitive ID read once (4 B, written by the bin kernel),
+    the colour written once (16 B; for deferred the G-buffer 24 B instead),
+    the barycentrics (8 B) when saved, and the attributes of the visible
+    triangle gathered once per covered pixel (3 vertex indices 12 B when
+    indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for
     deferred)."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
     npix = S * sc.width * sc.height
     deferred = getattr(sc, "shading", "gouraud") == "deferred"
-    per_px = 8 + (24 if deferred else 16) + (8 if want_bary else 0)
+    per_px = 4 + (24 if deferred else 16) + (8 if want_bary else 0)
     per_cov = (12 if sc.idx is not None else 0) + 36 + (36 if deferred else 0)
     return per_px * npix + per_cov * covered_px
 

@@ -321,7 +321,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const Geom &G = a.G;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wv = tid / kWave;
-    unsigned long long frags = 0;
+    uint32_t frags = 0;   // covered samples seen by this thread
     const bool overflow = a.w.misc[1] != 0;   // pair capacity exceeded: no lists
     // expansion-mode start marks: no live tag yet
     uint32_t tag = 0;
@@ -485,7 +485,10 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 // small triangles: each lane walks its own candidates with
                 // incrementally stepped edge functions
                 double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-                int col = 0, px = t.x0, py = t.y0;
+                // the candidate's key slot in the tile, stepped with the edges
+                int col = 0;
+                uint32_t slot = (uint32_t)((t.y0 - py0) * B + (t.x0 - px0));
+                const uint32_t row_skip = (uint32_t)(B - t.wdt + 1);
                 const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
                 e0 = (double)t.A[0] * Px + (double)t.Bc[0] * Py + t.C[0];
                 e1 = (double)t.A[1] * Px + (double)t.Bc[1] * Py + t.C[1];
@@ -505,15 +508,14 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                             unsigned long long key;
                             if (depth_key(e0, e1, e2, t.own, t.inv, t.z[0], t.z[1], t.z[2],
                                           (uint32_t)t.prim, key))
-                                atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
+                                atomicMin(&s_key[slot], key);
                         }
                         if (++col < t.wdt) {
                             e0 += sx0; e1 += sx1; e2 += sx2;
-                            ++px;
+                            ++slot;
                         } else {
                             col = 0;
-                            px = t.x0;
-                            ++py;
+                            slot += row_skip;
                             e0 += sy0; e1 += sy1; e2 += sy2;
                         }
                     }
@@ -681,7 +683,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     }
     if (a.sh.frag_count) {
         // wave reduction, then one atomic per workgroup on its partial slot
-        unsigned long long f = frags;
+        unsigned long long f = (unsigned long long)frags;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) f += __shfl_down(f, d, kWave);
         if (lane == 0) s_frag[wv] = f;
@@ -763,11 +765,10 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
         const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
         unsigned long long key;
         if (split) {
-            // the bin kernel already wrote the depth and primitive-ID targets
+            // the bin kernel already wrote the depth and primitive-ID targets;
+            // shading needs the winner only (the depth half stays unused)
             const int32_t prim = a.sh.out_primid[p];
-            key = prim < 0 ? kEmptyKey
-                           : ((unsigned long long)__float_as_uint(a.sh.out_depth[p]) << 32) |
-                                 (uint32_t)prim;
+            key = prim < 0 ? kEmptyKey : (unsigned long long)(uint32_t)prim;
         } else {
             key = a.w.keys[p];
         }
