@@ -292,8 +292,8 @@ __device__ inline bool depth_key(double e0, double e1, double e2, int own, doubl
 constexpr int kKeysOnly = -1;
 
 // Per-triangle staging record of the expansion mode, in 32-bit words, read
-// with 128-bit LDS loads: [0..3] first candidate, width | own << 8, divide
-// magic, origin x | y << 16; [4..9] 256 A_k as float64 (the edge step per
+// with 128-bit LDS loads: [0..3] first quad, width | height << 8 | own << 16 |
+// quads per row << 19, divide magic, origin x | y << 16; [4..9] 256 A_k as float64 (the edge step per
 // pixel in x); [10..15] 256 B_k (in y); [16..21] the edge values e_k at the
 // origin pixel centre (float64, own bias included); [22..23] 1/|A2|;
 // [24..26] z_k; [27] primitive.  With a stride of 28 words the 128-bit
@@ -521,28 +521,35 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     }
                 }
             } else {
-                // large triangles: lay the wave's candidates end to end and
-                // hand them out in blocks of 64, one per lane
-                int total = t.cnt;
+                // large triangles: cover each clipped bbox with 2x2 pixel
+                // quads, lay the wave's quads end to end and hand them out in
+                // blocks of 64, one per lane.  A quad pays the owner lookup,
+                // the record reads and the divide once for four pixels.
+                const int hgt = t.cnt > 0 ? t.cnt / t.wdt : 0;
+                const int qw = (t.wdt + 1) >> 1, qh = (hgt + 1) >> 1;
+                const int qcnt = t.cnt > 0 ? qw * qh : 0;
+                int total = qcnt;
 #pragma unroll
                 for (int d = 1; d < kWave; d <<= 1) {
                     const int y = __shfl_up(total, d, kWave);
                     if (lane >= d) total += y;
                 }
-                const int start = total - t.cnt;
+                const int start = total - qcnt;
                 total = __shfl(total, kWave - 1, kWave);
                 uint32_t *rec = s_rec[wv];
                 uint32_t *mark = s_mark[wv];
                 {
                     // stage this lane's triangle
                     uint32_t *r = rec + lane * kStRec;
-                    // m = ceil(2^18 / width) makes (c * m) >> 18 an exact divide
-                    // for candidate numbers c < 2^12 (c * (m * width - 2^18) <
-                    // 2^12 * width <= 2^18), all in full-rate 24-bit multiplies
-                    const uint32_t mag = ((1u << 18) + (uint32_t)max(t.wdt, 1) - 1u) / (uint32_t)max(t.wdt, 1);
+                    // m = ceil(2^18 / qw) makes (c * m) >> 18 an exact divide
+                    // for quad numbers c < 2^12 (c * (m * qw - 2^18) < 2^12 * qw
+                    // <= 2^18), all in full-rate 24-bit multiplies
+                    const uint32_t q1 = (uint32_t)max(qw, 1);
+                    const uint32_t mag = ((1u << 18) + q1 - 1u) / q1;
                     *reinterpret_cast<uint4 *>(r) =
-                        make_uint4((uint32_t)start, (uint32_t)(max(t.wdt, 1) | (t.own << 8)), mag,
-                                   (uint32_t)(t.x0 | (t.y0 << 16)));
+                        make_uint4((uint32_t)start,
+                                   (uint32_t)(max(t.wdt, 1) | (hgt << 8) | (t.own << 16) | (q1 << 19)),
+                                   mag, (uint32_t)(t.x0 | (t.y0 << 16)));
                     const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
                     double st[12];
 #pragma unroll
@@ -562,7 +569,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                int carry = 0;   // triangle of the last candidate of the previous block
+                int carry = 0;   // triangle of the last quad of the previous block
                 if (tag + (uint32_t)(total / kWave + 1) >= kNoTag) {
                     // (never in practice) recycle the tags before they run out
                     mark[lane] = 0xffffffffu;
@@ -570,14 +577,14 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 }
 #pragma unroll 1
                 for (int b = 0; b < total; b += kWave) {
-                    // Which triangle owns candidate j = b + lane: the last non-empty
+                    // Which triangle owns quad j = b + lane: the last non-empty
                     // triangle starting at or before j.  Each one starting inside
                     // this block marks its start position with its lane; a ballot
                     // of the live marks and a leading-zero count find the nearest
                     // mark at or below j, a lane shuffle fetches it, and a block
                     // position before any mark belongs to the previous block's
                     // last triangle.
-                    if (t.cnt > 0 && start >= b && start < b + kWave)
+                    if (qcnt > 0 && start >= b && start < b + kWave)
                         mark[start - b] = (tag << kTagShift) | (uint32_t)lane;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -598,30 +605,61 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     const double2 a01 = r2[0], a2b0 = r2[1], b12 = r2[2];
                     const double2 e01 = r2[3], e2i = r2[4];
                     const uint32_t local = (uint32_t)j - hd.x;
-                    const int32_t wi = (int32_t)hd.y;
-                    const uint32_t wdt = (uint32_t)(wi & 0xff);
-                    const uint32_t row = __umul24(local, hd.z) >> 18;
-                    const uint32_t col = local - __umul24(row, wdt);
+                    const uint32_t wi = hd.y;
+                    const uint32_t wdt = wi & 0xff, hh = (wi >> 8) & 0xff, own = (wi >> 16) & 7;
+                    const uint32_t qwl = wi >> 19;
+                    const uint32_t qr = __umul24(local, hd.z) >> 18;
+                    const uint32_t qc = local - __umul24(qr, qwl);
+                    const uint32_t col = 2 * qc, row = 2 * qr;
                     const double dc = (double)col, dr = (double)row;
-                    // e_k at (col, row) from the origin value and the steps:
-                    // every product and sum is an integer below 2^53, so the
-                    // fused and unfused forms are the same exact value
-                    const double e0 = fma(dr, a2b0.y, fma(dc, a01.x, e01.x));
-                    const double e1 = fma(dr, b12.x, fma(dc, a01.y, e01.y));
-                    const double e2 = fma(dr, b12.y, fma(dc, a2b0.x, e2i.x));
-                    if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
+                    // e_k at the quad's first pixel from the origin value and the
+                    // steps, then one step right, down, and both: every product
+                    // and sum is an integer below 2^53, so all are exact
+                    double ea[3], eb[3], ec[3], ed[3];
+                    ea[0] = fma(dr, a2b0.y, fma(dc, a01.x, e01.x));
+                    ea[1] = fma(dr, b12.x, fma(dc, a01.y, e01.y));
+                    ea[2] = fma(dr, b12.y, fma(dc, a2b0.x, e2i.x));
+                    const double sxk[3] = {a01.x, a01.y, a2b0.x}, syk[3] = {a2b0.y, b12.x, b12.y};
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        eb[k] = ea[k] + sxk[k];
+                        ec[k] = ea[k] + syk[k];
+                        ed[k] = eb[k] + syk[k];
+                    }
+                    const bool right = col + 1 < wdt, down = row + 1 < hh;
+                    const bool ca = ea[0] > 0.0 && ea[1] > 0.0 && ea[2] > 0.0;
+                    const bool cb = right && eb[0] > 0.0 && eb[1] > 0.0 && eb[2] > 0.0;
+                    const bool cc = down && ec[0] > 0.0 && ec[1] > 0.0 && ec[2] > 0.0;
+                    const bool cd = right && down && ed[0] > 0.0 && ed[1] > 0.0 && ed[2] > 0.0;
+                    if (!(ca || cb || cc || cd)) continue;
+                    const double2 zz = r2[5];
+                    const float z0 = __uint_as_float((uint32_t)__double2loint(zz.x));
+                    const float z1 = __uint_as_float((uint32_t)__double2hiint(zz.x));
+                    const float z2 = __uint_as_float((uint32_t)__double2loint(zz.y));
+                    const uint32_t prim = (uint32_t)__double2hiint(zz.y);
+                    const int32_t org = (int32_t)hd.w;
+                    const uint32_t slot = (uint32_t)(((org >> 16) + (int32_t)row - py0) * B +
+                                                     (org & 0xffff) + (int32_t)col - px0);
+                    unsigned long long key;
+                    if (ca) {
                         ++frags;
-                        const double2 zz = r2[5];
-                        unsigned long long key;
-                        const int32_t org = (int32_t)hd.w;
-                        const int32_t px = (org & 0xffff) + (int32_t)col;
-                        const int32_t py = (org >> 16) + (int32_t)row;
-                        if (depth_key(e0, e1, e2, wi >> 8, e2i.y,
-                                      __uint_as_float((uint32_t)__double2loint(zz.x)),
-                                      __uint_as_float((uint32_t)__double2hiint(zz.x)),
-                                      __uint_as_float((uint32_t)__double2loint(zz.y)),
-                                      (uint32_t)__double2hiint(zz.y), key))
-                            atomicMin(&s_key[(py - py0) * B + (px - px0)], key);
+                        if (depth_key(ea[0], ea[1], ea[2], own, e2i.y, z0, z1, z2, prim, key))
+                            atomicMin(&s_key[slot], key);
+                    }
+                    if (cb) {
+                        ++frags;
+                        if (depth_key(eb[0], eb[1], eb[2], own, e2i.y, z0, z1, z2, prim, key))
+                            atomicMin(&s_key[slot + 1], key);
+                    }
+                    if (cc) {
+                        ++frags;
+                        if (depth_key(ec[0], ec[1], ec[2], own, e2i.y, z0, z1, z2, prim, key))
+                            atomicMin(&s_key[slot + B], key);
+                    }
+                    if (cd) {
+                        ++frags;
+                        if (depth_key(ed[0], ed[1], ed[2], own, e2i.y, z0, z1, z2, prim, key))
+                            atomicMin(&s_key[slot + B + 1], key);
                     }
                 }
                 // the staging slots are rewritten by this wave's next chunk
