@@ -23,6 +23,11 @@
 
 namespace pk {
 
+// Three consecutive floats with 4-byte alignment: one dwordx3 access.
+struct Float3 {
+    float x, y, z;
+};
+
 struct RasterArgs {
     Geom G;
     Ws w;
@@ -97,6 +102,31 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
         const int32_t X[3] = {q[0].x, q[1].x, q[2].x}, Y[3] = {q[0].y, q[1].y, q[2].y};
         r.sinv = signed_inv_area(area2(X, Y));
     }
+    if (!a.G.idx) {
+        // unindexed: the three vertices are consecutive in every plane, one
+        // 12-byte load per plane instead of three
+        const int64_t v0 = r.v[0];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const Float3 c = *reinterpret_cast<const Float3 *>(sh.color + ch * V + v0);
+            r.c[0][ch] = c.x; r.c[1][ch] = c.y; r.c[2][ch] = c.z;
+        }
+        if (SHADE == PK_SHADE_TEXTURED) {
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch) {
+                const Float3 u = *reinterpret_cast<const Float3 *>(sh.uv + ch * V + v0);
+                r.ex[0][ch] = u.x; r.ex[1][ch] = u.y; r.ex[2][ch] = u.z;
+            }
+        }
+        if (SHADE == PK_SHADE_DEFERRED) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const Float3 n = *reinterpret_cast<const Float3 *>(sh.normal + ch * V + v0);
+                r.ex[0][ch] = n.x; r.ex[1][ch] = n.y; r.ex[2][ch] = n.z;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -123,8 +153,8 @@ __device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, in
         if (write_dp && sh.out_primid) sh.out_primid[p] = -1;
         if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(0, 0);
         if (SHADE == PK_SHADE_DEFERRED) {
-            sh.gbuf_n[3 * p] = 0; sh.gbuf_n[3 * p + 1] = 0; sh.gbuf_n[3 * p + 2] = 0;
-            sh.gbuf_a[3 * p] = 0; sh.gbuf_a[3 * p + 1] = 0; sh.gbuf_a[3 * p + 2] = 0;
+            *reinterpret_cast<Float3 *>(sh.gbuf_n + 3 * p) = Float3{0.0f, 0.0f, 0.0f};
+            *reinterpret_cast<Float3 *>(sh.gbuf_a + 3 * p) = Float3{0.0f, 0.0f, 0.0f};
         }
         return;
     }
@@ -198,8 +228,8 @@ __device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, in
             const float len = sqrtf(nn);
             nh0 = n[0] / len; nh1 = n[1] / len; nh2 = n[2] / len;
         }
-        sh.gbuf_n[3 * p] = nh0; sh.gbuf_n[3 * p + 1] = nh1; sh.gbuf_n[3 * p + 2] = nh2;
-        sh.gbuf_a[3 * p] = rgb[0]; sh.gbuf_a[3 * p + 1] = rgb[1]; sh.gbuf_a[3 * p + 2] = rgb[2];
+        *reinterpret_cast<Float3 *>(sh.gbuf_n + 3 * p) = Float3{nh0, nh1, nh2};
+        *reinterpret_cast<Float3 *>(sh.gbuf_a + 3 * p) = Float3{rgb[0], rgb[1], rgb[2]};
     } else if (sh.out_color) {
         reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
     }
@@ -904,7 +934,8 @@ __global__ __launch_bounds__(256) void k_deferred(Shade sh, int64_t npix) {
         reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(0, 0, 0, 0);
         return;
     }
-    const float n0 = sh.gbuf_n[3 * p], n1 = sh.gbuf_n[3 * p + 1], n2 = sh.gbuf_n[3 * p + 2];
+    const Float3 nn = *reinterpret_cast<const Float3 *>(sh.gbuf_n + 3 * p);
+    const float n0 = nn.x, n1 = nn.y, n2 = nn.z;
     float lit = 0.0f;
     for (int l = 0; l < sh.num_lights; ++l) {
         const float *L = sh.lights + 3 * l;
@@ -914,9 +945,8 @@ __global__ __launch_bounds__(256) void k_deferred(Shade sh, int64_t npix) {
         d = d < 0.0f ? 0.0f : d;
         lit = (l == 0) ? d : lit + d;
     }
-    reinterpret_cast<float4 *>(sh.out_color)[p] =
-        make_float4(sh.gbuf_a[3 * p] * lit, sh.gbuf_a[3 * p + 1] * lit,
-                    sh.gbuf_a[3 * p + 2] * lit, 1.0f);
+    const Float3 al = *reinterpret_cast<const Float3 *>(sh.gbuf_a + 3 * p);
+    reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(al.x * lit, al.y * lit, al.z * lit, 1.0f);
 }
 
 hipError_t launch_deferred(const Geom &G, const Shade &sh, hipStream_t st) {
