@@ -4,7 +4,10 @@ One step = one whole frame of the hot path on resident inputs: vertex
 transform + setup + bin counts (pk_setup), prefix sum + scatter of the bin
 lists (pk_assign_bin), per-bin coverage and depth test (pk_raster_shade with
 the shading deferred) and the per-pixel resolve / shading pass (pk_shade).
-Prints one JSON line.  Default workload: the 1920x1080
+Consecutive frames alternate between two renderers on two streams (each
+frame complete and in order on its stream; `single_stream` reports the same
+frames run one after another).  Prints one JSON line.  Default workload: the
+1920x1080
 displaced grid of 1024x512 quads (1,048,576 triangles) through a perspective
 camera, Gouraud shading, 16x16 bins.
 """
@@ -326,6 +329,8 @@ def main():
     ap.add_argument("--bin", type=int, default=0)
     ap.add_argument("--schedule", default="")
     ap.add_argument("--tpb", type=int, default=-1)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="frames alternate between this many renderers and streams")
     ap.add_argument("--groups", type=int, default=0,
                     help="persistent workgroups of the bin kernel (0 = library default)")
     ap.add_argument("--bary", action="store_true", help="also save barycentrics")
@@ -387,15 +392,40 @@ def main():
 
     K = args.steps
     stream = torch.cuda.current_stream()
-    # headline: K whole frames, no event inside a frame (an event record costs
-    # the queue a few microseconds, which would inflate the frame)
+    # Headline: K whole frames, each one complete (setup, binning, bin kernel,
+    # resolve) and in order on its stream, alternating between two renderers
+    # (own workspace and outputs, shared inputs) on two streams so that one
+    # frame's small kernels overlap the other's large ones.  No event inside
+    # a frame (an event record costs the queue a few microseconds).
+    nst = max(1, args.streams)
+    rs = [r] + [pk.Renderer(r.dev, cfg) for _ in range(nst - 1)]
+    for x in rs[1:]:
+        x.count_fragments(False)
+        x.render()
+    streams = [torch.cuda.Stream() for _ in range(nst)]   # default priority
+    for _ in range(args.warmup):
+        for x, st in zip(rs, streams):
+            with torch.cuda.stream(st):
+                x.frame()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    for k in range(K):
+        with torch.cuda.stream(streams[k % nst]):
+            rs[k % nst].frame()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for x in rs:
+        assert not x.ensure_capacity(), "bin-pair capacity changed during the timed region"
+    for x in rs[1:]:
+        assert torch.equal(x.out_primid, r.out_primid), "pipelined frames differ"
+        assert torch.equal(x.out_color, r.out_color), "pipelined frames differ"
+    # the same frames one after another on one stream (a frame's latency)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     for _ in range(K):
         r.frame()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert not r.ensure_capacity(), "bin-pair capacity changed during the timed region"
+    dt1 = time.perf_counter() - t1
     # the same K frames again with HIP events around each stage on the launch
     # stream: per-stage (per-kernel) durations for the roofline
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
@@ -453,6 +483,9 @@ def main():
                    "schedule": sched, "threads_per_bin": tpb, "fused_resolve": fused,
                    "saved_bary": bary, "triangles": tris,
                    "resolution": f"{sc.width}x{sc.height}", "scenes": S},
+        "streams": nst,
+        "single_stream": {"ms_per_step": round(dt1 * 1e3 / K, 4),
+                          "value": round(tris / (dt1 * 1e3 / K * 1e-3) / 1e6, 2)},
         "gfrags_per_s": round(gfrags, 3), "fragments_per_frame": frags,
         "bin_pairs_per_frame": npairs, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "roofline": roofline,
