@@ -105,6 +105,22 @@ def test_bin_lists_match_oracle(B):
         assert sorted(pairs[off[b]:off[b + 1]]) == list(otris[ooff[b]:ooff[b + 1]])
 
 
+@pytest.mark.parametrize("B", [8, 16])
+def test_bin_lists_random_micropolygons(B):
+    """400K randomly placed micropolygons: every setup workgroup touches
+    almost every bin (no spatial coherence for the LDS counts to exploit).
+    Lists and image must match the oracle."""
+    _note(f"random micropolygon bin lists B={B}")
+    sc = scenes.micro(seed=77, width=320, height=240, num_tris=400_000, bin_size=B)
+    g = gpu_render(sc, bin_size=B, want_bary=False)
+    off, pairs = g["renderer"].bin_lists()
+    ooff, otris = oracle.assign_bin(sc, B)
+    np.testing.assert_array_equal(off, ooff)
+    for b in range(len(ooff) - 1):
+        assert sorted(pairs[off[b]:off[b + 1]]) == list(otris[ooff[b]:ooff[b + 1]])
+    compare(sc, g, oracle.render(sc), check_bary=False)
+
+
 def test_repeat_runs_bit_identical():
     import torch
     sc = scenes.tiny(seed=3, width=96, height=96, num_tris=800)
