@@ -263,6 +263,35 @@ __device__ inline void fetch_tri(const Ws &w, int32_t item, RawTri &r) {
     r.q1 = rp[1];
 }
 
+// The software pipeline below prefetches into loop-carried registers.  A
+// prefetch load under a lane condition makes those registers a merge of the
+// loaded and the old value, and the compiler then waits for the load right
+// after issuing it in order to copy it.  So every lane issues the load: lanes
+// without an entry read a dummy address inside the workspace (the misc words,
+// 2304 bytes, 256-byte aligned) and discard the value.
+__device__ inline void prefetch_tri(const Ws &w, int32_t item, RawTri &r) {
+    const uint4 *rp = item >= 0 ? reinterpret_cast<const uint4 *>(w.rec + item)
+                                : reinterpret_cast<const uint4 *>(w.misc);
+    r.q0 = rp[0];
+    r.q1 = rp[1];
+}
+
+// The raw value: the caller applies `valid` when it uses it (a select right
+// after the load would wait for it).
+__device__ inline int32_t prefetch_pair(const Ws &w, bool valid, int32_t j) {
+    return *(valid ? w.pairs + j : reinterpret_cast<const int32_t *>(w.misc));
+}
+
+// The CSR offsets are read-only in the bin kernel and the bin is uniform
+// across the wave: read them through the constant address space so that
+// they are scalar loads, whose waits do not hold up the vector prefetches.
+typedef const __attribute__((address_space(4))) int32_t ConstI32;
+__device__ inline void bin_range(const Ws &w, int64_t b, int32_t &beg, int32_t &end) {
+    const ConstI32 *off = (const ConstI32 *)w.bin_off;
+    beg = off[b];
+    end = off[b + 1];
+}
+
 __device__ inline void decode_tri(const RawTri &r, int32_t item, int64_t item_base, int32_t px0,
                                   int32_t py0, int32_t pw, int32_t ph, int32_t W, int32_t H,
                                   EdgeTri &t) {
@@ -334,7 +363,10 @@ constexpr int kStRec = 28;
 // that the plane never needs clearing; kNoTag is never a live tag.
 constexpr uint32_t kTagShift = 6, kNoTag = 0xffffffffu >> kTagShift;
 
-template <int TPB, int B, int SHADE>
+// PIPED: the DIRECT_MAP schedule with its prefetching chunk stream (its own
+// instantiation keeps the loop simple enough for the prefetches to land in
+// their loop-carried registers); otherwise LOAD_BALANCE or DYNAMIC.
+template <int TPB, int B, int SHADE, bool PIPED>
 __global__ __launch_bounds__(TPB)
 __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(RasterArgs a) {
     constexpr int NPIX = B * B;
@@ -382,14 +414,15 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     // numbers of chunk n+2 are in flight, and the CSR offsets of the bin
     // after chunk n+2's bin are loaded, so no chunk waits for memory unless a
     // bin without chunks for this wave is skipped.
-    const bool piped = a.schedule == PK_SCHED_DIRECT_MAP;
+    constexpr bool piped = PIPED;
     const int32_t wbase = __builtin_amdgcn_readfirstlane(wv) * kWave;
     int64_t n_it = -1;                 // chunk n+1: iteration (bin) of the stream, -1 = none
     int32_t id_n = -1;                 //   this lane's pair number (-1 = past the list end)
     RawTri raw_n;                      //   its setup record (in flight)
     int64_t nn_it = -1;                // chunk n+2: iteration, first entry, list end
     int32_t nn_c0 = 0, nn_end = 0;
-    int32_t id_nn = -1;                //   this lane's pair number (in flight)
+    int32_t id_nn = -1;                //   this lane's pair number (in flight; valid iff ok_nn)
+    bool ok_nn = false;
     int64_t pre_it = -1;               // offsets of bin dm_bin(pre_it) (pre_it = nn_it + 1)
     int32_t pre_beg = 0, pre_end = 0;
     auto load_offsets = [&](int64_t it, int64_t &o_it, int32_t &o_beg, int32_t &o_end) {
@@ -397,7 +430,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         o_it = b >= 0 ? it : -1;
         o_beg = 0;
         o_end = 0;
-        if (b >= 0 && !overflow) { o_beg = a.w.bin_off[b]; o_end = a.w.bin_off[b + 1]; }
+        if (b >= 0 && !overflow) bin_range(a.w, b, o_beg, o_end);
     };
     // move chunk n+2 one chunk on, and start loading its pair numbers
     auto advance_nn = [&]() {
@@ -412,7 +445,8 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             }
         }
         const int32_t j = nn_c0 + lane;
-        id_nn = (nn_it >= 0 && j < nn_end) ? a.w.pairs[j] : -1;
+        ok_nn = nn_it >= 0 && j < nn_end;
+        id_nn = prefetch_pair(a.w, ok_nn, j);
     };
     if (piped) {
         // prologue: chunk 0 becomes "n+1", chunk 1 "n+2"
@@ -422,8 +456,8 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         nn_end = -TPB;
         advance_nn();
         n_it = nn_it;
-        id_n = id_nn;
-        if (id_n >= 0) fetch_tri(a.w, id_n, raw_n);
+        id_n = ok_nn ? id_nn : -1;
+        prefetch_tri(a.w, id_n, raw_n);
         advance_nn();
     }
     // DYNAMIC: current queue (range) and the bins of the last batch taken
@@ -431,7 +465,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     int64_t batch_beg = 0, batch_end = 0;
     for (int64_t it = 0;; ++it) {
         int64_t bin;
-        if (a.schedule == PK_SCHED_DYNAMIC) {
+        if (!piped && a.schedule == PK_SCHED_DYNAMIC) {
             if (batch_beg >= batch_end) {
                 // take a batch of bins from this die's queue; when it is
                 // empty, move on to the other dies' queues
@@ -499,8 +533,8 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 item = id_n;
                 // chunk n+2 becomes n+1: fetch its records; load the next pair numbers
                 n_it = nn_it;
-                id_n = id_nn;
-                if (id_n >= 0) fetch_tri(a.w, id_n, raw_n);
+                id_n = ok_nn ? id_nn : -1;
+                prefetch_tri(a.w, id_n, raw_n);
                 advance_nn();
             } else {
                 if (c0 >= lend) break;
@@ -850,16 +884,24 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
         if (on[k]) resolve_finish<SHADE>(a, s, px, py0 + k * kResH, r[k], !split);
 }
 
+template <int TPB, int B, int SHADE>
+static hipError_t launch_b(const RasterArgs &a, dim3 grid, hipStream_t st) {
+    if (a.schedule == PK_SCHED_DIRECT_MAP)
+        hipLaunchKernelGGL((k_raster<TPB, B, SHADE, true>), grid, dim3(TPB), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false>), grid, dim3(TPB), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int TPB, int SHADE>
 static hipError_t launch_tpb(const RasterArgs &a, dim3 grid, hipStream_t st) {
     switch (a.G.B) {
-    case 8:  hipLaunchKernelGGL((k_raster<TPB, 8, SHADE>), grid, dim3(TPB), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_raster<TPB, 16, SHADE>), grid, dim3(TPB), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_raster<TPB, 32, SHADE>), grid, dim3(TPB), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_raster<TPB, 64, SHADE>), grid, dim3(TPB), 0, st, a); break;
+    case 8:  return launch_b<TPB, 8, SHADE>(a, grid, st);
+    case 16: return launch_b<TPB, 16, SHADE>(a, grid, st);
+    case 32: return launch_b<TPB, 32, SHADE>(a, grid, st);
+    case 64: return launch_b<TPB, 64, SHADE>(a, grid, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int SHADE>
