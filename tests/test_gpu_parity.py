@@ -226,6 +226,41 @@ def test_empty_and_culled_inputs():
     compare(sc2, g2, oracle.render(sc2))
 
 
+def test_maximum_screen_and_guard_band():
+    """The largest screen the ABI takes (8192 x 8192) with triangles reaching
+    the guard band (|x_s| just below 2^14 px, so |X| near 2^22 sub-pixels and
+    edge products near 2^46), a vertex just outside it (culled), a long
+    sliver and mid-size triangles.  With 8-px bins the scene has 2^20 bins,
+    more than the LDS counts hold (the direct device-atomic binning path)."""
+    _note("maximum screen")
+    W = H = 8192
+    lim = 2.99987                      # (lim + 1) * 4096 < 16384
+    P = [(-4.99, -4.99, 0.9), (lim, -4.99, 0.9), (-4.99, lim, 0.9),
+         (lim, -4.99, 0.8), (lim, lim, 0.8), (-4.99, lim, 0.8),
+         (-4.9, -0.001, 0.3), (2.9, 0.0007, 0.3), (-4.9, 0.0013, 0.3),       # sliver
+         (3.0, 0.0, 0.1), (0.0, 0.5, 0.1), (-0.5, -0.5, 0.1)]               # x_s = 2^14: culled
+    rng = np.random.default_rng(81)
+    for _ in range(60):
+        c = rng.uniform(-1.0, 1.0, 2)
+        for _k in range(3):
+            d = rng.uniform(-0.03, 0.03, 2)
+            P.append((c[0] + d[0], c[1] + d[1], rng.uniform(0.0, 1.0)))
+    pos = np.asarray(P, np.float32).T.copy()
+    col = rng.uniform(0, 1, pos.shape).astype(np.float32)
+    sc = SimpleNamespace(width=W, height=H, pos=pos, color=col, idx=None, num_tris=pos.shape[1] // 3,
+                         mvp=None, num_scenes=1, scene_tri_off=None, scene_vtx_off=None,
+                         instanced=False, uv=None, normal=None, texture=None, lights=None,
+                         shading="gouraud")
+    o = oracle.render(sc, want_bary=False)     # about 25 s of CPU
+    for B in (8, 64):
+        _note(f"maximum screen B={B}")
+        g = gpu_render(sc, bin_size=B, want_bary=False)
+        compare(sc, g, o, check_bary=False)
+        assert (g["primid"] >= 0).all()        # the two big triangles cover the screen
+        assert 3 not in set(np.unique(g["primid"]))
+        del g
+
+
 def test_capacity_overflow_then_retry():
     import torch
     sc = scenes.tiny(seed=8, width=128, height=128, num_tris=500)
