@@ -169,7 +169,7 @@ def bench_batched(reps: int = 10) -> dict:
     from paper_1404_6293_amd import autotune, pk, scenes
     sc = scenes.batch()
     dev = pk.DeviceScene(sc)
-    cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map", "dynamic"),
+    cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64), schedules=("direct_map", "dynamic"),
                                      threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True
@@ -208,12 +208,12 @@ def bench_batched(reps: int = 10) -> dict:
 
 def bench_micro(reps: int = 10) -> dict:
     """2^23 micropolygons at 1920x1080 with deferred shading, bin size
-    autotuned in {8, 16, 32, 64}."""
+    autotuned in {0 (whole-screen bins), 8, 16, 32, 64}."""
     import torch
     from paper_1404_6293_amd import autotune, pk, scenes
     sc = scenes.micro()
     dev = pk.DeviceScene(sc)
-    cands = list(autotune.candidates(bins=(8, 16, 32, 64), schedules=("direct_map",),
+    cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64), schedules=("direct_map",),
                                      threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True

@@ -119,7 +119,12 @@ enum {
 
 typedef struct {               /* [host] */
     int32_t width, height;     /* 1..8192 pixels */
-    int32_t bin_size;          /* screen-space bin edge: 8, 16, 32 or 64 pixels */
+    int32_t bin_size;          /* screen-space bin edge: 8, 16, 32 or 64 pixels, or
+                                  0 = one whole-screen bin per scene (the unbinned
+                                  pipeline: no bin lists; each triangle is
+                                  rasterized on its own with a device-scope
+                                  depth test; schedule, threads_per_bin and
+                                  persistent_groups are ignored) */
     int32_t schedule;          /* pk_schedule */
     int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto */
     int32_t shading;           /* pk_shading */
@@ -187,7 +192,10 @@ pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream)
  * *pairs_needed (device, one int64) receives the total number of (bin,
  * triangle) pairs.  If it exceeds pair_capacity, no list is written and the
  * following pk_raster_shade writes no pixel; call again with a larger
- * workspace.  The order of triangles inside one bin is unspecified. */
+ * workspace.  The order of triangles inside one bin is unspecified.
+ * With bin_size 0 every scene is one bin that holds all of its triangles
+ * (Sec. 4.4: full-screen bins need no assignment): nothing is built and
+ * *pairs_needed receives 0. */
 pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t pair_capacity,
                         int64_t *pairs_needed, void *stream);
 
@@ -196,7 +204,14 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
  * every pixel of every target that is non-NULL (Sec. 4.4 sort-middle renderer;
  * Sec. 5.2.2 fusion of Rasterizer, Fragment Shader, Depth Test, Composite).
  * With PK_SHADE_DEFERRED the colour comes from a second pass over the
- * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace. */
+ * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace.
+ * With bin_size 0 (whole-screen bins) one thread per triangle covers its
+ * bounding box on the screen and the depth test is a device-scope 64-bit
+ * atomic min into the workspace's key buffer (the paper's baseline with
+ * full-screen bins, Sec. 7); the per-pixel resolve then always runs as its
+ * own pass (also under PK_FLAG_FUSE_RESOLVE, since there is no per-bin EndBin),
+ * and under PK_FLAG_DEFER_SHADE the keys stay in the workspace.  The image
+ * is the same as with any bin size. */
 pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
                           const pk_targets *out, void *stream);
 
@@ -228,7 +243,8 @@ pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
  * bin_offsets has num_bins + 1 entries (bins of scene s are numbered
  * s * bins_per_scene + by * ceil(W/bin_size) + bx); bin_tris holds the
  * triangle numbers (s * T + t for instanced views, the concatenated index
- * otherwise).  Host-only: computes addresses, launches nothing. */
+ * otherwise).  Host-only: computes addresses, launches nothing.  Returns
+ * PK_ERR_UNSUPPORTED for bin_size 0 (whole-screen bins keep no lists). */
 typedef struct {
     const int32_t *bin_offsets;  /* device */
     const int32_t *bin_tris;     /* device */

@@ -25,14 +25,18 @@ from . import pk
 CACHE_ENV = "PK_AUTOTUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pk_autotune.json")
 
-BIN_SIZES = (8, 16, 32, 64)
+BIN_SIZES = (0, 8, 16, 32, 64)   # 0: whole-screen bins (unbinned, Sec. 4.4)
 SCHEDULES = ("direct_map", "load_balance", "dynamic")
 THREADS = (64, 128, 256)
 
 
 def candidates(bins: Iterable[int] = BIN_SIZES, schedules: Iterable[str] = SCHEDULES,
                threads: Iterable[int] = THREADS, fused: Iterable[bool] = (False, True)):
-    for b, s, t, f in itertools.product(bins, schedules, threads, fused):
+    if 0 in bins:
+        # whole-screen bins ignore the schedule, the bin workgroup size and
+        # fusion: one candidate
+        yield pk.RenderConfig(bin_size=0)
+    for b, s, t, f in itertools.product([b for b in bins if b], schedules, threads, fused):
         yield pk.RenderConfig(bin_size=b, schedule=s, threads_per_bin=t, fuse_resolve=f)
 
 

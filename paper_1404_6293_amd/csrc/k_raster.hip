@@ -824,6 +824,147 @@ __global__ __launch_bounds__(kFragSlots) void k_raster_epilogue(uint32_t *misc,
     if (rewind && threadIdx.x < kXcd) misc[8 + threadIdx.x] = 0u;
 }
 
+// Whole-screen bins (bin size 0, the unbinned pipeline of Sec. 4.4 and the
+// paper's full-screen-bin baseline of Sec. 7): no bin lists, one thread per
+// triangle over its sample bounding box on the screen, and the depth test as
+// a device-scope 64-bit atomic min into the workspace key buffer (cleared to
+// all ones beforehand).  The keys are the same (depth, primitive) keys as in
+// the bin kernel, so the image is the same.  Triangles whose box is small
+// walk it per lane with stepped edge functions; larger ones are swept by the
+// whole wave, one triangle at a time, one pixel per lane.
+constexpr int kDirectThreads = 256;
+constexpr int kDirectLoopMax = 12;
+
+__global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
+    const Geom &G = a.G;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t item = blockIdx.x * (int64_t)kDirectThreads + threadIdx.x;
+    EdgeTri t;
+    t.cnt = 0;
+    int64_t kbase = 0;   // first key of the triangle's scene
+    if (item < G.items && a.w.bbox[item] != kEmptyKey) {
+        const ItemRef r = item_ref(G, item);
+        RawTri raw;
+        fetch_tri(a.w, (int32_t)item, raw);
+        decode_tri(raw, item, item - r.t, 0, 0, G.W, G.H, G.W, G.H, t);
+        kbase = (int64_t)r.s * G.W * G.H;
+    }
+    uint32_t frags = 0;
+    unsigned long long *keys = a.w.keys;
+    // small boxes: each lane walks its own
+    const int small = t.cnt <= kDirectLoopMax ? t.cnt : 0;
+    const int mx = wave_max(small);
+    if (mx > 0) {
+        int col = 0;
+        int64_t pix = kbase + (int64_t)t.y0 * G.W + t.x0;
+        const int64_t row_skip = (int64_t)G.W - t.wdt + 1;
+        const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
+        double e0 = (double)t.A[0] * Px + (double)t.Bc[0] * Py + t.C[0];
+        double e1 = (double)t.A[1] * Px + (double)t.Bc[1] * Py + t.C[1];
+        double e2 = (double)t.A[2] * Px + (double)t.Bc[2] * Py + t.C[2];
+        const double sx0 = (double)(256 * t.A[0]), sx1 = (double)(256 * t.A[1]),
+                     sx2 = (double)(256 * t.A[2]);
+        const double back = (double)(256 * (t.wdt - 1));
+        const double sy0 = (double)(256 * t.Bc[0]) - back * (double)t.A[0];
+        const double sy1 = (double)(256 * t.Bc[1]) - back * (double)t.A[1];
+        const double sy2 = (double)(256 * t.Bc[2]) - back * (double)t.A[2];
+#pragma unroll 1
+        for (int j = 0; j < mx; ++j) {
+            if (j < small) {
+                if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
+                    ++frags;
+                    unsigned long long key;
+                    if (depth_key(e0, e1, e2, t.own, t.inv, t.z[0], t.z[1], t.z[2],
+                                  (uint32_t)t.prim, key))
+                        atomicMin(keys + pix, key);
+                }
+                if (++col < t.wdt) {
+                    e0 += sx0; e1 += sx1; e2 += sx2;
+                    ++pix;
+                } else {
+                    col = 0;
+                    pix += row_skip;
+                    e0 += sy0; e1 += sy1; e2 += sy2;
+                }
+            }
+        }
+    }
+    // large boxes: the wave sweeps each in turn, one pixel per lane.  Edge
+    // values are evaluated directly: every product and sum is an integer
+    // below 2^53, so the float64 arithmetic is exact.
+    uint64_t big = __ballot(t.cnt > kDirectLoopMax);
+    while (big) {
+        const int l = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        double A[3], Bv[3], C[3];
+        float z[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] = (double)__shfl(t.A[k], l, kWave);
+            Bv[k] = (double)__shfl(t.Bc[k], l, kWave);
+            C[k] = __shfl(t.C[k], l, kWave);
+            z[k] = __shfl(t.z[k], l, kWave);
+        }
+        const double inv = __shfl(t.inv, l, kWave);
+        const int x0 = __shfl(t.x0, l, kWave), y0 = __shfl(t.y0, l, kWave);
+        const uint32_t wdt = (uint32_t)__shfl(t.wdt, l, kWave);
+        const int cnt = __shfl(t.cnt, l, kWave), own = __shfl(t.own, l, kWave);
+        const uint32_t prim = (uint32_t)__shfl(t.prim, l, kWave);
+        const int64_t kb = __shfl(kbase, l, kWave);
+#pragma unroll 1
+        for (int i = lane; i < cnt; i += kWave) {
+            const uint32_t row = (uint32_t)i / wdt, col = (uint32_t)i - row * wdt;
+            const int px = x0 + (int)col, py = y0 + (int)row;
+            const double Px = (double)(256 * px + 128), Py = (double)(256 * py + 128);
+            const double e0 = A[0] * Px + Bv[0] * Py + C[0];
+            const double e1 = A[1] * Px + Bv[1] * Py + C[1];
+            const double e2 = A[2] * Px + Bv[2] * Py + C[2];
+            if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
+                ++frags;
+                unsigned long long key;
+                if (depth_key(e0, e1, e2, own, inv, z[0], z[1], z[2], prim, key))
+                    atomicMin(keys + kb + (int64_t)py * G.W + px, key);
+            }
+        }
+    }
+    if (a.sh.frag_count) {
+        // wave reduction, then one atomic per workgroup on its partial slot
+        __shared__ unsigned long long s_frag[kDirectThreads / kWave];
+        unsigned long long f = (unsigned long long)frags;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) f += __shfl_down(f, d, kWave);
+        if (lane == 0) s_frag[threadIdx.x / kWave] = f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int i = 0; i < kDirectThreads / kWave; ++i) tot += s_frag[i];
+            unsigned long long *slots = reinterpret_cast<unsigned long long *>(a.w.misc + 64);
+            if (tot) atomicAdd(&slots[blockIdx.x % kFragSlots], tot);
+        }
+    }
+}
+
+hipError_t launch_direct(const Geom &G, const Ws &w, const Shade &sh, RasterMode mode,
+                         hipStream_t st) {
+    const int64_t npix = (int64_t)G.S * G.W * G.H;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.keys), 2 * npix, 0xffffffffu, st);
+    if (e != hipSuccess) return e;
+    RasterArgs a{G, w, sh, 0, 1};
+    if (G.items > 0) {
+        const int64_t blocks = (G.items + kDirectThreads - 1) / kDirectThreads;
+        hipLaunchKernelGGL(k_direct, dim3((unsigned)blocks), dim3(kDirectThreads), 0, st, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (sh.frag_count) {
+        hipLaunchKernelGGL(k_raster_epilogue, dim3(1), dim3(kFragSlots), 0, st, w.misc,
+                           sh.frag_count, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // no EndBin inside a bin here: the per-pixel pass follows unless deferred
+    if (mode != kRasterKeysOnly) return launch_resolve_pass(G, w, sh, st);
+    return hipSuccess;
+}
+
 // Resolve of every pixel of every scene from the key buffer: one thread per
 // pixel, 64 x 4 pixel tiles per workgroup.  Tiles are numbered row-major
 // (scene by scene) and split into kXcd contiguous ranges like the bins, and
@@ -856,7 +997,9 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     if (px >= G.W || py0 >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
-    const bool split = a.sh.out_depth && a.sh.out_primid;
+    // keys in the workspace: whole-screen bins always, other bins when a
+    // depth or primitive-ID target is missing
+    const bool split = G.B != 0 && a.sh.out_depth && a.sh.out_primid;
     Resolve r[kResPPT];
     bool on[kResPPT];
 #pragma unroll
@@ -938,6 +1081,7 @@ hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipS
 hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedule, int tpb,
                          int groups, RasterMode mode, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
+    if (G.B == 0) return launch_direct(G, w, sh, mode, st);
     // DYNAMIC pops are device-scope atomics on eight counters; take enough
     // bins per pop that each workgroup pops about four times
     int64_t per = G.nbins_total / ((int64_t)groups * 4);

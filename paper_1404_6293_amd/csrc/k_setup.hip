@@ -232,6 +232,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
         setup_indices(G, first + k * kGroupThreads + tid, tin[k]);
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) setup_fetch(G, w, tin[k]);
+    if (G.B == 0) {
+        // whole-screen bins: records and boxes only, no per-bin counts
+#pragma unroll
+        for (int k = 0; k < kItemsPerThread; ++k)
+            setup_finish(G, w, first + k * kGroupThreads + tid, tin[k]);
+        return;
+    }
     // (unrolled: tin and the rectangles must stay in registers)
     BinRect br[kItemsPerThread];
     int lo = INT_MAX, hi = INT_MIN;
@@ -469,6 +476,12 @@ hipError_t launch_scatter(const Geom &G, const Ws &w, hipStream_t st) {
 // slower on the 1080p grid: the per-thread runs make the count loads
 // uncoalesced.  The one-workgroup scan stays.)
 hipError_t launch_assign(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st) {
+    if (G.B == 0) {
+        // whole-screen bins: every scene is one bin holding all its
+        // triangles, and no list is built
+        return pairs_needed ? launch_fill_u32(reinterpret_cast<uint32_t *>(pairs_needed), 2, 0u, st)
+                            : hipSuccess;
+    }
     hipError_t e = launch_scan(G, w, pairs_needed, st);
     if (e == hipSuccess) e = launch_scatter(G, w, st);
     return e;

@@ -30,8 +30,7 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (!p) return PK_ERR_INVALID_ARGUMENT;
     if (p->width < 1 || p->width > 8192 || p->height < 1 || p->height > 8192)
         return PK_ERR_INVALID_ARGUMENT;
-    if (p->bin_size == 0) return PK_ERR_UNSUPPORTED;   // whole-screen bins: not in this build
-    if (!is_pow2_bin(p->bin_size)) return PK_ERR_INVALID_ARGUMENT;
+    if (p->bin_size != 0 && !is_pow2_bin(p->bin_size)) return PK_ERR_INVALID_ARGUMENT;
     if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_DYNAMIC)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->threads_per_bin != 0 && p->threads_per_bin != 64 && p->threads_per_bin != 128 &&
@@ -46,8 +45,9 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->num_scenes < 1 || p->num_scenes > 65535) return PK_ERR_INVALID_ARGUMENT;
     if (p->instanced != 0 && p->instanced != 1) return PK_ERR_INVALID_ARGUMENT;
     if (p->persistent_groups < 0) return PK_ERR_INVALID_ARGUMENT;
-    f.nbx = (p->width + p->bin_size - 1) / p->bin_size;
-    f.nby = (p->height + p->bin_size - 1) / p->bin_size;
+    // bin size 0: one whole-screen bin per scene (Sec. 4.4)
+    f.nbx = p->bin_size ? (p->width + p->bin_size - 1) / p->bin_size : 1;
+    f.nby = p->bin_size ? (p->height + p->bin_size - 1) / p->bin_size : 1;
     f.nbins_scene = (int64_t)f.nbx * f.nby;
     f.nbins_total = f.nbins_scene * p->num_scenes;
     if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
@@ -278,6 +278,7 @@ pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_vi
     if (st != PK_OK) return st;
     if ((st = check_mesh(p, m, f)) != PK_OK) return st;
     if (!ws || !out) return PK_ERR_INVALID_ARGUMENT;
+    if (p->bin_size == 0) return PK_ERR_UNSUPPORTED;   // whole-screen bins keep no lists
     const Ws w = carve(ws, f, 0);
     out->bin_offsets = w.bin_off;
     out->bin_tris = w.pairs;

@@ -69,9 +69,23 @@ def test_invalid_params_rejected_on_host(L, bad):
     assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh()), 100) == 0
 
 
-def test_whole_screen_bins_unsupported(L):
-    p = _params(bin_size=0)
-    assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_UNSUPPORTED
+def test_whole_screen_bins(L):
+    """bin_size 0: one bin per scene, no lists (their view is refused), the
+    rest of the validation unchanged."""
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    T = 1000
+    m = _mesh(num_tris=T, num_vertices=3 * T)
+    for S in (1, 3):
+        p = _params(width=100, height=70, bin_size=0, num_scenes=S, instanced=int(S > 1))
+        nb = S
+        want = (al(32 * S * T) + al(16 * S * T) + al(8 * S * T) + al(4 * nb) + al(4 * 576)
+                + al(4 * (nb + 1)) + al(4 * nb) + al(8 * S * 100 * 70))
+        assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == want
+        v = pk.BinView()
+        assert L.pk_bin_lists(C.byref(p), C.byref(m), 1 << 20, C.byref(v)) == pk.PK_ERR_UNSUPPORTED
+    for bad in (dict(schedule=3), dict(threads_per_bin=32), dict(width=0)):
+        p = _params(bin_size=0, **bad)
+        assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
 
 
 def test_null_and_inconsistent_pointers_rejected(L):

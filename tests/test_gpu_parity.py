@@ -64,7 +64,8 @@ def test_tiny64_random(seed):
 
 
 @pytest.mark.parametrize("W,H,B,T", [(37, 29, 8, 40), (100, 70, 16, 300), (130, 66, 64, 500),
-                                     (1, 1, 8, 20), (257, 3, 32, 100), (64, 200, 8, 1000)])
+                                     (1, 1, 8, 20), (257, 3, 32, 100), (64, 200, 8, 1000),
+                                     (37, 29, 0, 40), (1, 1, 0, 20), (257, 3, 0, 100)])
 def test_ragged_screens(W, H, B, T):
     _note(f"ragged {W}x{H} B={B} T={T}")
     sc = scenes.tiny(seed=W * 31 + H, width=W, height=H, num_tris=T)
@@ -92,6 +93,13 @@ def test_metamorphic_bins_schedules_threads():
                     ref = g
                 for k in ("color", "depth", "primid", "bary"):
                     assert (g[k] == ref[k]).all(), (B, sched, tpb, k)
+    # whole-screen bins (no lists, device-scope depth test): the same image
+    for fused, defer in ((False, False), (True, False), (False, True)):
+        _note(f"metamorphic B=0 fused={fused} defer={defer}")
+        g = gpu_render(sc, bin_size=0, fuse_resolve=fused, defer_shade=defer)
+        for k in ("color", "depth", "primid", "bary"):
+            assert (g[k] == ref[k]).all(), (0, fused, defer, k)
+        assert int(g["frag_count"][0]) == int(ref["frag_count"][0])
 
 
 @pytest.mark.parametrize("B", [8, 16, 64])
@@ -145,14 +153,24 @@ def test_grid1080_full_frame():
     compare(sc, g, o)
 
 
-MODES = {"split": {}, "fused": {"fuse_resolve": True}, "defer": {"defer_shade": True}}
+MODES = {"split": {}, "fused": {"fuse_resolve": True}, "defer": {"defer_shade": True},
+         "unbinned": {"bin_size": 0}, "unbinned_defer": {"bin_size": 0, "defer_shade": True}}
+
+
+def test_grid1080_full_frame_whole_screen_bins():
+    """The grid at 1080p through the unbinned path (bin size 0)."""
+    _note("grid1080 full frame, whole-screen bins")
+    sc = scenes.grid()
+    g = gpu_render(sc, bin_size=0, want_bary=False)
+    assert int(g["frag_count"][0]) == 1920 * 1080
+    compare(sc, g, oracle.render(sc, want_bary=False), check_bary=False)
 
 
 @pytest.mark.parametrize("mode", sorted(MODES))
 def test_deferred_micropolygons_small(mode):
     _note(f"micro small deferred mode={mode}")
     sc = scenes.micro(seed=11, width=256, height=128, num_tris=60000, num_lights=3)
-    g = gpu_render(sc, bin_size=16, **MODES[mode])
+    g = gpu_render(sc, **{"bin_size": 16, **MODES[mode]})
     o = oracle.render(sc)
     compare(sc, g, o)
     np.testing.assert_allclose(g["gbuf_normal"], o["gbuf_normal"], rtol=RTOL, atol=ATOL)
@@ -170,14 +188,15 @@ def test_deferred_tie_heavy():
 def test_textured_views(mode):
     _note(f"textured instanced views mode={mode}")
     sc = scenes.diffgrid(size=96, num_views=3, nx=32, ny=16, tex_size=16)
-    g = gpu_render(sc, bin_size=16, **MODES[mode])
+    g = gpu_render(sc, **{"bin_size": 16, **MODES[mode]})
     compare(sc, g, oracle.render(sc))
 
 
-def test_batched_scenes_match_per_scene_oracle():
-    _note("batched concatenated scenes")
+@pytest.mark.parametrize("B", [8, 0])
+def test_batched_scenes_match_per_scene_oracle(B):
+    _note(f"batched concatenated scenes B={B}")
     sc = scenes.batch(num_scenes=6, size=64, tmin=50, tmax=3000)
-    g = gpu_render(sc, bin_size=8, schedule="dynamic")
+    g = gpu_render(sc, bin_size=B, schedule="dynamic")
     compare(sc, g, oracle.render(sc))
 
 
@@ -195,8 +214,9 @@ def test_empty_and_culled_inputs():
     # no triangles at all
     sc = scenes.tiny(seed=1, width=40, height=30, num_tris=1)
     sc0 = SimpleNamespace(**{**vars(sc), "num_tris": 0})
-    g = gpu_render(sc0, bin_size=8)
-    assert (g["primid"] == -1).all() and (g["depth"] == 1).all() and (g["color"] == 0).all()
+    for B in (8, 0):
+        g = gpu_render(sc0, bin_size=B)
+        assert (g["primid"] == -1).all() and (g["depth"] == 1).all() and (g["color"] == 0).all()
     # every way a triangle gets dropped
     W = H = 32
     P = []
@@ -216,9 +236,10 @@ def test_empty_and_culled_inputs():
                          instanced=False, uv=None, normal=None, texture=None, lights=None,
                          shading="gouraud")
     o = oracle.render(sc)
-    g = gpu_render(sc, bin_size=8)
-    compare(sc, g, o)
-    assert set(np.unique(g["primid"])) <= {-1, 0}
+    for B in (8, 0):
+        g = gpu_render(sc, bin_size=B)
+        compare(sc, g, o)
+        assert set(np.unique(g["primid"])) <= {-1, 0}
     # w <= 0 through a matrix that puts w = -z
     mvp = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, -1, 0], np.float32)
     sc2 = SimpleNamespace(**{**vars(sc), "mvp": mvp})
@@ -252,7 +273,7 @@ def test_maximum_screen_and_guard_band():
                          instanced=False, uv=None, normal=None, texture=None, lights=None,
                          shading="gouraud")
     o = oracle.render(sc, want_bary=False)     # about 25 s of CPU
-    for B in (8, 64):
+    for B in (8, 64, 0):
         _note(f"maximum screen B={B}")
         g = gpu_render(sc, bin_size=B, want_bary=False)
         compare(sc, g, o, check_bary=False)
