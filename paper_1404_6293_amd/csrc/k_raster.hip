@@ -77,8 +77,12 @@ __device__ inline void resolve_fetch(const RasterArgs &a, int32_t s, int64_t ite
     unpack_xy(q0.x, q0.y, q0.z, q0.w, w4, X, Y);
     r.xy = make_uint4((uint32_t)X[0], (uint32_t)Y[0], (uint32_t)X[1], (uint32_t)Y[1]);
     r.xy2 = make_uint2((uint32_t)X[2], (uint32_t)Y[2]);
-    const float4 iw = a.w.iw[item];
-    r.iw[0] = iw.x; r.iw[1] = iw.y; r.iw[2] = iw.z;
+    if (G.mvp) {
+        const float4 iw = a.w.iw[item];
+        r.iw[0] = iw.x; r.iw[1] = iw.y; r.iw[2] = iw.z;
+    } else {
+        r.iw[0] = r.iw[1] = r.iw[2] = 1.0f;   // w = 1 exactly without a matrix
+    }
     r.sinv = signed_inv_area(area2(X, Y));
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.v[k] = (int32_t)(vbase_scene + 3 * (int64_t)r.t + k);

@@ -165,7 +165,8 @@ __device__ inline uint64_t setup_finish(const Geom &G, const Ws &w, int64_t item
             dst[0] = make_uint4(xy[0], xy[1], xy[2], xy[3]);
             dst[1] = make_uint4(xy[4], __float_as_uint(z[0]), __float_as_uint(z[1]),
                                 __float_as_uint(z[2]));
-            if (!G.idx) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
+            // (without a matrix 1/w is exactly 1 and the entry is not needed)
+            if (!G.idx && G.mvp) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
         }
     }
     w.bbox[item] = bb;

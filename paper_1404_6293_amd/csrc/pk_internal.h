@@ -108,8 +108,9 @@ constexpr int32_t kBadVertex = (int32_t)0x80000000;
 struct Ws {
     VtxRec *vtx;               // [S or 1][V] for indexed meshes, else unused
     TriRec *rec;               // [items]
-    float4 *iw;                // [items] 1/w0, 1/w1, 1/w2 (unindexed meshes; indexed
-                               // ones read 1/w from the vertex records)
+    float4 *iw;                // [items] 1/w0, 1/w1, 1/w2 (unindexed meshes with a
+                               // matrix; indexed ones read 1/w from the vertex
+                               // records, and without a matrix it is 1)
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
