@@ -846,10 +846,13 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     EdgeTri t;
     t.cnt = 0;
     int64_t kbase = 0;   // first key of the triangle's scene
-    if (item < G.items && a.w.bbox[item] != kEmptyKey) {
+    // the record load does not wait for the box (a culled triangle's record
+    // is simply not used)
+    const bool inb = item < G.items;
+    RawTri raw;
+    fetch_tri(a.w, inb ? (int32_t)item : 0, raw);
+    if (inb && a.w.bbox[item] != kEmptyKey) {
         const ItemRef r = item_ref(G, item);
-        RawTri raw;
-        fetch_tri(a.w, (int32_t)item, raw);
         decode_tri(raw, item, item - r.t, 0, 0, G.W, G.H, G.W, G.H, t);
         kbase = (int64_t)r.s * G.W * G.H;
     }
