@@ -32,8 +32,9 @@ WORKLOADS = {
                           "shared vertices), perspective camera, Gouraud, 16x16 bins",
                      bin=16, schedule="direct_map", tpb=0, bary=False),
     "micro8m": dict(desc="1920x1080, 8,388,608 independent micropolygons (log-normal area "
-                         "around 0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
-                    bin=16, schedule="direct_map", tpb=0, bary=False),
+                         "around 0.5 px^2), deferred shading over an fp32 G-buffer, 1 light, "
+                         "whole-screen bins (the autotuned choice)",
+                    bin=0, schedule="direct_map", tpb=0, bary=False),
     "batch256": dict(desc="256 scenes at 256x256, log-uniform 1K-200K random triangles each "
                           "(edge ~ log-normal around 4 px), one batched launch",
                      bin=16, schedule="direct_map", tpb=0, bary=False),
@@ -55,19 +56,28 @@ def make_scene(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def bin_kernel_algorithmic_bytes(sc, npairs: int) -> int:
+def bin_kernel_algorithmic_bytes(sc, npairs: int, B: int) -> int:
     """Algorithmic bytes of one launch of the per-bin coverage + depth-test
     kernel (k_raster, keys written for the per-pixel pass): per (bin, triangle)
     pair the 4-byte list entry and the 36 bytes that coverage and depth need
     of the triangle (three snapped vertices: x, y, z as 32-bit words); per bin
     its two 4-byte CSR offsets; per pixel the 8-byte winning (depth, primitive)
-    key it writes.  The setup record's actual size (64 B) is an
+    key it writes.  The setup record's actual size (32 B) is an
     implementation choice and is not counted."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
     npix = S * sc.width * sc.height
-    B = int(getattr(sc, "bin_size", 16))
     nbins = S * (-(-sc.width // B)) * (-(-sc.height // B))
     return 40 * npairs + 8 * nbins + 8 * npix
+
+
+def direct_kernel_algorithmic_bytes(sc, tris: int) -> int:
+    """Algorithmic bytes of the unbinned raster (whole-screen bins: the key
+    clear and k_direct): per input triangle the 36 bytes that coverage and
+    depth need (three snapped vertices: x, y, z as 32-bit words); per pixel
+    the 8-byte (depth, primitive) key cleared and left for the per-pixel
+    pass (16 B).  There is no bin list."""
+    S = int(getattr(sc, "num_scenes", 1) or 1)
+    return 36 * tris + 16 * S * sc.width * sc.height
 
 
 def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
@@ -326,7 +336,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="grid1080", choices=sorted(WORKLOADS))
-    ap.add_argument("--bin", type=int, default=0)
+    ap.add_argument("--bin", type=int, default=-1,
+                    help="bin size (0 = whole-screen bins); default: the workload's")
     ap.add_argument("--schedule", default="")
     ap.add_argument("--tpb", type=int, default=-1)
     ap.add_argument("--streams", type=int, default=2,
@@ -363,7 +374,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     sc = make_scene(args.workload)
-    B = args.bin or wl["bin"]
+    B = wl["bin"] if args.bin < 0 else args.bin
     sched = args.schedule or wl["schedule"]
     tpb = wl["tpb"] if args.tpb < 0 else args.tpb
     bary = args.bary or wl["bary"]
@@ -450,9 +461,13 @@ def main():
     mtris = tris / (ms * 1e-3) / 1e6
     gfrags = frags / (ms * 1e-3) / 1e9
 
-    alg_bin = bin_kernel_algorithmic_bytes(sc, npairs)
+    alg_bin = bin_kernel_algorithmic_bytes(sc, npairs, B) if B else 0
     alg_px = shade_pass_algorithmic_bytes(sc, covered, bary)
-    if fused:
+    if B == 0:
+        # whole-screen bins: the key clear and the unbinned raster
+        kern, t_ms = "k_direct", stage["raster"]
+        alg = direct_kernel_algorithmic_bytes(sc, tris)
+    elif fused:
         # one kernel: no key written or read back
         kern, t_ms = "k_raster (fused resolve)", stage["raster"]
         alg = alg_bin + alg_px - 16 * S * sc.width * sc.height
@@ -461,7 +476,7 @@ def main():
     achieved = alg / (t_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if fused else profiled_traffic(args.workload, "k_raster"),
+                "traffic": None if fused else profiled_traffic(args.workload, kern),
                 "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
     try:
         roofline["measured_stream_gbs"] = round(measured_stream_bandwidth(torch), 1)
