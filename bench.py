@@ -242,6 +242,23 @@ def bench_micro(reps: int = 10) -> dict:
             "gfrags_per_s": round(frags / ms / 1e6, 3)}
 
 
+def bench_ablation(reps: int = 5) -> dict:
+    """The schedule ablation of Sec. 7.2 on grid1080: whole-screen bins (the
+    unbinned baseline) and every bin size with each schedule, the resolve in
+    its own pass or fused into the bin kernel.  One whole frame per
+    configuration on one stream (median of HIP-event timings, ms); every
+    configuration renders the same image."""
+    from paper_1404_6293_amd import autotune, pk, scenes
+    dev = pk.DeviceScene(scenes.grid())
+    cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64),
+                                     schedules=("direct_map", "load_balance", "dynamic"),
+                                     threads=(0,), fused=(False, True)))
+    best, times = autotune.autotune(dev, cands=cands, reps=reps, use_cache=False)
+    return {"workload": "grid1080", "frame_ms": {k: round(v, 4) for k, v in times.items()},
+            "fastest": {"bin_size": best.bin_size, "schedule": best.schedule,
+                        "fused_resolve": best.fuse_resolve}}
+
+
 def measured_stream_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:
     """GB/s of a plain device-to-device copy of `mib` MiB (read + write bytes
     over time), buffers far larger than the 256 MB MALL: the achievable HBM
@@ -512,6 +529,8 @@ def main():
         out["backward"] = bench_backward()
         print("bench: micropolygons", file=sys.stderr, flush=True)
         out["micro"] = bench_micro()
+        print("bench: schedule ablation", file=sys.stderr, flush=True)
+        out["ablation"] = bench_ablation()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(sc)
         cb["host"] = platform.processor() or platform.machine()
