@@ -97,15 +97,20 @@ def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the HIP sources and the public header, so that a profiled
-    traffic figure is only reported for the kernels it was measured on."""
+    """SHA-256 over the HIP sources and the public header with comments and
+    whitespace removed, so that a profiled traffic figure is only reported
+    for the code it was measured on (and survives comment edits)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1404_6293_amd", "csrc")
     for path in sorted(os.listdir(csrc)) + ["../../include/pk.h"]:
-        with open(os.path.join(csrc, path), "rb") as f:
-            h.update(os.path.basename(path).encode())
-            h.update(f.read())
+        with open(os.path.join(csrc, path), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(os.path.basename(path).encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -6,17 +6,24 @@
 // buffer of Sec. 5.2.4), here as 64-bit (depth, primitive) keys in LDS
 // updated with ds_min_u64, which makes the test order-independent.
 //
-// Work inside a bin is balanced per fragment candidate, not per triangle:
-// a chunk of TPB triangles is staged in LDS, each contributes the pixels of
-// its bounding box clipped to the bin, a workgroup prefix sum lays those
-// candidates end to end, and every thread tests candidates j, j+TPB, ...,
-// finding its triangle by binary search over the prefix sums.  Tiny and
-// large triangles therefore cost the same per candidate.
+// Work inside a bin: each wave takes its own chunks of 64 triangles of the
+// bin list (no workgroup barrier until EndBin).  When every box of a chunk,
+// clipped to the bin, holds at most 12 pixels, each lane walks its own
+// triangle's candidates with incrementally stepped edge functions; otherwise
+// the wave covers the boxes with 2x2 pixel quads laid end to end and hands
+// them out 64 at a time, finding each quad's triangle from start marks in
+// LDS, so large and small triangles share the lanes evenly.
 //
 // Schedules (Sec. 4.3 directives; Sec. 6 work-group organization):
-//   LOAD_BALANCE  one workgroup per bin (hardware dispatcher balances)
-//   DIRECT_MAP    G workgroups, bin b on workgroup b mod G (pre-scheduled)
-//   DYNAMIC       G workgroups pop bins from a device counter
+//   LOAD_BALANCE  one workgroup per bin (the hardware dispatcher balances)
+//   DIRECT_MAP    G persistent workgroups, bins pre-assigned in contiguous
+//                 ranges per die (pre-scheduling, Sec. 5.2.3), with the
+//                 records and pair numbers of the next chunks prefetched
+//   DYNAMIC       G persistent workgroups pop batches of bins from per-die
+//                 device counters
+// Whole-screen bins (bin size 0) skip the bin lists: k_direct rasterizes
+// every triangle on its own with a device-scope depth test, and k_resolve
+// reads the keys from the workspace.
 #include "pk_internal.h"
 
 #pragma clang fp contract(off)
