@@ -459,6 +459,27 @@ def main():
         r.frame()
     torch.cuda.synchronize()
     dt1 = time.perf_counter() - t1
+    # cold frames: a 512 MB scratch write before each flushes the 256 MB
+    # last-level cache (MALL), so the frame reads its inputs from HBM; the
+    # median of HIP-event timings around the frame alone
+    cold_ms = None
+    try:
+        scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        cold = []
+        for _ in range(min(K, 20)):
+            scratch.fill_(1)
+            c0 = torch.cuda.Event(enable_timing=True)
+            c1 = torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            r.frame()
+            c1.record(stream)
+            torch.cuda.synchronize()
+            cold.append(c0.elapsed_time(c1))
+        cold.sort()
+        cold_ms = cold[len(cold) // 2]
+        del scratch
+    except RuntimeError:      # not enough free memory for the scratch buffer
+        pass
     # the same K frames again with HIP events around each stage on the launch
     # stream: per-stage (per-kernel) durations for the roofline
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
@@ -525,6 +546,7 @@ def main():
                           "value": round(tris / (dt1 * 1e3 / K * 1e-3) / 1e6, 2)},
         "gfrags_per_s": round(gfrags, 3), "fragments_per_frame": frags,
         "bin_pairs_per_frame": npairs, "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "cold_ms_per_frame": None if cold_ms is None else round(cold_ms, 4),
         "roofline": roofline,
     }
     if not args.no_extras and args.workload == "grid1080":
