@@ -131,6 +131,23 @@ def profiled_traffic(workload: str, kernel: str):
     return None
 
 
+def profiled_valu_busy(workload: str, kernel: str):
+    """Percent of the time the VALU was busy during `kernel` (rocprofv3's
+    VALUBusy) from the committed summary of `workload`, or None when there is
+    none or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_kernels.md")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    for line in open(path):
+        # "valubusy <kernel> <percent> percent sources <sha256>"
+        parts = line.split()
+        if (len(parts) == 6 and parts[0] == "valubusy" and parts[1] == kernel
+                and parts[5] == want):
+            return float(parts[2])
+    return None
+
+
 def cpu_baseline(sc, budget_s: float = 12.0):
     """The oracle as it stands (single-threaded C) timed on this host on the
     same workload: whole scenes, one after another, until the time budget is
@@ -520,7 +537,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if fused else profiled_traffic(args.workload, kern),
-                "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4)}
+                "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4),
+                "valu_busy_pct": None if fused else profiled_valu_busy(args.workload, kern)}
     try:
         roofline["measured_stream_gbs"] = round(measured_stream_bandwidth(torch), 1)
         roofline["frac_of_measured"] = round(achieved / roofline["measured_stream_gbs"], 4)
