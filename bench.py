@@ -201,7 +201,8 @@ def bench_batched(reps: int = 10) -> dict:
     from paper_1404_6293_amd import autotune, pk, scenes
     sc = scenes.batch()
     dev = pk.DeviceScene(sc)
-    cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64), schedules=("direct_map", "dynamic"),
+    cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64),
+                                     schedules=("direct_map", "dynamic", "split"),
                                      threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True
@@ -273,7 +274,7 @@ def bench_ablation(reps: int = 5) -> dict:
     from paper_1404_6293_amd import autotune, pk, scenes
     dev = pk.DeviceScene(scenes.grid())
     cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64),
-                                     schedules=("direct_map", "load_balance", "dynamic"),
+                                     schedules=("direct_map", "load_balance", "dynamic", "split"),
                                      threads=(0,), fused=(False, True)))
     best, times = autotune.autotune(dev, cands=cands, reps=reps, use_cache=False)
     return {"workload": "grid1080", "frame_ms": {k: round(v, 4) for k, v in times.items()},

@@ -91,8 +91,13 @@ typedef enum {
  * "Work-Group Organization"). */
 typedef enum {
     PK_SCHED_LOAD_BALANCE = 0, /* one workgroup per bin, hardware dispatcher balances */
-    PK_SCHED_DIRECT_MAP = 1,   /* G persistent workgroups; bin b runs on workgroup b mod G */
-    PK_SCHED_DYNAMIC = 2       /* G persistent workgroups pop bins from a device counter */
+    PK_SCHED_DIRECT_MAP = 1,   /* G persistent workgroups, bins pre-assigned to them */
+    PK_SCHED_DYNAMIC = 2,      /* G persistent workgroups pop bins from device counters */
+    PK_SCHED_SPLIT = 3         /* heavy bins split (the All directive with a tile split
+                                  size, Sec. 4.3): a bin with more than split_size pairs
+                                  becomes several work items on different workgroups,
+                                  whose depth tiles merge by device-scope 64-bit atomic
+                                  min; G persistent workgroups take the work items */
 } pk_schedule;
 
 typedef enum {
@@ -133,7 +138,9 @@ typedef struct {               /* [host] */
                                   S*ceil(W/64)*ceil(H/4) < 2^31 */
     int32_t instanced;         /* S > 1 only: 1 = S views (one MVP each) of the same
                                   mesh; 0 = S concatenated scenes (scene_*_off) */
-    int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC workgroup count; 0 = auto */
+    int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC / SPLIT workgroup count; 0 = auto */
+    int32_t split_size;        /* PK_SCHED_SPLIT: most (bin, triangle) pairs per work
+                                  item, >= 1; 0 = 256.  Ignored by other schedules */
 } pk_params;
 
 typedef struct {                 /* [host] struct of device pointers */
@@ -193,6 +200,8 @@ pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream)
  * triangle) pairs.  If it exceeds pair_capacity, no list is written and the
  * following pk_raster_shade writes no pixel; call again with a larger
  * workspace.  The order of triangles inside one bin is unspecified.
+ * With PK_SCHED_SPLIT it also numbers the work items (each bin's list cut
+ * into pieces of at most split_size pairs) for pk_raster_shade.
  * With bin_size 0 every scene is one bin that holds all of its triangles
  * (Sec. 4.4: full-screen bins need no assignment): nothing is built and
  * *pairs_needed receives 0. */
@@ -211,7 +220,9 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
  * full-screen bins, Sec. 7); the per-pixel resolve then always runs as its
  * own pass (also under PK_FLAG_FUSE_RESOLVE, since there is no per-bin EndBin),
  * and under PK_FLAG_DEFER_SHADE the keys stay in the workspace.  The image
- * is the same as with any bin size. */
+ * is the same as with any bin size.  PK_SCHED_SPLIT likewise keeps the keys
+ * in the workspace (pieces of one bin merge there) and resolves in a
+ * per-pixel pass; it excludes PK_FLAG_FUSE_RESOLVE. */
 pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, void *ws,
                           const pk_targets *out, void *stream);
 

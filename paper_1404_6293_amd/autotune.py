@@ -26,7 +26,7 @@ CACHE_ENV = "PK_AUTOTUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pk_autotune.json")
 
 BIN_SIZES = (0, 8, 16, 32, 64)   # 0: whole-screen bins (unbinned, Sec. 4.4)
-SCHEDULES = ("direct_map", "load_balance", "dynamic")
+SCHEDULES = ("direct_map", "load_balance", "dynamic", "split")
 THREADS = (64, 128, 256)
 
 
@@ -37,6 +37,8 @@ def candidates(bins: Iterable[int] = BIN_SIZES, schedules: Iterable[str] = SCHED
         # fusion: one candidate
         yield pk.RenderConfig(bin_size=0)
     for b, s, t, f in itertools.product([b for b in bins if b], schedules, threads, fused):
+        if s == "split" and f:
+            continue                      # pieces of a bin merge before the resolve
         yield pk.RenderConfig(bin_size=b, schedule=s, threads_per_bin=t, fuse_resolve=f)
 
 

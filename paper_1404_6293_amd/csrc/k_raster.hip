@@ -471,6 +471,11 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         prefetch_tri(a.w, id_n, raw_n);
         advance_nn();
     }
+    // PK_SCHED_SPLIT: work-item numbers of the bins (read-only here: scalar
+    // loads) and their count
+    const ConstI32 *voff = (const ConstI32 *)a.w.vbin_off;
+    const int64_t nwork = (!piped && a.w.split && !overflow) ? (int64_t)voff[nb] : 0;
+    int32_t piece = 0;
     // DYNAMIC: current queue (range) and the bins of the last batch taken
     int qx = xcd, q_tried = 0;
     int64_t batch_beg = 0, batch_end = 0;
@@ -510,6 +515,20 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         } else if (piped) {
             bin = dm_bin(it);
             if (bin < 0) break;
+        } else if (a.w.split) {
+            // PK_SCHED_SPLIT: work item v is piece `piece` of the last bin
+            // whose first work item is at or before v (bins without pairs
+            // have none and share the next bin's first number)
+            if (overflow) break;
+            const int64_t v = blockIdx.x + it * (int64_t)gridDim.x;
+            if (v >= nwork) break;
+            int64_t lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if ((int64_t)voff[mid] <= v) lo = mid; else hi = mid - 1;
+            }
+            bin = lo;
+            piece = (int32_t)(v - voff[lo]);
         } else {
             if (it > 0 || lane_in_xcd >= r_len) break;
             bin = r_beg + lane_in_xcd;
@@ -527,9 +546,15 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
 
         for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
+        bool shared = false;   // PK_SCHED_SPLIT: the bin has several pieces
         if (!overflow && !piped) {
             lbeg = a.w.bin_off[bin];
             lend = a.w.bin_off[bin + 1];
+            if (a.w.split) {
+                shared = lend - lbeg > a.w.split;
+                lbeg += piece * a.w.split;
+                lend = min(lend, lbeg + a.w.split);
+            }
         }
         __syncthreads();
 
@@ -750,7 +775,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             // as the final depth and primitive-ID targets when the caller
             // has both (the two halves of the key), else as keys
             const int64_t sb = (int64_t)s * G.W * G.H;
-            const bool split = a.sh.out_depth && a.sh.out_primid;
+            const bool split = !a.w.split && a.sh.out_depth && a.sh.out_primid;
 #pragma unroll 1
             for (int i = tid; i < NPIX; i += TPB) {
                 const int lx = i % B, ly = i / B;
@@ -760,6 +785,9 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     if (split) {
                         a.sh.out_depth[p] = k == kEmptyKey ? 1.0f : __uint_as_float((uint32_t)(k >> 32));
                         a.sh.out_primid[p] = k == kEmptyKey ? -1 : (int32_t)(uint32_t)k;
+                    } else if (shared) {
+                        // pieces of one bin merge in the cleared key buffer
+                        if (k != kEmptyKey) atomicMin(&a.w.keys[p], k);
                     } else {
                         a.w.keys[p] = k;
                     }
@@ -1011,9 +1039,9 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     if (px >= G.W || py0 >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
-    // keys in the workspace: whole-screen bins always, other bins when a
-    // depth or primitive-ID target is missing
-    const bool split = G.B != 0 && a.sh.out_depth && a.sh.out_primid;
+    // keys in the workspace: whole-screen bins and split bins always, other
+    // bins when a depth or primitive-ID target is missing
+    const bool split = G.B != 0 && !a.w.split && a.sh.out_depth && a.sh.out_primid;
     Resolve r[kResPPT];
     bool on[kResPPT];
 #pragma unroll
@@ -1105,6 +1133,13 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
     if (schedule != PK_SCHED_LOAD_BALANCE) nblk = groups < G.nbins_total ? groups : G.nbins_total;
     const dim3 grid((unsigned)nblk);
     hipError_t e = hipSuccess;
+    if (w.split) {
+        // pieces of a bin merge by atomic min, bins without pairs have no
+        // work item: start from empty keys
+        e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.keys), 2 * (int64_t)G.S * G.W * G.H,
+                            0xffffffffu, st);
+        if (e != hipSuccess) return e;
+    }
     if (mode != kRasterFused) {
         e = launch_shade<kKeysOnly>(a, tpb, grid, st);
     } else {

@@ -321,16 +321,17 @@ constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kScanThreads * kScanPer;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan(Ws w, int64_t n, int64_t *pairs_needed) {
-    __shared__ uint32_t s_v[kScanTile];
-    __shared__ int64_t s_part[kScanThreads / kWave];
+// Exclusive prefix sum of get(0..n-1) by the whole (single) workgroup, tile
+// by tile; put(i, prefix) stores each result.  Returns the total.
+template <class Get, class Put>
+__device__ inline int64_t block_scan(int64_t n, Get get, Put put, uint32_t *s_v, int64_t *s_part) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     int64_t carry = 0;
     for (int64_t t0 = 0; t0 < n; t0 += kScanTile) {
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const int64_t i = t0 + k * kScanThreads + tid;
-            s_v[k * kScanThreads + tid] = i < n ? w.bin_count[i] : 0u;
+            s_v[k * kScanThreads + tid] = i < n ? get(i) : 0u;
         }
         __syncthreads();
         uint32_t v[kScanPer];
@@ -355,26 +356,40 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Ws w, int64_t n, int64_t 
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             s_v[tid * kScanPer + k] = (uint32_t)run;   // wraps only when it overflows,
-            run += v[k];                                // which the flag below reports
+            run += v[k];                                // which the caller reports
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const int64_t i = t0 + k * kScanThreads + tid;
-            if (i < n) {
-                const int32_t o = (int32_t)s_v[k * kScanThreads + tid];
-                w.bin_off[i] = o;
-                w.cursor[i] = o;
-            }
+            if (i < n) put(i, (int32_t)s_v[k * kScanThreads + tid]);
         }
         carry += total;
         __syncthreads();
     }
-    if (tid == 0) {
-        const bool fits = carry <= w.pair_capacity;
+    return carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(Ws w, int64_t n, int64_t *pairs_needed) {
+    __shared__ uint32_t s_v[kScanTile];
+    __shared__ int64_t s_part[kScanThreads / kWave];
+    const int64_t carry = block_scan(
+        n, [&](int64_t i) { return w.bin_count[i]; },
+        [&](int64_t i, int32_t o) { w.bin_off[i] = o; w.cursor[i] = o; }, s_v, s_part);
+    const bool fits = carry <= w.pair_capacity;
+    if (threadIdx.x == 0) {
         w.bin_off[n] = fits ? (int32_t)carry : 0;
         w.misc[1] = fits ? 0u : 1u;
         if (pairs_needed) *pairs_needed = carry;
+    }
+    if (w.split && fits) {
+        // PK_SCHED_SPLIT: bin b is ceil(count / split) work items (none when
+        // empty); vbin_off numbers them
+        const uint32_t sp = (uint32_t)w.split;
+        const int64_t works = block_scan(
+            n, [&](int64_t i) { return (w.bin_count[i] + sp - 1u) / sp; },
+            [&](int64_t i, int32_t o) { w.vbin_off[i] = o; }, s_v, s_part);
+        if (threadIdx.x == 0) w.vbin_off[n] = (int32_t)works;
     }
 }
 

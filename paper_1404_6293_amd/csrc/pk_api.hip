@@ -20,6 +20,7 @@ struct Frame {
     int64_t items = 0;
     int64_t vrecs = 0;     // snapped vertex records (indexed meshes)
     bool indexed = false;
+    int32_t split = 0;     // PK_SCHED_SPLIT with bins: pairs per work item
     int64_t npix = 0;      // S * W * H
     int64_t nbins_scene = 0;
     int64_t nbins_total = 0;
@@ -31,8 +32,14 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->width < 1 || p->width > 8192 || p->height < 1 || p->height > 8192)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->bin_size != 0 && !is_pow2_bin(p->bin_size)) return PK_ERR_INVALID_ARGUMENT;
-    if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_DYNAMIC)
+    if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_SPLIT)
         return PK_ERR_INVALID_ARGUMENT;
+    if (p->split_size < 0) return PK_ERR_INVALID_ARGUMENT;
+    // pieces of a bin merge in the workspace: no resolve inside the bin kernel
+    if (p->schedule == PK_SCHED_SPLIT && (p->flags & PK_FLAG_FUSE_RESOLVE))
+        return PK_ERR_INVALID_ARGUMENT;
+    f.split = (p->schedule == PK_SCHED_SPLIT && p->bin_size != 0)
+                  ? (p->split_size ? p->split_size : 256) : 0;
     if (p->threads_per_bin != 0 && p->threads_per_bin != 64 && p->threads_per_bin != 128 &&
         p->threads_per_bin != 256)
         return PK_ERR_INVALID_ARGUMENT;
@@ -74,7 +81,7 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
 }
 
 struct Layout {
-    size_t vtx, rec, iw, bbox, bin_count, bin_off, cursor, misc, keys, pairs, total;
+    size_t vtx, rec, iw, bbox, bin_count, bin_off, vbin_off, cursor, misc, keys, pairs, total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
@@ -89,6 +96,7 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
+    L.vbin_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)(f.split ? f.nbins_total + 1 : 0));
     L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix);
     L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
     L.total = o;
@@ -107,6 +115,8 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.bbox = reinterpret_cast<uint64_t *>(b + L.bbox);
     w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
     w.bin_off = reinterpret_cast<int32_t *>(b + L.bin_off);
+    w.vbin_off = f.split ? reinterpret_cast<int32_t *>(b + L.vbin_off) : nullptr;
+    w.split = f.split;
     w.cursor = reinterpret_cast<int32_t *>(b + L.cursor);
     w.keys = reinterpret_cast<unsigned long long *>(b + L.keys);
     w.misc = reinterpret_cast<uint32_t *>(b + L.misc);

@@ -114,6 +114,8 @@ struct Ws {
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
+    int32_t *vbin_off;         // [nbins_total + 1] first work item of each bin
+                               // (PK_SCHED_SPLIT only, else NULL)
     int32_t *cursor;           // [nbins_total], between bin_count and misc: next
                                // free slot of each bin (set by the scan)
     uint32_t *misc;            // [kMiscWords], right after bin_count: [1] pair
@@ -124,6 +126,7 @@ struct Ws {
     unsigned long long *keys;  // [S][H][W] winning (depth, primitive) keys
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
+    int32_t split;             // PK_SCHED_SPLIT: pairs per work item; 0 otherwise
 };
 
 struct Shade {

@@ -20,14 +20,14 @@ LIB_PATH = os.path.join(_HERE, "libpk.so")
 
 # enums of pk.h
 PK_OK, PK_ERR_INVALID_ARGUMENT, PK_ERR_CAPACITY, PK_ERR_HIP, PK_ERR_UNSUPPORTED = range(5)
-PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC = range(3)
+PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC, PK_SCHED_SPLIT = range(4)
 PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED = range(3)
 PK_FLAG_COUNT_FRAGS = 1
 PK_FLAG_FUSE_RESOLVE = 2
 PK_FLAG_DEFER_SHADE = 4
 
 SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIRECT_MAP,
-             "dynamic": PK_SCHED_DYNAMIC}
+             "dynamic": PK_SCHED_DYNAMIC, "split": PK_SCHED_SPLIT}
 SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
             "deferred": PK_SHADE_DEFERRED}
 
@@ -45,7 +45,7 @@ class Params(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bin_size", C.c_int32),
                 ("schedule", C.c_int32), ("threads_per_bin", C.c_int32), ("shading", C.c_int32),
                 ("flags", C.c_int32), ("num_scenes", C.c_int32), ("instanced", C.c_int32),
-                ("persistent_groups", C.c_int32)]
+                ("persistent_groups", C.c_int32), ("split_size", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -170,6 +170,7 @@ class RenderConfig:
     schedule: str = "direct_map"
     threads_per_bin: int = 0
     persistent_groups: int = 0
+    split_size: int = 0            # schedule "split": pairs per work item (0 = 256)
     count_frags: bool = False
     want_bary: bool = True
     fuse_resolve: bool = False
@@ -268,7 +269,7 @@ class Renderer:
                              (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
                              | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0)
                              | (PK_FLAG_DEFER_SHADE if cfg.defer_shade else 0), self.S,
-                             int(d.instanced), int(cfg.persistent_groups))
+                             int(d.instanced), int(cfg.persistent_groups), int(cfg.split_size))
         self.mesh = d.mesh()
         self.attribs = d.attribs()
         S, H, W = self.S, self.H, self.W

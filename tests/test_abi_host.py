@@ -59,7 +59,8 @@ def _mesh(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
-    dict(bin_size=-8), dict(schedule=3), dict(schedule=-1), dict(threads_per_bin=32),
+    dict(bin_size=-8), dict(schedule=4), dict(schedule=-1), dict(threads_per_bin=32),
+    dict(split_size=-1), dict(schedule=3, flags=2),
     dict(threads_per_bin=512), dict(shading=3), dict(flags=8), dict(flags=6), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
@@ -83,7 +84,7 @@ def test_whole_screen_bins(L):
         assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == want
         v = pk.BinView()
         assert L.pk_bin_lists(C.byref(p), C.byref(m), 1 << 20, C.byref(v)) == pk.PK_ERR_UNSUPPORTED
-    for bad in (dict(schedule=3), dict(threads_per_bin=32), dict(width=0)):
+    for bad in (dict(schedule=4), dict(threads_per_bin=32), dict(width=0)):
         p = _params(bin_size=0, **bad)
         assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
 
@@ -161,6 +162,21 @@ def test_workspace_bytes_arithmetic(L):
     assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh(num_tris=-1)), 0) == 0
     assert L.pk_workspace_bytes(C.byref(p), C.byref(m), -5) == 0
     assert L.pk_workspace_bytes(C.byref(p), None, 0) == 0
+
+
+def test_split_schedule_workspace(L):
+    """PK_SCHED_SPLIT adds one work-item number per bin (+1) to the
+    workspace; other schedules and whole-screen bins do not."""
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    m = _mesh(num_tris=1000, num_vertices=3000)
+    base = L.pk_workspace_bytes(C.byref(_params(width=100, height=70, bin_size=16, schedule=1)),
+                                C.byref(m), 0)
+    for sp in (0, 1, 500):
+        p = _params(width=100, height=70, bin_size=16, schedule=3, split_size=sp)
+        assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == base + al(4 * 36)
+    p0 = _params(width=100, height=70, bin_size=0, schedule=3)
+    assert L.pk_workspace_bytes(C.byref(p0), C.byref(m), 0) == L.pk_workspace_bytes(
+        C.byref(_params(width=100, height=70, bin_size=0)), C.byref(m), 0)
 
 
 def test_bin_lists_view_points_into_workspace(L):

@@ -93,6 +93,17 @@ def test_metamorphic_bins_schedules_threads():
                     ref = g
                 for k in ("color", "depth", "primid", "bary"):
                     assert (g[k] == ref[k]).all(), (B, sched, tpb, k)
+    # heavy bins split into pieces of at most split_size pairs (one piece per
+    # bin through many): the same image
+    for B in (8, 32):
+        for sp, groups in ((1, 0), (7, 7), (64, 0)):
+            for defer in (False, True):
+                _note(f"metamorphic B={B} split={sp} groups={groups} defer={defer}")
+                g = gpu_render(sc, bin_size=B, schedule="split", split_size=sp,
+                               persistent_groups=groups, defer_shade=defer)
+                for k in ("color", "depth", "primid", "bary"):
+                    assert (g[k] == ref[k]).all(), (B, "split", sp, defer, k)
+                assert int(g["frag_count"][0]) == int(ref["frag_count"][0])
     # whole-screen bins (no lists, device-scope depth test): the same image
     for fused, defer in ((False, False), (True, False), (False, True)):
         _note(f"metamorphic B=0 fused={fused} defer={defer}")
@@ -181,7 +192,10 @@ def test_deferred_tie_heavy():
     """Micropolygons with depth quantised to 8 levels: many equal depths, the
     smaller triangle index must win everywhere."""
     sc = scenes.micro(seed=12, width=200, height=120, num_tris=80000, z_levels=8)
-    compare(sc, gpu_render(sc, bin_size=32, schedule="dynamic"), oracle.render(sc))
+    o = oracle.render(sc)
+    compare(sc, gpu_render(sc, bin_size=32, schedule="dynamic"), o)
+    # pieces of a bin meet at equal depths too: the smaller index still wins
+    compare(sc, gpu_render(sc, bin_size=32, schedule="split", split_size=40), o)
 
 
 @pytest.mark.parametrize("mode", sorted(MODES))
@@ -192,11 +206,11 @@ def test_textured_views(mode):
     compare(sc, g, oracle.render(sc))
 
 
-@pytest.mark.parametrize("B", [8, 0])
-def test_batched_scenes_match_per_scene_oracle(B):
-    _note(f"batched concatenated scenes B={B}")
+@pytest.mark.parametrize("B,sched", [(8, "dynamic"), (0, "dynamic"), (8, "split")])
+def test_batched_scenes_match_per_scene_oracle(B, sched):
+    _note(f"batched concatenated scenes B={B} {sched}")
     sc = scenes.batch(num_scenes=6, size=64, tmin=50, tmax=3000)
-    g = gpu_render(sc, bin_size=B, schedule="dynamic")
+    g = gpu_render(sc, bin_size=B, schedule=sched, split_size=16)
     compare(sc, g, oracle.render(sc))
 
 
