@@ -68,6 +68,7 @@ def _load():
                "orc_setup": (C.c_int, [P, P, P, P]),
                "orc_assign_bin": (C.c_int64, [P, C.c_int32, P, P, C.c_int64]),
                "orc_render": (C.c_int, [P, P]),
+               "orc_render_oit": (C.c_int, [P, P, C.c_int32, P, P, P, P]),
                "orc_backward": (C.c_int, [P, P, P, P, P, P])}
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -88,7 +89,8 @@ class using_library:
         self.saved = _lib
         _load()                      # make sure the real one is set up first
         lib = C.CDLL(self.path)
-        for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_backward"):
+        for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_render_oit",
+                     "orc_backward"):
             src, dst = getattr(_lib, name), getattr(lib, name)
             dst.restype, dst.argtypes = src.restype, src.argtypes
         _lib = lib
@@ -223,6 +225,27 @@ def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool 
         rc = lib.orc_render(C.byref(s), C.byref(t))
         if rc != 0:
             raise MemoryError("oracle render failed")
+    return out
+
+
+def render_oit(sc, alpha, layers: int):
+    """Order-independent transparency of a one-scene Gouraud scene: the
+    `layers` nearest fragments of every pixel composited nearest first with
+    the per-vertex opacities `alpha` [V] (see orc_render_oit).  Returns
+    color [1][H][W][4], depth, primid, bary with a leading scene axis."""
+    lib = _load()
+    parts = list(scene_parts(sc))
+    assert len(parts) == 1, "one scene"
+    H, W = int(sc.height), int(sc.width)
+    out = dict(color=np.zeros((1, H, W, 4), np.float32), depth=np.zeros((1, H, W), np.float32),
+               primid=np.zeros((1, H, W), np.int32), bary=np.zeros((1, H, W, 2), np.float32))
+    keep = _Keep()
+    s = _scene_struct(parts[0], keep)
+    a = np.ascontiguousarray(alpha, np.float32)
+    rc = lib.orc_render_oit(C.byref(s), _ptr(a), int(layers), _ptr(out["color"]),
+                            _ptr(out["depth"]), _ptr(out["primid"]), _ptr(out["bary"]))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
     return out
 
 

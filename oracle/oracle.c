@@ -469,6 +469,93 @@ int orc_render(const orc_scene *s, const orc_targets *o)
 }
 
 /*
+ * Order-independent transparency (the paper's example of an EndBin between
+ * Depth Test and Composite; the compositing rule is this project's reading):
+ * every pixel keeps the K fragments with the smallest (depth, triangle) keys
+ * -- the same keys and range test as the opaque depth test -- and composites
+ * them nearest first with per-vertex opacity `alpha` [V], interpolated like
+ * the colours:
+ *   T = 1, C = 0;  for each kept fragment j, nearest first:
+ *     a = alpha_j;  w = T * a;  C_c = C_c + w * c_jc;  T = T * (1 - a)
+ *   colour = (C_0, C_1, C_2, 1 - T).
+ * Depth, primid and bary are those of the nearest fragment; an empty pixel is
+ * as in orc_render.  Gouraud colours only.  color [H][W][4]; depth, primid,
+ * bary may be NULL.
+ */
+int orc_render_oit(const orc_scene *s, const float *alpha, int32_t K, float *color, float *depth,
+                   int32_t *primid, float *bary)
+{
+    const int W = s->width, H = s->height;
+    const int64_t npx = (int64_t)W * H;
+    if (K < 1) return -1;
+    uint64_t *keys = malloc(sizeof(uint64_t) * (size_t)(npx > 0 ? npx : 1) * (size_t)K);
+    if (!keys) return -1;
+    for (int64_t i = 0; i < npx * K; ++i) keys[i] = ~0ull;
+
+    /* every triangle in submission order, every sample of its bbox: insert
+     * the key into the pixel's ascending list of the K smallest */
+    for (int64_t t = 0; t < s->num_tris; ++t) {
+        otri r = setup_stage(s, t);
+        if (!r.live) continue;
+        for (int py = r.by0; py <= r.by1; ++py) {
+            for (int px = r.bx0; px <= r.bx1; ++px) {
+                int64_t E[3];
+                edge_values(&r, 256 * (int64_t)px + 128, 256 * (int64_t)py + 128, E);
+                if (!covers(&r, E)) continue;
+                double beta[3];
+                barycentrics64(&r, E, beta);
+                const float z = depth_of(&r, beta);
+                if (!(0.0f <= z && z < 1.0f)) continue;
+                uint64_t key = ((uint64_t)float_bits(z) << 32) | (uint32_t)t;
+                uint64_t *list = keys + ((int64_t)py * W + px) * K;
+                for (int j = 0; j < K; ++j) {
+                    if (key < list[j]) { const uint64_t tmp = list[j]; list[j] = key; key = tmp; }
+                }
+            }
+        }
+    }
+
+    const int64_t V = s->num_vertices;
+    for (int py = 0; py < H; ++py) {
+        for (int px = 0; px < W; ++px) {
+            const int64_t p = (int64_t)py * W + px;
+            const uint64_t *list = keys + p * K;
+            float C[3] = {0.0f, 0.0f, 0.0f};
+            float T = 1.0f;
+            if (list[0] == ~0ull) {
+                if (depth) depth[p] = 1.0f;
+                if (primid) primid[p] = -1;
+                if (bary) bary[2 * p] = bary[2 * p + 1] = 0.0f;
+            }
+            for (int j = 0; j < K && list[j] != ~0ull; ++j) {
+                const int64_t t = (int64_t)(list[j] & 0xffffffffull);
+                otri r = setup_stage(s, t);
+                int64_t E[3];
+                edge_values(&r, 256 * (int64_t)px + 128, 256 * (int64_t)py + 128, E);
+                double beta[3];
+                barycentrics64(&r, E, beta);
+                float bp[3];
+                persp_bary(&r, beta, bp);
+                const float a = interp(alpha, r.vid, bp);
+                const float w = T * a;
+                for (int c = 0; c < 3; ++c) C[c] = C[c] + w * interp(s->color + c * V, r.vid, bp);
+                T = T * (1.0f - a);
+                if (j == 0) {
+                    if (depth) depth[p] = bits_float((uint32_t)(list[0] >> 32));
+                    if (primid) primid[p] = (int32_t)t;
+                    if (bary) { bary[2 * p] = bp[1]; bary[2 * p + 1] = bp[2]; }
+                }
+            }
+            float *col = color + 4 * p;
+            col[0] = C[0]; col[1] = C[1]; col[2] = C[2];
+            col[3] = list[0] == ~0ull ? 0.0f : 1.0f - T;
+        }
+    }
+    free(keys);
+    return 0;
+}
+
+/*
  * Reference gradient of an image loss with respect to the per-vertex colours
  * and the texels, given the forward's primid and bary buffers and the
  * upstream gradient G[H][W][4] (alpha ignored).  float64 accumulation in

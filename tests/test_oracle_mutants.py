@@ -39,6 +39,10 @@ MUTANTS = {
     "colour_weight_swapped": ("t = t + bp[1] * plane[vid[1]];", "t = t + bp[2] * plane[vid[1]];"),
     "edge_sign": ("E[k] = dx * (Py - r->Y[a]) - dy * (Px - r->X[a]);",
                   "E[k] = dx * (Py - r->Y[a]) + dy * (Px - r->X[a]);"),
+    "oit_keeps_farthest": ("if (key < list[j]) { const uint64_t tmp = list[j];",
+                           "if (key > list[j] || list[j] == ~0ull) { const uint64_t tmp = list[j];"),
+    "oit_no_transmittance": ("T = T * (1.0f - a);", "T = T * 1.0f;"),
+    "oit_weight_without_transmittance": ("const float w = T * a;", "const float w = a;"),
     "backward_weight": ("grad_vcolor[c * V + vid[k]] += (double)bp[k] * (double)G[c];",
                         "grad_vcolor[c * V + vid[k]] += (double)bp[2 - k] * (double)G[c];"),
 }
@@ -182,6 +186,34 @@ def _pins_fail() -> list:
             ok &= abs((lp - lm) / (2 * h) - gv[c, v]) <= 1e-3 * abs(gv[c, v]) + 1e-3
         return ok
     check("backward", backward_sum)
+
+    def oit():
+        # the independent composition of the OIT pins, small
+        sc = scenes.tiny(seed=9, width=16, height=12, num_tris=16)
+        a = np.random.default_rng(2).uniform(0.05, 0.95, sc.pos.shape[1]).astype(np.float32)
+        f32 = np.float32
+        frags = {}
+        for t in range(sc.num_tris):
+            one = SimpleNamespace(**{**vars(sc), "pos": sc.pos[:, 3 * t:3 * t + 3].copy(),
+                                     "color": sc.color[:, 3 * t:3 * t + 3].copy(), "num_tris": 1})
+            o = oracle.render(one)
+            for y, x in zip(*np.nonzero(o["primid"][0] >= 0)):
+                b1, b2 = o["bary"][0, y, x]
+                b0 = (f32(1.0) - b1) - b2
+                al = f32(f32(f32(b0 * a[3 * t]) + b1 * a[3 * t + 1]) + b2 * a[3 * t + 2])
+                frags.setdefault((y, x), []).append(((int(o["depth"][0, y, x].view(np.uint32)), t),
+                                                     al, o["color"][0, y, x, :3].copy()))
+        r = oracle.render_oit(sc, a, 2)
+        for (y, x), fl in frags.items():
+            C, T = [f32(0.0)] * 3, f32(1.0)
+            for (_, al, c) in sorted(fl, key=lambda f: f[0])[:2]:
+                w = T * al
+                C = [C[i] + w * c[i] for i in range(3)]
+                T = T * (f32(1.0) - al)
+            if list(r["color"][0, y, x, :3]) != C or r["color"][0, y, x, 3] != f32(1.0) - T:
+                return False
+        return True
+    check("oit", oit)
     return failed
 
 
