@@ -282,6 +282,32 @@ def bench_ablation(reps: int = 5) -> dict:
                         "fused_resolve": best.fuse_resolve}}
 
 
+def bench_transparency(reps: int = 5) -> dict:
+    """Order-independent transparency on batch256 (random triangles, depth
+    complexity about 3.75) with per-vertex opacity ~ U[0.2, 0.8): one whole
+    frame (16-px bins, one workgroup per bin) for 1, 2, 4 and 8 layers
+    against the opaque frame; each layer is one more pass over every bin's
+    list (depth peeling) and one more resolved fragment per pixel."""
+    import numpy as np
+    import torch
+    from types import SimpleNamespace
+    from paper_1404_6293_amd import pk, scenes
+    sc = scenes.batch()
+    sc = SimpleNamespace(**{**vars(sc), "alpha": np.random.default_rng(7).uniform(
+        0.2, 0.8, sc.pos.shape[1]).astype(np.float32)})
+    dev = pk.DeviceScene(sc)
+    out = {}
+    for K in (0, 1, 2, 4, 8):
+        r = pk.Renderer(dev, pk.RenderConfig(bin_size=16, schedule="load_balance",
+                                             want_bary=False, layers=K))
+        r.render()
+        torch.cuda.synchronize()
+        out["opaque" if K == 0 else f"layers{K}"] = round(_median_ms(torch, r.frame, reps), 4)
+        del r
+    return {"workload": "batch256 with per-vertex opacity U[0.2, 0.8), 16-px bins, "
+                        "LOAD_BALANCE", "frame_ms": out}
+
+
 def measured_stream_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:
     """GB/s of a plain device-to-device copy of `mib` MiB (read + write bytes
     over time), buffers far larger than the 256 MB MALL: the achievable HBM
@@ -577,6 +603,8 @@ def main():
         out["micro"] = bench_micro()
         print("bench: schedule ablation", file=sys.stderr, flush=True)
         out["ablation"] = bench_ablation()
+        print("bench: transparency layers", file=sys.stderr, flush=True)
+        out["transparency"] = bench_transparency()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(sc)
         cb["host"] = platform.processor() or platform.machine()

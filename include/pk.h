@@ -141,6 +141,18 @@ typedef struct {               /* [host] */
     int32_t persistent_groups; /* DIRECT_MAP / DYNAMIC / SPLIT workgroup count; 0 = auto */
     int32_t split_size;        /* PK_SCHED_SPLIT: most (bin, triangle) pairs per work
                                   item, >= 1; 0 = 256.  Ignored by other schedules */
+    int32_t layers;            /* 0 = opaque.  1..8 = order-independent transparency:
+                                  every pixel composites its `layers` nearest fragments
+                                  (smallest (depth, triangle) keys, the opaque test's
+                                  keys), nearest first, with the per-vertex opacity
+                                  pk_attribs.alpha:  T = 1, C = 0;  per fragment
+                                  w = T*a, C += w*c, T = T*(1 - a);  colour = (C, 1 - T).
+                                  Depth, primid and bary are the nearest fragment's.
+                                  The paper's example of an EndBin between Depth Test
+                                  and Composite (Sec. 4.3); the compositing rule is
+                                  this library's.  Gouraud shading, 8/16/32-px bins,
+                                  not SPLIT (else PK_ERR_UNSUPPORTED), not fused; the
+                                  bins run one workgroup each (LOAD_BALANCE) */
 } pk_params;
 
 typedef struct {                 /* [host] struct of device pointers */
@@ -164,6 +176,7 @@ typedef struct {                 /* [host] struct of device pointers */
     int32_t tex_w, tex_h;
     const float *lights;         /* [num_lights][3] unit directions, DEFERRED only */
     int32_t num_lights;
+    const float *alpha;          /* [V] per-vertex opacity in [0, 1]; pk_params.layers > 0 only */
 } pk_attribs;
 
 typedef struct {                 /* [host] struct of device pointers; outputs [S][H][W](...) */

@@ -377,13 +377,15 @@ constexpr uint32_t kTagShift = 6, kNoTag = 0xffffffffu >> kTagShift;
 // PIPED: the DIRECT_MAP schedule with its prefetching chunk stream (its own
 // instantiation keeps the loop simple enough for the prefetches to land in
 // their loop-carried registers); otherwise LOAD_BALANCE or DYNAMIC.
-template <int TPB, int B, int SHADE, bool PIPED>
+template <int TPB, int B, int SHADE, bool PIPED, bool OIT = false>
 __global__ __launch_bounds__(TPB)
 __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(RasterArgs a) {
     constexpr int NPIX = B * B;
     constexpr int NW = TPB / kWave;
     constexpr int kLoopMax = 12;   // wave-max candidates for the per-lane loop
     __shared__ unsigned long long s_key[NPIX];
+    // transparency layers: the previous pass's nearest keys (depth peeling)
+    __shared__ unsigned long long s_prev[OIT ? NPIX : 1];
     // per-wave staging for the expansion mode (large triangles): one record
     // per lane's triangle, and a plane of start marks
     __shared__ __align__(16) uint32_t s_rec[NW][kWave * kStRec];
@@ -544,6 +546,15 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
         const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
 
+        // One pass per transparency layer (one pass when opaque): pass l keeps,
+        // per pixel, the smallest key above pass l-1's, so the passes find the
+        // nearest fragments in order.
+        const int nlayers = OIT ? a.sh.layers : 1;
+#pragma unroll 1
+        for (int layer = 0; layer < nlayers; ++layer) {
+        auto zmin = [&](uint32_t sl, unsigned long long key) {
+            if (!OIT || layer == 0 || key > s_prev[sl]) atomicMin(&s_key[sl], key);
+        };
         for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
         bool shared = false;   // PK_SCHED_SPLIT: the bin has several pieces
@@ -604,11 +615,11 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 for (int j = 0; j < mx; ++j) {
                     if (j < t.cnt) {
                         if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
-                            ++frags;
+                            frags += (!OIT || layer == 0);
                             unsigned long long key;
                             if (depth_key(e0, e1, e2, t.own, t.inv, t.z[0], t.z[1], t.z[2],
                                           (uint32_t)t.prim, key))
-                                atomicMin(&s_key[slot], key);
+                                zmin(slot, key);
                         }
                         if (++col < t.wdt) {
                             e0 += sx0; e1 += sx1; e2 += sx2;
@@ -742,24 +753,24 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                                                      (org & 0xffff) + (int32_t)col - px0);
                     unsigned long long key;
                     if (ca) {
-                        ++frags;
+                        frags += (!OIT || layer == 0);
                         if (depth_key(ea[0], ea[1], ea[2], own, e2i.y, z0, z1, z2, prim, key))
-                            atomicMin(&s_key[slot], key);
+                            zmin(slot, key);
                     }
                     if (cb) {
-                        ++frags;
+                        frags += (!OIT || layer == 0);
                         if (depth_key(eb[0], eb[1], eb[2], own, e2i.y, z0, z1, z2, prim, key))
-                            atomicMin(&s_key[slot + 1], key);
+                            zmin(slot + 1, key);
                     }
                     if (cc) {
-                        ++frags;
+                        frags += (!OIT || layer == 0);
                         if (depth_key(ec[0], ec[1], ec[2], own, e2i.y, z0, z1, z2, prim, key))
-                            atomicMin(&s_key[slot + B], key);
+                            zmin(slot + B, key);
                     }
                     if (cd) {
-                        ++frags;
+                        frags += (!OIT || layer == 0);
                         if (depth_key(ed[0], ed[1], ed[2], own, e2i.y, z0, z1, z2, prim, key))
-                            atomicMin(&s_key[slot + B + 1], key);
+                            zmin(slot + B + 1, key);
                     }
                 }
                 // the staging slots are rewritten by this wave's next chunk
@@ -775,7 +786,9 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             // as the final depth and primitive-ID targets when the caller
             // has both (the two halves of the key), else as keys
             const int64_t sb = (int64_t)s * G.W * G.H;
-            const bool split = !a.w.split && a.sh.out_depth && a.sh.out_primid;
+            const bool split = !OIT && !a.w.split && a.sh.out_depth && a.sh.out_primid;
+            // layer l's keys follow the whole key buffer of layers 0..l-1
+            const int64_t lofs = OIT ? (int64_t)layer * G.S * G.W * G.H : 0;
 #pragma unroll 1
             for (int i = tid; i < NPIX; i += TPB) {
                 const int lx = i % B, ly = i / B;
@@ -789,7 +802,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                         // pieces of one bin merge in the cleared key buffer
                         if (k != kEmptyKey) atomicMin(&a.w.keys[p], k);
                     } else {
-                        a.w.keys[p] = k;
+                        a.w.keys[p + lofs] = k;
                     }
                 }
             }
@@ -820,6 +833,12 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     if (on[k]) resolve_finish<SHADE>(a, s, px0 + lx[k], py0 + ly[k], rs[k]);
             }
         }
+        if (OIT) {
+            // each thread copies the pixels it stored; the next pass reads
+            // them only after the barrier that follows its key reset
+            for (int i = tid; i < NPIX; i += TPB) s_prev[i] = s_key[i];
+        }
+        }   // layer
         __syncthreads();
     }
     if (a.sh.frag_count) {
@@ -1069,8 +1088,100 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
         if (on[k]) resolve_finish<SHADE>(a, s, px, py0 + k * kResH, r[k], !split);
 }
 
+// Order-independent transparency, per pixel: the layers' keys (nearest
+// first, as the depth-peeling passes of the bin kernel left them) are
+// resolved one after another and composited with the interpolated per-vertex
+// opacity a:  T = 1, C = 0;  w = T*a, C += w*c, T = T*(1 - a);  colour =
+// (C, 1 - T).  Depth, primitive ID and barycentrics are the nearest layer's.
+// Gouraud colours; same tiles as k_resolve.
+__global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
+    const Geom &G = a.G;
+    const Shade &sh = a.sh;
+    const int ntx = (G.W + kResW - 1) / kResW, nty = (G.H + kResRows - 1) / kResRows;
+    const int64_t per_scene = (int64_t)ntx * nty;
+    const int64_t ntiles = per_scene * G.S;
+    const int64_t q = ntiles / kXcd, rem = ntiles % kXcd;
+    const int xcd = blockIdx.x % kXcd;
+    const uint32_t tile = (uint32_t)(xcd * q + min<int64_t>(xcd, rem) + blockIdx.x / kXcd);
+    const int32_t s = G.S == 1 ? 0 : (int32_t)(tile / (uint32_t)per_scene);
+    const uint32_t ts = tile - (uint32_t)s * (uint32_t)per_scene;
+    const int ty = (int)(ts / (uint32_t)ntx), tx = (int)(ts - (uint32_t)ty * (uint32_t)ntx);
+    const int px = tx * kResW + (int)(threadIdx.x % kResW);
+    const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
+    const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
+    const int64_t layer_stride = (int64_t)G.S * G.W * G.H;
+    const int64_t V = G.V;
+#pragma unroll 1
+    for (int k = 0; k < kResPPT; ++k) {
+        const int py = ty * kResRows + (int)(threadIdx.x / kResW) + k * kResH;
+        if (px >= G.W || py >= G.H) continue;
+        const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
+        float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
+        bool any = false;
+#pragma unroll 1
+        for (int l = 0; l < sh.layers; ++l) {
+            const unsigned long long key = a.w.keys[p + l * layer_stride];
+            if (key == kEmptyKey) break;
+            Resolve r;
+            resolve_fetch<PK_SHADE_GOURAUD>(a, s, item_base, vbase, px, py, key, r);
+            resolve_attribs<PK_SHADE_GOURAUD>(a, s, r);
+            const int32_t X0 = (int32_t)r.xy.x, Y0 = (int32_t)r.xy.y, X1 = (int32_t)r.xy.z,
+                          Y1 = (int32_t)r.xy.w;
+            const int32_t X2 = (int32_t)r.xy2.x, Y2 = (int32_t)r.xy2.y;
+            const int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
+            const int64_t E0 = (int64_t)(X2 - X1) * (Py - Y1) - (int64_t)(Y2 - Y1) * (Px - X1);
+            const int64_t E1 = (int64_t)(X0 - X2) * (Py - Y2) - (int64_t)(Y0 - Y2) * (Px - X2);
+            const int64_t E2 = (int64_t)(X1 - X0) * (Py - Y0) - (int64_t)(Y1 - Y0) * (Px - X0);
+            const float bs0 = (float)((double)E0 * r.sinv);
+            const float bs1 = (float)((double)E1 * r.sinv);
+            const float bs2 = (float)((double)E2 * r.sinv);
+            const float qq0 = bs0 * r.iw[0], qq1 = bs1 * r.iw[1], qq2 = bs2 * r.iw[2];
+            const float Q = (qq0 + qq1) + qq2;
+            const float b1 = qq1 / Q, b2 = qq2 / Q;
+            const float b0 = (1.0f - b1) - b2;
+            float al = b0 * sh.alpha[r.v[0]];
+            al = al + b1 * sh.alpha[r.v[1]];
+            al = al + b2 * sh.alpha[r.v[2]];
+            float rgb[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = b0 * r.c[0][ch];
+                acc = acc + b1 * r.c[1][ch];
+                acc = acc + b2 * r.c[2][ch];
+                rgb[ch] = acc;
+            }
+            const float w = T * al;
+            C0 = C0 + w * rgb[0];
+            C1 = C1 + w * rgb[1];
+            C2 = C2 + w * rgb[2];
+            T = T * (1.0f - al);
+            if (l == 0) {
+                any = true;
+                if (sh.out_depth) sh.out_depth[p] = r.depth;
+                if (sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
+                if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(b1, b2);
+            }
+        }
+        if (!any) {
+            if (sh.out_depth) sh.out_depth[p] = 1.0f;
+            if (sh.out_primid) sh.out_primid[p] = -1;
+            if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(0, 0);
+        }
+        if (sh.out_color)
+            reinterpret_cast<float4 *>(sh.out_color)[p] =
+                make_float4(C0, C1, C2, any ? 1.0f - T : 0.0f);
+    }
+    (void)V;
+}
+
 template <int TPB, int B, int SHADE>
 static hipError_t launch_b(const RasterArgs &a, dim3 grid, hipStream_t st) {
+    if constexpr (SHADE == kKeysOnly && B <= 32) {
+        if (a.sh.layers > 0) {
+            hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false, true>), grid, dim3(TPB), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     if (a.schedule == PK_SCHED_DIRECT_MAP)
         hipLaunchKernelGGL((k_raster<TPB, B, SHADE, true>), grid, dim3(TPB), 0, st, a);
     else
@@ -1112,6 +1223,12 @@ static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
 hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
     RasterArgs a{G, w, sh, 0, 1};
+    if (sh.layers > 0) {
+        const int64_t ntiles = (int64_t)((G.W + kResW - 1) / kResW) *
+                               ((G.H + kResRows - 1) / kResRows) * G.S;
+        hipLaunchKernelGGL(k_resolve_oit, dim3((unsigned)ntiles), dim3(kResW * kResH), 0, st, a);
+        return hipGetLastError();
+    }
     switch (sh.shading) {
     case PK_SHADE_GOURAUD:  return launch_resolve<PK_SHADE_GOURAUD>(a, st);
     case PK_SHADE_TEXTURED: return launch_resolve<PK_SHADE_TEXTURED>(a, st);

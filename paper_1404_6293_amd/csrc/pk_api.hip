@@ -20,6 +20,7 @@ struct Frame {
     int64_t items = 0;
     int64_t vrecs = 0;     // snapped vertex records (indexed meshes)
     bool indexed = false;
+    int32_t layers = 0;    // order-independent transparency: key tiles per pixel
     int32_t split = 0;     // PK_SCHED_SPLIT with bins: pairs per work item
     int64_t npix = 0;      // S * W * H
     int64_t nbins_scene = 0;
@@ -35,9 +36,17 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_SPLIT)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->split_size < 0) return PK_ERR_INVALID_ARGUMENT;
+    if (p->layers < 0 || p->layers > 8) return PK_ERR_INVALID_ARGUMENT;
+    if (p->layers > 0) {
+        if (p->flags & PK_FLAG_FUSE_RESOLVE) return PK_ERR_INVALID_ARGUMENT;
+        if (p->shading != PK_SHADE_GOURAUD || p->bin_size == 0 || p->bin_size == 64 ||
+            p->schedule == PK_SCHED_SPLIT)
+            return PK_ERR_UNSUPPORTED;
+    }
     // pieces of a bin merge in the workspace: no resolve inside the bin kernel
     if (p->schedule == PK_SCHED_SPLIT && (p->flags & PK_FLAG_FUSE_RESOLVE))
         return PK_ERR_INVALID_ARGUMENT;
+    f.layers = p->layers;
     f.split = (p->schedule == PK_SCHED_SPLIT && p->bin_size != 0)
                   ? (p->split_size ? p->split_size : 256) : 0;
     if (p->threads_per_bin != 0 && p->threads_per_bin != 64 && p->threads_per_bin != 128 &&
@@ -97,7 +106,7 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.vbin_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)(f.split ? f.nbins_total + 1 : 0));
-    L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix);
+    L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix * (size_t)(f.layers > 0 ? f.layers : 1));
     L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
     L.total = o;
     return L;
@@ -164,6 +173,7 @@ pk_status shade_args(const pk_params *p, const pk_attribs *a, const pk_targets *
          a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
         return PK_ERR_INVALID_ARGUMENT;
     if ((p->flags & PK_FLAG_COUNT_FRAGS) && !out->frag_count) return PK_ERR_INVALID_ARGUMENT;
+    if (p->layers > 0 && !a->alpha) return PK_ERR_INVALID_ARGUMENT;
     sh = Shade{};
     sh.color = a->color; sh.uv = a->uv; sh.normal = a->normal; sh.texture = a->texture;
     sh.lights = a->lights; sh.tex_w = a->tex_w; sh.tex_h = a->tex_h;
@@ -174,6 +184,8 @@ pk_status shade_args(const pk_params *p, const pk_attribs *a, const pk_targets *
     sh.out_primid = out->primid;
     sh.flags = p->flags;
     sh.frag_count = (p->flags & PK_FLAG_COUNT_FRAGS) ? out->frag_count : nullptr;
+    sh.alpha = p->layers > 0 ? a->alpha : nullptr;
+    sh.layers = p->layers;
     return PK_OK;
 }
 
@@ -237,7 +249,9 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     // the pair list is the last slice, so its address does not depend on the
     // capacity; the lists are read through bin_off only
     const Ws w = carve(ws, f, 0);
-    hipError_t e = launch_raster(G, w, sh, p->schedule, tpb, groups, mode, (hipStream_t)stream);
+    // transparency layers peel each bin's list several times: one workgroup per bin
+    const int sched = p->layers > 0 ? PK_SCHED_LOAD_BALANCE : p->schedule;
+    hipError_t e = launch_raster(G, w, sh, sched, tpb, groups, mode, (hipStream_t)stream);
     if (e == hipSuccess && mode != kRasterKeysOnly && p->shading == PK_SHADE_DEFERRED)
         e = launch_deferred(G, sh, (hipStream_t)stream);
     return hip_status(e);
@@ -268,7 +282,7 @@ pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
     pk_status st = check_params(p, f);
     if (st != PK_OK) return st;
     if ((st = check_mesh(p, m, f)) != PK_OK) return st;
-    if (p->shading == PK_SHADE_DEFERRED) return PK_ERR_UNSUPPORTED;
+    if (p->shading == PK_SHADE_DEFERRED || p->layers > 0) return PK_ERR_UNSUPPORTED;
     if (!a || !primid || !bary || !grad_color || !grad_vcolor || !a->color)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->shading == PK_SHADE_TEXTURED &&

@@ -136,6 +136,8 @@ struct Shade {
     int32_t *out_primid;
     unsigned long long *frag_count;
     int32_t flags;
+    const float *alpha;        // [V] per-vertex opacity (layers > 0)
+    int32_t layers;            // 0 = opaque, else layers composited per pixel
 };
 
 // Which scene an item belongs to and which triangle of the mesh it is.

@@ -45,7 +45,8 @@ class Params(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("bin_size", C.c_int32),
                 ("schedule", C.c_int32), ("threads_per_bin", C.c_int32), ("shading", C.c_int32),
                 ("flags", C.c_int32), ("num_scenes", C.c_int32), ("instanced", C.c_int32),
-                ("persistent_groups", C.c_int32), ("split_size", C.c_int32)]
+                ("persistent_groups", C.c_int32), ("split_size", C.c_int32),
+                ("layers", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -57,7 +58,7 @@ class Mesh(C.Structure):
 class Attribs(C.Structure):
     _fields_ = [("color", C.c_void_p), ("uv", C.c_void_p), ("normal", C.c_void_p),
                 ("texture", C.c_void_p), ("tex_w", C.c_int32), ("tex_h", C.c_int32),
-                ("lights", C.c_void_p), ("num_lights", C.c_int32)]
+                ("lights", C.c_void_p), ("num_lights", C.c_int32), ("alpha", C.c_void_p)]
 
 
 class BinView(C.Structure):
@@ -171,6 +172,8 @@ class RenderConfig:
     threads_per_bin: int = 0
     persistent_groups: int = 0
     split_size: int = 0            # schedule "split": pairs per work item (0 = 256)
+    layers: int = 0                # > 0: order-independent transparency with the
+                                   # scene's per-vertex `alpha` (that many layers)
     count_frags: bool = False
     want_bary: bool = True
     fuse_resolve: bool = False
@@ -226,6 +229,7 @@ class DeviceScene:
         self.uv = up(getattr(sc, "uv", None), f32)
         self.normal = up(getattr(sc, "normal", None), f32)
         self.texture = up(getattr(sc, "texture", None), f32)
+        self.alpha = up(getattr(sc, "alpha", None), f32)
         lights = getattr(sc, "lights", None)
         if lights is None:
             lights = _light_default()
@@ -242,7 +246,7 @@ class DeviceScene:
         return Attribs(_ptr(self.color), _ptr(self.uv), _ptr(self.normal), _ptr(tex),
                        0 if tex is None else int(tex.shape[1]),
                        0 if tex is None else int(tex.shape[0]), _ptr(self.lights),
-                       int(self.lights.shape[0]))
+                       int(self.lights.shape[0]), _ptr(self.alpha))
 
 
 class Renderer:
@@ -269,7 +273,8 @@ class Renderer:
                              (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
                              | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0)
                              | (PK_FLAG_DEFER_SHADE if cfg.defer_shade else 0), self.S,
-                             int(d.instanced), int(cfg.persistent_groups), int(cfg.split_size))
+                             int(d.instanced), int(cfg.persistent_groups), int(cfg.split_size),
+                             int(cfg.layers))
         self.mesh = d.mesh()
         self.attribs = d.attribs()
         S, H, W = self.S, self.H, self.W

@@ -60,7 +60,8 @@ def _mesh(**kw):
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
     dict(bin_size=-8), dict(schedule=4), dict(schedule=-1), dict(threads_per_bin=32),
-    dict(split_size=-1), dict(schedule=3, flags=2),
+    dict(split_size=-1), dict(schedule=3, flags=2), dict(layers=-1), dict(layers=9),
+    dict(layers=2, flags=2),
     dict(threads_per_bin=512), dict(shading=3), dict(flags=8), dict(flags=6), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
@@ -177,6 +178,29 @@ def test_split_schedule_workspace(L):
     p0 = _params(width=100, height=70, bin_size=0, schedule=3)
     assert L.pk_workspace_bytes(C.byref(p0), C.byref(m), 0) == L.pk_workspace_bytes(
         C.byref(_params(width=100, height=70, bin_size=0)), C.byref(m), 0)
+
+
+@pytest.mark.parametrize("kw", [dict(shading=1), dict(shading=2), dict(bin_size=0), dict(bin_size=64),
+                                dict(schedule=3)])
+def test_transparency_layers_unsupported_combinations(L, kw):
+    p = _params(**{"layers": 2, **kw})
+    assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_UNSUPPORTED
+
+
+def test_transparency_layers_workspace_and_alpha(L):
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    m = _mesh(num_tris=1000, num_vertices=3000)
+    b0 = L.pk_workspace_bytes(C.byref(_params(width=100, height=70, bin_size=16)), C.byref(m), 0)
+    for K in (1, 3, 8):
+        p = _params(width=100, height=70, bin_size=16, layers=K)
+        assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == b0 + al(8 * 7000 * K) - al(8 * 7000)
+    # the opacity plane is required, and there is no backward
+    p = _params(layers=2)
+    t = pk.Targets(FAKE, FAKE, FAKE, None, None, None, None)
+    assert L.pk_raster_shade(C.byref(p), C.byref(_mesh()), C.byref(pk.Attribs(color=FAKE)), FAKE,
+                             C.byref(t), None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_backward(C.byref(p), C.byref(_mesh()), C.byref(pk.Attribs(color=FAKE, alpha=FAKE)),
+                         FAKE, FAKE, FAKE, FAKE, None, None) == pk.PK_ERR_UNSUPPORTED
 
 
 def test_bin_lists_view_points_into_workspace(L):
