@@ -1110,7 +1110,6 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
     const int64_t layer_stride = (int64_t)G.S * G.W * G.H;
-    const int64_t V = G.V;
 #pragma unroll 1
     for (int k = 0; k < kResPPT; ++k) {
         const int py = ty * kResRows + (int)(threadIdx.x / kResW) + k * kResH;
@@ -1171,7 +1170,6 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
             reinterpret_cast<float4 *>(sh.out_color)[p] =
                 make_float4(C0, C1, C2, any ? 1.0f - T : 0.0f);
     }
-    (void)V;
 }
 
 template <int TPB, int B, int SHADE>
