@@ -524,10 +524,15 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             if (overflow) break;
             const int64_t v = blockIdx.x + it * (int64_t)gridDim.x;
             if (v >= nwork) break;
+            // each wave searches with 64 probes per step (every wave finds the
+            // same bin): the answer stays in [lo, hi] and voff[lo] <= v
             int64_t lo = 0, hi = nb - 1;
             while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if ((int64_t)voff[mid] <= v) lo = mid; else hi = mid - 1;
+                const int64_t step = (hi - lo + kWave) / kWave;
+                const int64_t probe = lo + (int64_t)lane * step;
+                const uint64_t m = __ballot(probe <= hi && (int64_t)a.w.vbin_off[probe] <= v);
+                lo += (int64_t)(63 - __clzll((long long)m)) * step;
+                hi = min(hi, lo + step - 1);
             }
             bin = lo;
             piece = (int32_t)(v - voff[lo]);

@@ -399,3 +399,17 @@ def test_transparency_layers_modes_and_perspective():
     op = oracle.render(base)
     np.testing.assert_array_equal(g["primid"], op["primid"])
     np.testing.assert_allclose(g["color"], op["color"], rtol=1e-6, atol=1e-7)
+
+
+def test_transparency_layers_batched_scenes():
+    """Concatenated scenes in one launch with transparency: every scene
+    equals the oracle's render of that scene alone."""
+    _note("transparency, batched scenes")
+    sc = _with_alpha(scenes.batch(num_scenes=4, size=64, tmin=100, tmax=2000, seed0=31), 8)
+    g = gpu_render(sc, bin_size=16, layers=3)
+    for s in range(4):
+        part = scenes.split_batch(sc, s)
+        v0, v1 = int(sc.scene_vtx_off[s]), int(sc.scene_vtx_off[s + 1])
+        o = oracle.render_oit(part, sc.alpha[v0:v1], 3)
+        one = {k: g[k][s:s + 1] for k in ("primid", "depth", "bary", "color")}
+        _compare_oit(one, o)
