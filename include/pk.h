@@ -24,6 +24,10 @@
  *                   pass when requested.
  *   pk_shade        the per-pixel composite + shading pass on its own, for
  *                   callers that split the frame (PK_FLAG_DEFER_SHADE).
+ *
+ * Variants selected by parameters: whole-screen bins (bin_size 0, the
+ * unbinned pipeline), heavy bins split across workgroups (PK_SCHED_SPLIT)
+ * and order-independent transparency (layers > 0, by depth peeling).
  *   pk_backward     gradients of an image loss with respect to per-vertex
  *                   colours and texels (not in the paper).
  *
