@@ -285,9 +285,10 @@ def bench_ablation(reps: int = 5) -> dict:
 def bench_transparency(reps: int = 5) -> dict:
     """Order-independent transparency on batch256 (random triangles, depth
     complexity about 3.75) with per-vertex opacity ~ U[0.2, 0.8): one whole
-    frame (16-px bins, one workgroup per bin) for 1, 2, 4 and 8 layers
-    against the opaque frame; each layer is one more pass over every bin's
-    list (depth peeling) and one more resolved fragment per pixel."""
+    frame (one workgroup per bin) for 1, 2, 4 and 8 layers against the
+    opaque frame.  8- and 16-px bins keep every pixel's K nearest keys in LDS
+    and pass over each bin's list once; 32-px bins peel, one pass per layer.
+    Each layer is one more resolved fragment per pixel."""
     import numpy as np
     import torch
     from types import SimpleNamespace
@@ -297,15 +298,19 @@ def bench_transparency(reps: int = 5) -> dict:
         0.2, 0.8, sc.pos.shape[1]).astype(np.float32)})
     dev = pk.DeviceScene(sc)
     out = {}
-    for K in (0, 1, 2, 4, 8):
-        r = pk.Renderer(dev, pk.RenderConfig(bin_size=16, schedule="load_balance",
-                                             want_bary=False, layers=K))
-        r.render()
-        torch.cuda.synchronize()
-        out["opaque" if K == 0 else f"layers{K}"] = round(_median_ms(torch, r.frame, reps), 4)
-        del r
-    return {"workload": "batch256 with per-vertex opacity U[0.2, 0.8), 16-px bins, "
-                        "LOAD_BALANCE", "frame_ms": out}
+    for B in (8, 16, 32):
+        for K in (0, 1, 2, 4, 8):
+            r = pk.Renderer(dev, pk.RenderConfig(bin_size=B, schedule="load_balance",
+                                                 want_bary=False, layers=K))
+            r.render()
+            torch.cuda.synchronize()
+            name = "opaque" if K == 0 else f"layers{K}"
+            out[f"B{B}/{name}"] = round(_median_ms(torch, r.frame, reps), 4)
+            del r
+    return {"workload": "batch256 with per-vertex opacity U[0.2, 0.8), LOAD_BALANCE, "
+                        "default threads per bin; B8/B16 one pass (K keys per pixel in "
+                        "LDS), B32 depth peeling",
+            "frame_ms": out}
 
 
 def measured_stream_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:

@@ -27,7 +27,8 @@
  *
  * Variants selected by parameters: whole-screen bins (bin_size 0, the
  * unbinned pipeline), heavy bins split across workgroups (PK_SCHED_SPLIT)
- * and order-independent transparency (layers > 0, by depth peeling).
+ * and order-independent transparency (layers > 0: one pass keeping every
+ * pixel's nearest keys in LDS for 8/16-px bins, depth peeling for 32-px).
  *   pk_backward     gradients of an image loss with respect to per-vertex
  *                   colours and texels (not in the paper).
  *
@@ -135,7 +136,9 @@ typedef struct {               /* [host] */
                                   depth test; schedule, threads_per_bin and
                                   persistent_groups are ignored) */
     int32_t schedule;          /* pk_schedule */
-    int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto */
+    int32_t threads_per_bin;   /* workgroup size for a bin: 64, 128, 256; 0 = auto
+                                  (64 up to 16-px bins, else 256; with 16-px bins
+                                  and 2 / 3+ transparency layers 128 / 256) */
     int32_t shading;           /* pk_shading */
     int32_t flags;             /* PK_FLAG_* */
     int32_t num_scenes;        /* S, 1..65535; S*W*H <= 2^40 pixels and
@@ -156,7 +159,9 @@ typedef struct {               /* [host] */
                                   and Composite (Sec. 4.3); the compositing rule is
                                   this library's.  Gouraud shading, 8/16/32-px bins,
                                   not SPLIT (else PK_ERR_UNSUPPORTED), not fused; the
-                                  bins run one workgroup each (LOAD_BALANCE) */
+                                  bins run one workgroup each (LOAD_BALANCE).  8/16-px
+                                  bins keep each pixel's `layers` nearest keys in LDS
+                                  in one pass; 32-px bins take one pass per layer */
 } pk_params;
 
 typedef struct {                 /* [host] struct of device pointers */

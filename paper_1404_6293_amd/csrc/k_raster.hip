@@ -377,7 +377,14 @@ constexpr uint32_t kTagShift = 6, kNoTag = 0xffffffffu >> kTagShift;
 // PIPED: the DIRECT_MAP schedule with its prefetching chunk stream (its own
 // instantiation keeps the loop simple enough for the prefetches to land in
 // their loop-carried registers); otherwise LOAD_BALANCE or DYNAMIC.
-template <int TPB, int B, int SHADE, bool PIPED, bool OIT = false>
+// OIT: transparency layers by depth peeling (one pass per layer).  KBUF:
+// transparency layers in one pass, each pixel keeping its K smallest keys in
+// LDS by an atomic-min cascade (a key that displaces a larger one carries that
+// one on to the next slot): the value left in slot j is the minimum of all
+// keys that reached it, i.e. the (j+1)-th smallest, whatever the order.
+// Slot 0 is the opaque test's key tile; slots 1..K-1 live in the dynamic LDS
+// ((K-1) * B*B * 8 bytes, sized at launch).
+template <int TPB, int B, int SHADE, bool PIPED, bool OIT = false, bool KBUF = false>
 __global__ __launch_bounds__(TPB)
 __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(RasterArgs a) {
     constexpr int NPIX = B * B;
@@ -386,6 +393,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     __shared__ unsigned long long s_key[NPIX];
     // transparency layers: the previous pass's nearest keys (depth peeling)
     __shared__ unsigned long long s_prev[OIT ? NPIX : 1];
+    extern __shared__ unsigned long long s_kbuf[];
     // per-wave staging for the expansion mode (large triangles): one record
     // per lane's triangle, and a plane of start marks
     __shared__ __align__(16) uint32_t s_rec[NW][kWave * kStRec];
@@ -558,9 +566,27 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
 #pragma unroll 1
         for (int layer = 0; layer < nlayers; ++layer) {
         auto zmin = [&](uint32_t sl, unsigned long long key) {
-            if (!OIT || layer == 0 || key > s_prev[sl]) atomicMin(&s_key[sl], key);
+            if (KBUF) {
+                // slot-major, so that neighbouring pixels use neighbouring
+                // banks; the last slot's minimum needs no old value
+                unsigned long long *slot = &s_key[sl];
+                for (int j = 1;; ++j) {
+                    if (j == a.sh.layers) {
+                        atomicMin(slot, key);
+                        break;
+                    }
+                    const unsigned long long old = atomicMin(slot, key);
+                    if (old == kEmptyKey) break;
+                    key = old > key ? old : key;
+                    slot = &s_kbuf[(j - 1) * NPIX + sl];
+                }
+            } else if (!OIT || layer == 0 || key > s_prev[sl]) {
+                atomicMin(&s_key[sl], key);
+            }
         };
         for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
+        if (KBUF)
+            for (int i = tid; i < (a.sh.layers - 1) * NPIX; i += TPB) s_kbuf[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
         bool shared = false;   // PK_SCHED_SPLIT: the bin has several pieces
         if (!overflow && !piped) {
@@ -791,7 +817,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             // as the final depth and primitive-ID targets when the caller
             // has both (the two halves of the key), else as keys
             const int64_t sb = (int64_t)s * G.W * G.H;
-            const bool split = !OIT && !a.w.split && a.sh.out_depth && a.sh.out_primid;
+            const bool split = !OIT && !KBUF && !a.w.split && a.sh.out_depth && a.sh.out_primid;
             // layer l's keys follow the whole key buffer of layers 0..l-1
             const int64_t lofs = OIT ? (int64_t)layer * G.S * G.W * G.H : 0;
 #pragma unroll 1
@@ -806,6 +832,11 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                     } else if (shared) {
                         // pieces of one bin merge in the cleared key buffer
                         if (k != kEmptyKey) atomicMin(&a.w.keys[p], k);
+                    } else if (KBUF) {
+                        const int64_t stride = (int64_t)G.S * G.W * G.H;
+                        a.w.keys[p] = k;
+                        for (int l = 1; l < a.sh.layers; ++l)
+                            a.w.keys[p + l * stride] = s_kbuf[(l - 1) * NPIX + i];
                     } else {
                         a.w.keys[p + lofs] = k;
                     }
@@ -1094,7 +1125,7 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
 }
 
 // Order-independent transparency, per pixel: the layers' keys (nearest
-// first, as the depth-peeling passes of the bin kernel left them) are
+// first, as the bin kernel left them) are
 // resolved one after another and composited with the interpolated per-vertex
 // opacity a:  T = 1, C = 0;  w = T*a, C += w*c, T = T*(1 - a);  colour =
 // (C, 1 - T).  Depth, primitive ID and barycentrics are the nearest layer's.
@@ -1122,13 +1153,8 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
         const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
         float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
         bool any = false;
-#pragma unroll 1
-        for (int l = 0; l < sh.layers; ++l) {
-            const unsigned long long key = a.w.keys[p + l * layer_stride];
-            if (key == kEmptyKey) break;
-            Resolve r;
-            resolve_fetch<PK_SHADE_GOURAUD>(a, s, item_base, vbase, px, py, key, r);
-            resolve_attribs<PK_SHADE_GOURAUD>(a, s, r);
+        // composite one resolved fragment behind the ones before it
+        auto composite = [&](const Resolve &r) {
             const int32_t X0 = (int32_t)r.xy.x, Y0 = (int32_t)r.xy.y, X1 = (int32_t)r.xy.z,
                           Y1 = (int32_t)r.xy.w;
             const int32_t X2 = (int32_t)r.xy2.x, Y2 = (int32_t)r.xy2.y;
@@ -1159,12 +1185,28 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
             C1 = C1 + w * rgb[1];
             C2 = C2 + w * rgb[2];
             T = T * (1.0f - al);
-            if (l == 0) {
+            if (!any) {
                 any = true;
                 if (sh.out_depth) sh.out_depth[p] = r.depth;
                 if (sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
                 if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(b1, b2);
             }
+        };
+        // two layers at a time, so that their gathers overlap
+#pragma unroll 1
+        for (int l = 0; l < sh.layers; l += 2) {
+            const unsigned long long k0 = a.w.keys[p + l * layer_stride];
+            const unsigned long long k1 =
+                l + 1 < sh.layers ? a.w.keys[p + (l + 1) * layer_stride] : kEmptyKey;
+            if (k0 == kEmptyKey) break;
+            Resolve r0, r1;
+            resolve_fetch<PK_SHADE_GOURAUD>(a, s, item_base, vbase, px, py, k0, r0);
+            resolve_fetch<PK_SHADE_GOURAUD>(a, s, item_base, vbase, px, py, k1, r1);
+            resolve_attribs<PK_SHADE_GOURAUD>(a, s, r0);
+            resolve_attribs<PK_SHADE_GOURAUD>(a, s, r1);
+            composite(r0);
+            if (k1 == kEmptyKey) break;
+            composite(r1);
         }
         if (!any) {
             if (sh.out_depth) sh.out_depth[p] = 1.0f;
@@ -1179,7 +1221,16 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
 
 template <int TPB, int B, int SHADE>
 static hipError_t launch_b(const RasterArgs &a, dim3 grid, hipStream_t st) {
-    if constexpr (SHADE == kKeysOnly && B <= 32) {
+    if constexpr (SHADE == kKeysOnly && B <= 16) {
+        if (a.sh.layers > 0) {
+            // K slots per pixel fit the LDS: one pass
+            const size_t slots = (size_t)(a.sh.layers - 1) * B * B * sizeof(unsigned long long);
+            hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false, false, true>), grid, dim3(TPB),
+                               slots, st, a);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (SHADE == kKeysOnly && B == 32) {
         if (a.sh.layers > 0) {
             hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false, true>), grid, dim3(TPB), 0, st, a);
             return hipGetLastError();

@@ -238,9 +238,14 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     if ((st = shade_args(p, a, out, f, sh)) != PK_OK) return st;
     const Geom G = geom(p, m, f);
     // defaults: one wave per bin up to 16x16 bins (no cross-wave barriers),
-    // and 16 resident waves per compute unit for the persistent schedules
+    // and 16 resident waves per compute unit for the persistent schedules.
+    // Transparency slots take LDS per workgroup: with 16x16 bins and more
+    // layers, more waves share one bin's slots (measured on batches of
+    // random triangles)
     int tpb = p->threads_per_bin;
     if (tpb == 0) tpb = p->bin_size <= 16 ? 64 : 256;
+    if (p->threads_per_bin == 0 && p->bin_size == 16 && p->layers > 1)
+        tpb = p->layers == 2 ? 128 : 256;
     int groups = p->persistent_groups;
     if (groups == 0) groups = 256 * 16 * kWave / tpb;
     const RasterMode mode = (p->flags & PK_FLAG_FUSE_RESOLVE) ? kRasterFused
@@ -249,7 +254,8 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     // the pair list is the last slice, so its address does not depend on the
     // capacity; the lists are read through bin_off only
     const Ws w = carve(ws, f, 0);
-    // transparency layers peel each bin's list several times: one workgroup per bin
+    // transparency layers keep per-pixel LDS state for a whole bin (slots or
+    // peeling passes): one workgroup per bin
     const int sched = p->layers > 0 ? PK_SCHED_LOAD_BALANCE : p->schedule;
     hipError_t e = launch_raster(G, w, sh, sched, tpb, groups, mode, (hipStream_t)stream);
     if (e == hipSuccess && mode != kRasterKeysOnly && p->shading == PK_SHADE_DEFERRED)

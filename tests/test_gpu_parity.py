@@ -369,7 +369,8 @@ def _compare_oit(g, o):
 @pytest.mark.parametrize("K", [1, 2, 5, 8])
 def test_transparency_layers_match_oracle(K):
     """Order-independent transparency: the K nearest fragments of every pixel
-    (depth peeling in the bin kernel) composited with per-vertex opacity."""
+    (one pass with per-pixel LDS slots for 8/16-px bins, depth peeling for
+    32-px bins) composited with per-vertex opacity."""
     _note(f"transparency K={K}")
     sc = _with_alpha(scenes.tiny(seed=20 + K, width=72, height=56, num_tris=300), K)
     o = oracle.render_oit(sc, sc.alpha, K)
@@ -377,6 +378,19 @@ def test_transparency_layers_match_oracle(K):
         g = gpu_render(sc, bin_size=B, layers=K)
         _compare_oit(g, o)
         assert int(g["frag_count"][0]) == int(oracle.render(sc)["frag_count"].sum())
+
+
+def test_transparency_layers_workgroup_sizes():
+    """Every workgroup size over one bin's LDS slots (several waves share a
+    pixel's slots at 128 and 256 threads), on a deep scene where most pixels
+    hold more fragments than slots: the same image as the oracle's."""
+    _note("transparency, workgroup sizes")
+    sc = _with_alpha(scenes.tiny(seed=71, width=64, height=48, num_tris=900), 12)
+    for K in (3, 8):
+        o = oracle.render_oit(sc, sc.alpha, K)
+        for B in (8, 16, 32):
+            for t in (64, 128, 256):
+                _compare_oit(gpu_render(sc, bin_size=B, layers=K, threads_per_bin=t), o)
 
 
 def test_transparency_layers_modes_and_perspective():
