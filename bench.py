@@ -282,7 +282,7 @@ def bench_ablation(reps: int = 5) -> dict:
                         "fused_resolve": best.fuse_resolve}}
 
 
-def bench_transparency(reps: int = 5) -> dict:
+def bench_transparency(reps: int = 5, bins=(8, 16, 32), layers=(0, 1, 2, 4, 8)) -> dict:
     """Order-independent transparency on batch256 (random triangles, depth
     complexity about 3.75) with per-vertex opacity ~ U[0.2, 0.8): one whole
     frame (one workgroup per bin) for 1, 2, 4 and 8 layers against the
@@ -298,8 +298,8 @@ def bench_transparency(reps: int = 5) -> dict:
         0.2, 0.8, sc.pos.shape[1]).astype(np.float32)})
     dev = pk.DeviceScene(sc)
     out = {}
-    for B in (8, 16, 32):
-        for K in (0, 1, 2, 4, 8):
+    for B in bins:
+        for K in layers:
             r = pk.Renderer(dev, pk.RenderConfig(bin_size=B, schedule="load_balance",
                                                  want_bary=False, layers=K))
             r.render()
@@ -423,7 +423,14 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(calibrates the HBM byte counters of a profiler run)")
+    ap.add_argument("--transparency", type=int, default=-1, metavar="K",
+                    help="only time the transparency frame of batch256 with K layers "
+                         "(bin size --bin, default 16; 20 frames) and print its JSON")
     args = ap.parse_args()
+    if args.transparency >= 0:
+        print(json.dumps(bench_transparency(reps=20, bins=(16 if args.bin < 0 else args.bin,),
+                                            layers=(args.transparency,))), flush=True)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe << 20
