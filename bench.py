@@ -265,6 +265,32 @@ def bench_micro(reps: int = 10) -> dict:
             "gfrags_per_s": round(frags / ms / 1e6, 3)}
 
 
+def bench_lights(reps: int = 5) -> dict:
+    """Shader complexity swept by the light count, the knob of the paper's
+    fusion experiments (Sec. 7.2), on micro8m (deferred shading): one whole
+    frame with 1, 4, 16 and 64 lights for the unbinned baseline (whole-screen
+    bins), 16-px bins with the resolve in its own pass, and 16-px bins with
+    the resolve fused into the bin kernel.  Lighting runs once per pixel in
+    the deferred pass in all three."""
+    import torch
+    from types import SimpleNamespace
+    from paper_1404_6293_amd import pk, scenes
+    base = scenes.micro()
+    cfgs = {"B0": dict(bin_size=0), "B16": dict(bin_size=16),
+            "B16/fused": dict(bin_size=16, fuse_resolve=True)}
+    out = {}
+    for L in (1, 4, 16, 64):
+        dev = pk.DeviceScene(SimpleNamespace(**{**vars(base), "lights": scenes.lights(L)}))
+        for name, c in cfgs.items():
+            r = pk.Renderer(dev, pk.RenderConfig(want_bary=False, **c))
+            r.render()
+            torch.cuda.synchronize()
+            out[f"{name}/lights{L}"] = round(_median_ms(torch, r.frame, reps), 4)
+            del r
+        del dev
+    return {"workload": "micro8m, deferred shading with 1-64 lights", "frame_ms": out}
+
+
 def bench_ablation(reps: int = 5) -> dict:
     """The schedule ablation of Sec. 7.2 on grid1080: whole-screen bins (the
     unbinned baseline) and every bin size with each schedule, the resolve in
@@ -617,6 +643,8 @@ def main():
         out["ablation"] = bench_ablation()
         print("bench: transparency layers", file=sys.stderr, flush=True)
         out["transparency"] = bench_transparency()
+        print("bench: light count", file=sys.stderr, flush=True)
+        out["lights"] = bench_lights()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(sc)
         cb["host"] = platform.processor() or platform.machine()

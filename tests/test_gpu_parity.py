@@ -188,6 +188,18 @@ def test_deferred_micropolygons_small(mode):
     np.testing.assert_allclose(g["gbuf_albedo"], o["gbuf_albedo"], rtol=RTOL, atol=ATOL)
 
 
+@pytest.mark.parametrize("L", [16, 64])
+def test_deferred_many_lights(L):
+    """Shader complexity as a light count (the knob of the paper's fusion
+    experiments): the deferred pass sums every light, unbinned, binned and
+    fused alike."""
+    _note(f"deferred lights={L}")
+    sc = scenes.micro(seed=13, width=160, height=96, num_tris=30000, num_lights=L)
+    o = oracle.render(sc)
+    for cfg in ({"bin_size": 0}, {"bin_size": 16}, {"bin_size": 16, "fuse_resolve": True}):
+        compare(sc, gpu_render(sc, **cfg), o)
+
+
 def test_deferred_tie_heavy():
     """Micropolygons with depth quantised to 8 levels: many equal depths, the
     smaller triangle index must win everywhere."""
