@@ -39,7 +39,10 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 constexpr int kGroupThreads = 256;
 constexpr int kItemsPerThread = 4;
 constexpr int kGroupItems = kGroupThreads * kItemsPerThread;
-// (with the 8 reduction words, one workgroup takes exactly 32 KiB of LDS: 5 per CU)
+// (with the 8 reduction words, one workgroup takes exactly 32 KiB of LDS: 5 per CU).
+// k_setup takes its histogram as dynamic LDS, launched without it for
+// whole-screen bins, which count nothing: there the occupancy is not
+// capped by LDS.
 constexpr int kHist = 8192 - 2 * kGroupThreads / 64;
 
 __device__ inline int32_t scene_of(const Geom &G, int64_t item) {
@@ -220,7 +223,7 @@ __device__ inline void group_span(int lo, int hi, int *s_red, int &glo, int &ghi
 }
 
 __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
-    __shared__ uint32_t s_hist[kHist];
+    extern __shared__ uint32_t s_hist[];   // kHist words, binned screens only
     __shared__ int s_red[2 * kGroupThreads / kWave];
     const int tid = threadIdx.x;
     const int64_t first = blockIdx.x * (int64_t)kGroupItems;
@@ -309,7 +312,8 @@ hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st) {
     }
     if (e != hipSuccess || G.items == 0) return e;
     const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
-    hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), 0, st, G, w);
+    const size_t hist = G.B ? kHist * sizeof(uint32_t) : 0;
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), hist, st, G, w);
     return hipGetLastError();
 }
 
