@@ -430,8 +430,8 @@ def bench_backward(reps: int = 10) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grid1080", choices=sorted(WORKLOADS))
     ap.add_argument("--bin", type=int, default=-1,
                     help="bin size (0 = whole-screen bins); default: the workload's")
