@@ -313,7 +313,8 @@ def bench_transparency(reps: int = 5, bins=(8, 16, 32), layers=(0, 1, 2, 4, 8)) 
     complexity about 3.75) with per-vertex opacity ~ U[0.2, 0.8): one whole
     frame (one workgroup per bin) for 1, 2, 4 and 8 layers against the
     opaque frame.  8- and 16-px bins keep every pixel's K nearest keys in LDS
-    and pass over each bin's list once; 32-px bins peel, one pass per layer.
+    and pass over each bin's list once; so do 32-px bins up to 3 layers, and
+    peel beyond, one pass per layer.
     Each layer is one more resolved fragment per pixel."""
     import numpy as np
     import torch
@@ -334,8 +335,8 @@ def bench_transparency(reps: int = 5, bins=(8, 16, 32), layers=(0, 1, 2, 4, 8)) 
             out[f"B{B}/{name}"] = round(_median_ms(torch, r.frame, reps), 4)
             del r
     return {"workload": "batch256 with per-vertex opacity U[0.2, 0.8), LOAD_BALANCE, "
-                        "default threads per bin; B8/B16 one pass (K keys per pixel in "
-                        "LDS), B32 depth peeling",
+                        "default threads per bin; one pass with K keys per pixel in "
+                        "LDS, except B32 beyond 3 layers (depth peeling)",
             "frame_ms": out}
 
 

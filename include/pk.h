@@ -28,7 +28,8 @@
  * Variants selected by parameters: whole-screen bins (bin_size 0, the
  * unbinned pipeline), heavy bins split across workgroups (PK_SCHED_SPLIT)
  * and order-independent transparency (layers > 0: one pass keeping every
- * pixel's nearest keys in LDS for 8/16-px bins, depth peeling for 32-px).
+ * pixel's nearest keys in LDS, or depth peeling for 32-px bins beyond 3
+ * layers).
  *   pk_backward     gradients of an image loss with respect to per-vertex
  *                   colours and texels (not in the paper).
  *
@@ -159,9 +160,10 @@ typedef struct {               /* [host] */
                                   and Composite (Sec. 4.3); the compositing rule is
                                   this library's.  Gouraud shading, 8/16/32-px bins,
                                   not SPLIT (else PK_ERR_UNSUPPORTED), not fused; the
-                                  bins run one workgroup each (LOAD_BALANCE).  8/16-px
-                                  bins keep each pixel's `layers` nearest keys in LDS
-                                  in one pass; 32-px bins take one pass per layer */
+                                  bins run one workgroup each (LOAD_BALANCE).  The bin
+                                  kernel keeps each pixel's `layers` nearest keys in
+                                  LDS in one pass, except 32-px bins with more than 3
+                                  layers, which take one pass per layer */
 } pk_params;
 
 typedef struct {                 /* [host] struct of device pointers */

@@ -1219,10 +1219,14 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve_oit(RasterArgs a) {
     }
 }
 
+// 32-px bins keep transparency slots in LDS for up to this many layers
+// ((K-1) * 8 KB); beyond, they peel
+constexpr int kSlotLayers32 = 3;
+
 template <int TPB, int B, int SHADE>
 static hipError_t launch_b(const RasterArgs &a, dim3 grid, hipStream_t st) {
-    if constexpr (SHADE == kKeysOnly && B <= 16) {
-        if (a.sh.layers > 0) {
+    if constexpr (SHADE == kKeysOnly && B <= 32) {
+        if (a.sh.layers > 0 && (B <= 16 || a.sh.layers <= kSlotLayers32)) {
             // K slots per pixel fit the LDS: one pass
             const size_t slots = (size_t)(a.sh.layers - 1) * B * B * sizeof(unsigned long long);
             hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false, false, true>), grid, dim3(TPB),
@@ -1231,7 +1235,7 @@ static hipError_t launch_b(const RasterArgs &a, dim3 grid, hipStream_t st) {
         }
     }
     if constexpr (SHADE == kKeysOnly && B == 32) {
-        if (a.sh.layers > 0) {
+        if (a.sh.layers > kSlotLayers32) {
             hipLaunchKernelGGL((k_raster<TPB, B, SHADE, false, true>), grid, dim3(TPB), 0, st, a);
             return hipGetLastError();
         }
