@@ -9,7 +9,7 @@
  *
  *   pk_setup        vertex shader + rasterizer setup; the next stage's
  *                   AssignBin counts are produced in the same kernel
- *                   (Sec. 5.2.1: a kernel holds Schedule + Process of one
+ *                   (Sec. 5.2, opening text: a kernel holds Schedule + Process of one
  *                   stage and AssignBin of the next).
  *   pk_assign_bin   AssignToBoundingBox (Sec. 4.3, directive table): a prefix
  *                   sum over the per-bin counts and a scatter into CSR bin
@@ -20,7 +20,7 @@
  *                   buffer of Sec. 5.2.4 lives in LDS), then composite and
  *                   fragment shader either in a per-pixel pass over the
  *                   bins' winning keys or fused into the bin kernel
- *                   (Sec. 5.2.2 kernel fusion), then the deferred shading
+ *                   (Sec. 5.2.1 kernel fusion), then the deferred shading
  *                   pass when requested.
  *   pk_shade        the per-pixel composite + shading pass on its own, for
  *                   callers that split the frame (PK_FLAG_DEFER_SHADE).
@@ -157,7 +157,7 @@ typedef struct {               /* [host] */
                                   w = T*a, C += w*c, T = T*(1 - a);  colour = (C, 1 - T).
                                   Depth, primid and bary are the nearest fragment's.
                                   The paper's example of an EndBin between Depth Test
-                                  and Composite (Sec. 4.3); the compositing rule is
+                                  and Composite (Sec. 5.2.3); the compositing rule is
                                   this library's.  Gouraud shading, 8/16/32-px bins,
                                   not SPLIT (else PK_ERR_UNSUPPORTED), not fused; the
                                   bins run one workgroup each (LOAD_BALANCE).  The bin
@@ -215,15 +215,15 @@ size_t pk_workspace_bytes(const pk_params *p, const pk_mesh *m, int64_t pair_cap
  * first run the Vertex Shader once per vertex (per view), then setup gathers
  * the snapped vertices; unindexed ones transform in setup.  Writes the
  * workspace only.  Sec. 7.1 stage list (Vertex Shader, Rasterizer setup);
- * Sec. 5.2.1 basic kernel mapping. */
+ * Sec. 5.2 opening text, basic kernel mapping. */
 pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream);
 
 /* AssignToBoundingBox (Sec. 4.3): exclusive prefix sum of the per-bin counts
  * and scatter of triangle indices into CSR bin lists inside the workspace.
  * *pairs_needed (device, one int64) receives the total number of (bin,
  * triangle) pairs.  If it exceeds pair_capacity, no list is written and the
- * following pk_raster_shade writes no pixel; call again with a larger
- * workspace.  The order of triangles inside one bin is unspecified.
+ * following pk_raster_shade writes empty pixels (colour 0, depth 1, primid -1,
+ * bary 0) to every given target; call again with a larger workspace.  The order of triangles inside one bin is unspecified.
  * With PK_SCHED_SPLIT it also numbers the work items (each bin's list cut
  * into pieces of at most split_size pairs) for pk_raster_shade.
  * With bin_size 0 every scene is one bin that holds all of its triangles
@@ -235,7 +235,7 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
 /* Schedule + Process of the screen-space stage for every bin of every scene:
  * coverage, depth test in an LDS-resident tile, resolve and shading, writing
  * every pixel of every target that is non-NULL (Sec. 4.4 sort-middle renderer;
- * Sec. 5.2.2 fusion of Rasterizer, Fragment Shader, Depth Test, Composite).
+ * Sec. 5.2.1 fusion of Rasterizer, Fragment Shader, Depth Test, Composite).
  * With PK_SHADE_DEFERRED the colour comes from a second pass over the
  * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace.
  * With bin_size 0 (whole-screen bins) one thread per triangle covers its
@@ -252,7 +252,7 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
 
 /* Second half of a frame rendered with PK_FLAG_DEFER_SHADE: the Composite and
  * Fragment Shader stages as their own per-pixel pass (Sec. 7.1 stage list;
- * Sec. 5.2.2 discusses running them fused or apart).  Reads the winning keys
+ * Sec. 5.2.1 discusses running them fused or apart).  Reads the winning keys
  * that pk_raster_shade left (in the depth and primid targets, or in `ws`),
  * resolves and shades every pixel, and
  * writes every non-NULL target exactly as a pk_raster_shade without the flag

@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-Wall", "-Wno-misleading-indentation"]
 
-SHADING = {"gouraud": 0, "textured": 1, "deferred": 2}
+SHADING = {"gouraud": 0, "textured": 1, "deferred": 2, "lit": 3}
 
 
 def build(force: bool = True) -> str:

@@ -50,7 +50,7 @@ typedef struct {
     int32_t tex_w, tex_h;
     const float *lights;     /* [L][3] */
     int32_t num_lights;
-    int32_t shading;         /* 0 gouraud, 1 textured, 2 deferred */
+    int32_t shading;         /* 0 gouraud, 1 textured, 2 deferred, 3 forward-lit */
 } orc_scene;
 
 typedef struct {
@@ -433,7 +433,11 @@ int orc_render(const orc_scene *s, const orc_targets *o)
                 otap tp = bilinear_taps(s, u, v);
                 for (int c = 0; c < 3; ++c) rgb[c] = rgb[c] * sample_channel(s, &tp, c);
             }
-            if (s->shading == 2) {
+            if (s->shading == 2 || s->shading == 3) {
+                /* deferred (2) writes the G-buffer and lights it in a second
+                 * pass; forward-lit (3) lights the same unit normal and albedo
+                 * in the fragment shader itself.  Either way the colour is
+                 * albedo * sum over the lights of max(0, n.l). */
                 float n[3];
                 for (int c = 0; c < 3; ++c) n[c] = interp(s->normal + c * V, r.vid, bp);
                 float nn = n[0] * n[0];
@@ -446,7 +450,7 @@ int orc_render(const orc_scene *s, const orc_targets *o)
                 }
                 if (o->gbuf_normal) for (int c = 0; c < 3; ++c) o->gbuf_normal[3 * p + c] = nh[c];
                 if (o->gbuf_albedo) for (int c = 0; c < 3; ++c) o->gbuf_albedo[3 * p + c] = rgb[c];
-                /* deferred pass: albedo * sum_l max(0, n.l) */
+                /* lighting: albedo * sum_l max(0, n.l), lights in the given order */
                 float lit = 0.0f;
                 for (int l = 0; l < s->num_lights; ++l) {
                     const float *L = s->lights + 3 * l;

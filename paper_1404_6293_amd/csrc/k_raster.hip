@@ -2,7 +2,7 @@
 // sort-middle renderer): for every bin, coverage, depth test, resolve and
 // shading in one kernel.  The paper's Rasterizer, Fragment Shader, Depth
 // Test and Composite stages share bin size and bin mapping, so they fuse
-// (Sec. 5.2.2); the depth buffer of a bin stays on chip (the on-chip depth
+// (Sec. 5.2.1); the depth buffer of a bin stays on chip (the on-chip depth
 // buffer of Sec. 5.2.4), here as 64-bit (depth, primitive) keys in LDS
 // updated with ds_min_u64, which makes the test order-independent.
 //
@@ -17,7 +17,7 @@
 // Schedules (Sec. 4.3 directives; Sec. 6 work-group organization):
 //   LOAD_BALANCE  one workgroup per bin (the hardware dispatcher balances)
 //   DIRECT_MAP    G persistent workgroups, bins pre-assigned in contiguous
-//                 ranges per die (pre-scheduling, Sec. 5.2.3), with the
+//                 ranges per die (pre-scheduling, Sec. 5.2.2), with the
 //                 records and pair numbers of the next chunks prefetched
 //   DYNAMIC       G persistent workgroups pop batches of bins from per-die
 //                 device counters

@@ -36,6 +36,9 @@ MUTANTS = {
     "texture_axes_swapped": ("const float fs = su - fi, ft = sv - fj;", "const float ft = su - fi, fs = sv - fj;"),
     "texel_centre_shift": ("const float su = u * (float)s->tex_w - 0.5f;", "const float su = u * (float)s->tex_w;"),
     "deferred_no_clamp": ("if (d < 0.0f) d = 0.0f;", ""),
+    "last_light_only": ("lit = (l == 0) ? d : lit + d;", "lit = d;"),
+    "first_light_only": ("lit = (l == 0) ? d : lit + d;", "lit = (l == 0) ? d : lit;"),
+    "lights_max": ("lit = (l == 0) ? d : lit + d;", "lit = (l == 0) ? d : fmaxf(lit, d);"),
     "colour_weight_swapped": ("t = t + bp[1] * plane[vid[1]];", "t = t + bp[2] * plane[vid[1]];"),
     "edge_sign": ("E[k] = dx * (Py - r->Y[a]) - dy * (Px - r->X[a]);",
                   "E[k] = dx * (Py - r->Y[a]) + dy * (Px - r->X[a]);"),
@@ -166,6 +169,17 @@ def _pins_fail() -> list:
                   lights=scenes.default_light(), shading="deferred")
         return np.abs(oracle.render(sc)["color"][0, :, :, :3]).max() <= 1e-7
     check("deferred", deferred)
+
+    def lights_sum():
+        # constant normal (0,0,1), albedo 1: colour = sum of the clamped
+        # n.l over a back-facing light, then two lit ones
+        X, Y = [0, 4096, 0, 4096], [0, 0, 4096, 4096]
+        n = np.repeat(np.array([[0.0], [0.0], [1.0]], np.float32), 4, axis=1)
+        L = np.array([[0, 0, -1], [0.6, 0, 0.8], [0, 0.28, 0.96]], np.float32)
+        sc = _ndc(16, 16, X, Y, [0.5] * 4, idx=[[0, 1, 3], [0, 3, 2]], normal=n, lights=L,
+                  color=np.ones((3, 4), np.float32), shading="deferred")
+        return np.allclose(oracle.render(sc)["color"][0, :, :, :3], 0.8 + 0.96, rtol=1e-6, atol=0)
+    check("lights_sum", lights_sum)
 
     def backward_sum():
         sc = scenes.tiny(seed=2, width=24, height=18, num_tris=8)

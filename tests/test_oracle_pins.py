@@ -434,6 +434,65 @@ def test_deferred_light_aligned_and_orthogonal():
         np.testing.assert_allclose(np.linalg.norm(o["gbuf_normal"][0], axis=-1), 1.0, rtol=1e-6)
 
 
+def _unit(v):
+    v = np.asarray(v, np.float64)
+    return v / np.linalg.norm(v)
+
+
+# Light sets in which the sum, the last light alone, the first alone and the
+# largest term all differ; each holds one light behind the surface, which
+# must add nothing (it would subtract without the clamp).
+_LIGHT_SETS = [
+    [(0, 0, -1), (1, 1, 1), (0, 1, 1), (1, 0, 3)],
+    [(1, 1, 1), (0, 0, -1), (0, 1, 1)],
+    [(0, 1, 1), (1, 0, 3), (1, 1, 1), (-1, -2, -2)],
+]
+
+
+@pytest.mark.parametrize("shading", ["deferred", "lit"])
+@pytest.mark.parametrize("nvec", [(0, 0, 1), (1, 2, 2), (2, -1, 2)])
+@pytest.mark.parametrize("which", range(len(_LIGHT_SETS)))
+def test_lighting_sums_clamped_terms_over_lights(shading, nvec, which):
+    """Several lights: the colour is albedo * sum_l max(0, n.l) with the
+    normal and lights fixed by hand (constant over the triangle), the sum
+    worked out here in float64.  A back-facing light adds zero.  The lighting
+    model is the paper's example fragment shader (material times the dot
+    product of normal and light, Sec. 4.1 listing "kernels") clamped at zero
+    and summed over the lights, which are the shader-complexity knob of
+    Sec. 7.2."""
+    W = H = 16
+    X = [0, 256 * 16, 0, 256 * 16]
+    Y = [0, 0, 256 * 16, 256 * 16]
+    alb = np.array([0.8, 0.5, 0.25], np.float32)      # exact in float32
+    n = _unit(nvec)
+    lights = np.stack([_unit(l) for l in _LIGHT_SETS[which]]).astype(np.float32)
+    nrm = np.repeat(n.astype(np.float32).reshape(3, 1), 4, axis=1)
+    sc = _ndc_scene(W, H, X, Y, [0.5] * 4, color=np.repeat(alb.reshape(3, 1), 4, axis=1),
+                    idx=[[0, 1, 3], [0, 3, 2]], normal=nrm, lights=lights, shading=shading)
+    o = oracle.render(sc)
+    terms = [max(0.0, float(n @ l.astype(np.float64))) for l in lights]
+    assert min(float(n @ l.astype(np.float64)) for l in lights) < -0.1   # one light behind
+    expect = alb.astype(np.float64) * sum(terms)
+    assert (o["primid"][0] >= 0).all()
+    np.testing.assert_allclose(o["color"][0, :, :, :3], np.broadcast_to(expect, (H, W, 3)),
+                               rtol=2e-6, atol=0)
+    np.testing.assert_array_equal(o["color"][0, :, :, 3], 1.0)
+    # the alternatives a mistake would produce are far away
+    for wrong in (terms[-1], terms[0], max(terms)):
+        assert abs(wrong - sum(terms)) > 0.1
+
+
+def test_forward_lit_equals_deferred_colour():
+    """Forward-lit shading lights the same unit normal and albedo in the
+    fragment shader as the deferred pass does from the G-buffer, so the two
+    colours agree bit for bit on a random scene with several lights."""
+    sc = scenes.micro(num_tris=3000, width=48, height=40, seed=11, num_lights=5)
+    d = oracle.render(sc)
+    f = oracle.render(SimpleNamespace(**{**vars(sc), "shading": "lit"}), want_gbuf=False)
+    np.testing.assert_array_equal(d["primid"], f["primid"])
+    np.testing.assert_array_equal(d["color"], f["color"])
+
+
 # ---------------------------------------------------------------------------
 # backward: central differences are exact for the quadratic loss
 # ---------------------------------------------------------------------------
