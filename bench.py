@@ -104,7 +104,8 @@ def kernel_source_hash() -> str:
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1404_6293_amd", "csrc")
-    for path in sorted(os.listdir(csrc)) + ["../../include/pk.h"]:
+    srcs = [f for f in sorted(os.listdir(csrc)) if not f.startswith("probe_")]
+    for path in srcs + ["../../include/pk.h"]:
         with open(os.path.join(csrc, path), encoding="utf-8") as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)

@@ -68,6 +68,7 @@ def _load():
                "orc_setup": (C.c_int, [P, P, P, P]),
                "orc_assign_bin": (C.c_int64, [P, C.c_int32, P, P, C.c_int64]),
                "orc_render": (C.c_int, [P, P]),
+               "orc_render_rows": (C.c_int, [P, P, C.c_int32, C.c_int32]),
                "orc_render_oit": (C.c_int, [P, P, C.c_int32, P, P, P, P]),
                "orc_backward": (C.c_int, [P, P, P, P, P, P])}
         for name, (res, args) in sig.items():
@@ -89,8 +90,8 @@ class using_library:
         self.saved = _lib
         _load()                      # make sure the real one is set up first
         lib = C.CDLL(self.path)
-        for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_render_oit",
-                     "orc_backward"):
+        for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_render_rows",
+                     "orc_render_oit", "orc_backward"):
             src, dst = getattr(_lib, name), getattr(lib, name)
             dst.restype, dst.argtypes = src.restype, src.argtypes
         _lib = lib
@@ -199,10 +200,17 @@ def assign_bin(sc, bin_size: int):
     return off, tris[:total]
 
 
-def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool = False):
+def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool = False,
+           threads: int = 1):
     """Render every scene of ``sc``.  Returns a dict of arrays with a leading
     scene axis: color [S][H][W][4], depth, primid, bary, gbuf_normal,
-    gbuf_albedo, cover_count, frag_count [S]."""
+    gbuf_albedo, cover_count, frag_count [S].
+
+    ``threads`` > 1 renders on that many host threads (the C calls release
+    the interpreter lock): several scenes run side by side, and a single
+    scene is cut into bands of pixel rows (orc_render_rows).  Every pixel is
+    computed on its own, so the result is the single-threaded one bit for
+    bit."""
     lib = _load()
     parts = list(scene_parts(sc))
     S, H, W = len(parts), int(sc.height), int(sc.width)
@@ -215,16 +223,34 @@ def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool 
                gbuf_albedo=np.zeros((S, H, W, 3), np.float32) if want_gbuf else None,
                cover_count=np.zeros((S, H, W), np.int32) if want_cover else None,
                frag_count=np.zeros(S, np.uint64))
-    for i, part in enumerate(parts):
+    # bands of rows: one per scene, or (one scene on several threads) about
+    # four per thread so that uneven bands even out
+    nb = 1 if (threads <= 1 or S > 1) else min(H, 4 * threads)
+    edges = [H * k // nb for k in range(nb + 1)]
+    fc = np.zeros((S, nb), np.uint64)
+    structs = []
+    for part in parts:
         keep = _Keep()
-        s = _scene_struct(part, keep)
+        structs.append((_scene_struct(part, keep), keep))
+
+    def one(job):
+        i, b = job
         sel = lambda a: None if a is None else a[i].ctypes.data  # noqa: E731
         t = _Targets(sel(out["color"]), sel(out["depth"]), sel(out["primid"]), sel(out["bary"]),
                      sel(out["gbuf_normal"]), sel(out["gbuf_albedo"]), sel(out["cover_count"]),
-                     out["frag_count"][i:].ctypes.data)
-        rc = lib.orc_render(C.byref(s), C.byref(t))
-        if rc != 0:
-            raise MemoryError("oracle render failed")
+                     fc[i, b:].ctypes.data)
+        return lib.orc_render_rows(C.byref(structs[i][0]), C.byref(t), edges[b], edges[b + 1])
+
+    jobs = [(i, b) for i in range(S) for b in range(nb)]
+    if threads <= 1:
+        rcs = [one(j) for j in jobs]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            rcs = list(ex.map(one, jobs))
+    if any(rc != 0 for rc in rcs):
+        raise MemoryError("oracle render failed")
+    out["frag_count"][:] = fc.sum(axis=1)
     return out
 
 

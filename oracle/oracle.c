@@ -367,21 +367,34 @@ int64_t orc_assign_bin(const orc_scene *s, int32_t bin_size, int32_t *bin_off,
  * 64-bit key (depth bits << 32 | triangle index) among fragments with
  * 0 <= z < 1, then the shading of that winner.
  */
-int orc_render(const orc_scene *s, const orc_targets *o)
+/*
+ * The same definition for the pixel rows [row0, row1) only: every pixel is
+ * computed on its own, so rendering the rows in disjoint bands (for instance
+ * one band per host thread) gives the whole image bit for bit.  Writes the
+ * band's rows of every target; *frag_count receives the band's covered
+ * samples.
+ */
+int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int32_t row1)
 {
     const int W = s->width, H = s->height;
-    const int64_t npx = (int64_t)W * H;
+    if (row0 < 0) row0 = 0;
+    if (row1 > H) row1 = H;
+    if (row1 < row0) row1 = row0;
+    const int64_t base = (int64_t)row0 * W;           /* first pixel of the band */
+    const int64_t npx = (int64_t)(row1 - row0) * W;
     uint64_t *zbuf = malloc(sizeof(uint64_t) * (size_t)(npx > 0 ? npx : 1));
     if (!zbuf) return -1;
     for (int64_t p = 0; p < npx; ++p) zbuf[p] = ~0ull;
-    if (o->cover_count) memset(o->cover_count, 0, sizeof(int32_t) * (size_t)npx);
+    if (o->cover_count) memset(o->cover_count + base, 0, sizeof(int32_t) * (size_t)npx);
     uint64_t frags = 0;
 
     /* steps 2, 4, 5, 6: every triangle in submission order, every sample of its bbox */
     for (int64_t t = 0; t < s->num_tris; ++t) {
         otri r = setup_stage(s, t);
         if (!r.live) continue;
-        for (int py = r.by0; py <= r.by1; ++py) {
+        const int y0 = r.by0 > row0 ? r.by0 : row0;
+        const int y1 = r.by1 < row1 - 1 ? r.by1 : row1 - 1;
+        for (int py = y0; py <= y1; ++py) {
             for (int px = r.bx0; px <= r.bx1; ++px) {
                 const int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
                 int64_t E[3];
@@ -395,18 +408,19 @@ int orc_render(const orc_scene *s, const orc_targets *o)
                 const float z = depth_of(&r, beta);
                 if (!(0.0f <= z && z < 1.0f)) continue;
                 const uint64_t key = ((uint64_t)float_bits(z) << 32) | (uint32_t)t;
-                if (key < zbuf[p]) zbuf[p] = key;
+                if (key < zbuf[p - base]) zbuf[p - base] = key;
             }
         }
     }
     if (o->frag_count) *o->frag_count = frags;
 
     /* step 7: resolve and shade every pixel */
-    for (int py = 0; py < H; ++py) {
+    for (int py = row0; py < row1; ++py) {
         for (int px = 0; px < W; ++px) {
             const int64_t p = (int64_t)py * W + px;
+            const uint64_t kp = zbuf[p - base];
             float *col = o->color ? o->color + 4 * p : NULL;
-            if (zbuf[p] == ~0ull) {
+            if (kp == ~0ull) {
                 if (col) col[0] = col[1] = col[2] = col[3] = 0.0f;
                 if (o->depth) o->depth[p] = 1.0f;
                 if (o->primid) o->primid[p] = -1;
@@ -415,8 +429,8 @@ int orc_render(const orc_scene *s, const orc_targets *o)
                 if (o->gbuf_albedo) o->gbuf_albedo[3 * p] = o->gbuf_albedo[3 * p + 1] = o->gbuf_albedo[3 * p + 2] = 0.0f;
                 continue;
             }
-            const int64_t t = (int64_t)(zbuf[p] & 0xffffffffull);
-            const float z = bits_float((uint32_t)(zbuf[p] >> 32));
+            const int64_t t = (int64_t)(kp & 0xffffffffull);
+            const float z = bits_float((uint32_t)(kp >> 32));
             otri r = setup_stage(s, t);
             int64_t E[3];
             edge_values(&r, 256 * (int64_t)px + 128, 256 * (int64_t)py + 128, E);
@@ -470,6 +484,11 @@ int orc_render(const orc_scene *s, const orc_targets *o)
     }
     free(zbuf);
     return 0;
+}
+
+int orc_render(const orc_scene *s, const orc_targets *o)
+{
+    return orc_render_rows(s, o, 0, s->height);
 }
 
 /*

@@ -134,17 +134,30 @@ def test_autotuner_picks_a_config_with_the_same_image(tmp_path):
         assert torch.equal(a[k], b[k])
 
 
-def test_micro8m_full_frame_deferred():
-    """8,388,608 micropolygons at 1920x1080, deferred, in the benchmark's
-    launch configuration: full-frame comparison with the oracle."""
+_MICRO = {}
+
+
+def _micro8m():
+    """The micro8m scene and its oracle render, made once for the module."""
+    if not _MICRO:
+        sc = scenes.micro()
+        _MICRO["scene"] = sc
+        _MICRO["oracle"] = oracle.render(sc, want_bary=False)
+    return _MICRO["scene"], _MICRO["oracle"]
+
+
+@pytest.mark.parametrize("bin_size", [16, 0])
+def test_micro8m_full_frame_deferred(bin_size):
+    """8,388,608 micropolygons at 1920x1080, deferred, full frame against the
+    oracle: with 16-px bins, and with whole-screen bins, the benchmark's
+    (autotuned) launch configuration for this workload."""
     import torch
-    _note("micro8m full frame")
-    sc = scenes.micro()
-    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=0,
+    _note(f"micro8m full frame bin_size={bin_size}")
+    sc, o = _micro8m()
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=bin_size, schedule="direct_map", threads_per_bin=0,
                                         count_frags=True, want_bary=False))
     out = r.render()
     torch.cuda.synchronize()
-    o = oracle.render(sc, want_bary=False)
     np.testing.assert_array_equal(out["primid"].cpu().numpy(), o["primid"])
     assert (out["depth"].cpu().numpy() == o["depth"]).all()
     np.testing.assert_allclose(out["color"].cpu().numpy(), o["color"], rtol=1e-5, atol=1e-6)
@@ -175,3 +188,120 @@ def test_batch256_sampled_scenes_and_plain_equivalence():
         o1 = r1.render()
         assert torch.equal(o1["primid"][0], ob["primid"][s])
         assert torch.equal(o1["color"][0], ob["color"][s])
+
+
+def _one_view(sc, j):
+    d = dict(vars(sc))
+    d.update(mvp=np.asarray(sc.mvp)[j:j + 1].copy(), num_scenes=1, instanced=False)
+    return SimpleNamespace(**d)
+
+
+def test_diff64_full_size_views_backward_and_central_differences():
+    """The differentiable workload at full size: 64 views at 512x512 of the
+    1,048,576-triangle grid, textured, in the benchmark's launch
+    configuration.  Sampled views match the oracle element by element
+    (primid and depth bit-exact); the backward of an image loss on those
+    views matches the oracle's float64 gradient; and on view 0 the gradient
+    of the sum-of-squares loss over the 32x32 crop at (240, 240) matches
+    central differences (h = 1e-3) of the GPU forward for 256 vertex-colour
+    and 256 texel scalars that reach the crop."""
+    import torch
+    _note("diff64 full size: forward of 64 views")
+    sc = scenes.diffgrid()
+    tgt_sc = scenes.diffgrid(seed=5001)
+    cfg = pk.RenderConfig(bin_size=16, schedule="direct_map", threads_per_bin=0, want_bary=True)
+    r = pk.Renderer(sc, cfg)
+    out = r.render()
+    torch.cuda.synchronize()
+    views = [0, 27, 63]
+    pid_v = out["primid"][views].cpu().numpy()
+    bary_v = out["bary"][views].cpu().numpy()
+    col_v = out["color"][views].cpu().numpy()
+    dep_v = out["depth"][views].cpu().numpy()
+    for i, j in enumerate(views):
+        _note(f"diff64 view {j} vs oracle")
+        o = oracle.render(_one_view(sc, j))
+        np.testing.assert_array_equal(pid_v[i], o["primid"][0])
+        assert (dep_v[i] == o["depth"][0]).all()
+        np.testing.assert_allclose(col_v[i], o["color"][0], rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(bary_v[i], o["bary"][0], rtol=1e-5, atol=1e-6)
+    assert (pid_v >= 0).sum() > 0.5 * pid_v.size
+
+    # backward over all 64 views with the upstream gradient non-zero on the
+    # sampled views only: the oracle's gradient of those views is the answer
+    _note("diff64 backward vs oracle gradient")
+    rng = np.random.default_rng(51)
+    G = np.zeros((64, 512, 512, 4), np.float32)
+    G[views] = rng.standard_normal((len(views), 512, 512, 4)).astype(np.float32)
+    gv = torch.zeros((3, sc.pos.shape[1]), dtype=torch.float32, device="cuda")
+    gt = torch.zeros(sc.texture.shape, dtype=torch.float32, device="cuda")
+    r.backward(torch.from_numpy(G).cuda(), gv, gt)
+    torch.cuda.synchronize()
+    sub = SimpleNamespace(**{**vars(sc), "mvp": np.asarray(sc.mvp)[views].copy(),
+                             "num_scenes": len(views)})
+    ov, ot = oracle.backward(sub, pid_v, bary_v, G[views])
+    av, at = oracle.backward(sub, pid_v, bary_v, np.abs(G[views]))
+    # float32 atomics summing n terms in any order: |error| <= n eps sum|terms|
+    n, eps = 1024, 2.0 ** -24
+    assert (np.abs(gv.cpu().numpy() - ov) <= 1e-4 * np.abs(ov) + n * eps * av + 1e-6).all()
+    assert (np.abs(gt.cpu().numpy() - ot) <= 1e-4 * np.abs(ot) + n * eps * at + 1e-6).all()
+    del r, out, gv, gt
+    torch.cuda.empty_cache()
+
+    # view 0: loss over the crop against a render of a second colour set
+    # and texture, its gradient, and central differences
+    _note("diff64 view 0: crop gradient and central differences")
+    y0, x0, cs = 240, 240, 32
+    v0 = _one_view(sc, 0)
+    r0 = pk.Renderer(v0, pk.RenderConfig(bin_size=16, want_bary=True))
+    img = r0.render()["color"].clone()
+    tgt = pk.Renderer(_one_view(tgt_sc, 0), pk.RenderConfig(bin_size=16)).render()["color"].clone()
+
+    def loss(im):
+        d = im[0, y0:y0 + cs, x0:x0 + cs, :3].double() - tgt[0, y0:y0 + cs, x0:x0 + cs, :3].double()
+        return float((d * d).sum())
+
+    Gc = torch.zeros_like(img)
+    Gc[0, y0:y0 + cs, x0:x0 + cs, :3] = (2.0 * (img[0, y0:y0 + cs, x0:x0 + cs, :3].double()
+                                               - tgt[0, y0:y0 + cs, x0:x0 + cs, :3].double())).float()
+    gv0 = torch.zeros((3, sc.pos.shape[1]), dtype=torch.float32, device="cuda")
+    gt0 = torch.zeros(sc.texture.shape, dtype=torch.float32, device="cuda")
+    r0.backward(Gc, gv0, gt0)
+    torch.cuda.synchronize()
+    gv0, gt0 = gv0.cpu().numpy().astype(np.float64), gt0.cpu().numpy().astype(np.float64)
+    pid0 = r0.out_primid.cpu().numpy()
+    b0 = r0.out_bary.cpu().numpy()
+    o0v, o0t = oracle.backward(v0, pid0, b0, Gc.cpu().numpy())
+    a0v, a0t = oracle.backward(v0, pid0, b0, np.abs(Gc.cpu().numpy()))
+    assert (np.abs(gv0 - o0v) <= 1e-4 * np.abs(o0v) + 64 * eps * a0v + 1e-6).all()
+    assert (np.abs(gt0 - o0t) <= 1e-4 * np.abs(o0t) + 64 * eps * a0t + 1e-6).all()
+    # parameters that reach the crop: vertices of the visible triangles, and
+    # texels with a non-zero gradient there
+    crop_t = np.unique(pid0[0, y0:y0 + cs, x0:x0 + cs])
+    crop_t = crop_t[crop_t >= 0]
+    verts = np.unique(sc.idx[crop_t].ravel())
+    vpar = [(int(c), int(v)) for c, v in zip(rng.integers(0, 3, 256), rng.choice(verts, 256))]
+    tnz = np.argwhere(np.abs(o0t) > 0)
+    tpar = [tuple(int(x) for x in tnz[k]) for k in rng.choice(len(tnz), 256, replace=False)]
+    h = 1e-3
+    col_t, tex_t = r0.dev.color, r0.dev.texture
+    base = img
+    worst = 0.0
+    for which, plist in (("vcolor", vpar), ("tex", tpar)):
+        for key in plist:
+            ref = float(gv0[key]) if which == "vcolor" else float(gt0[key])
+            T = col_t if which == "vcolor" else tex_t
+            orig = T[key].clone()
+            vals = []
+            for sgn in (1.0, -1.0):
+                T[key] = orig + sgn * h
+                r0.frame()
+                im = r0.out_color
+                vals.append((loss(im), float(T[key].item()), int((im != base).any(dim=-1).sum())))
+            T[key] = orig
+            fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+            changed = max(vals[0][2], vals[1][2])
+            bound = 1e-3 * abs(ref) + 1e-5 + changed * 3 * 4 * 6e-8 / (2 * h)
+            assert abs(fd - ref) <= bound, (which, key, fd, ref, bound)
+            worst = max(worst, abs(fd - ref) / bound)
+    _note(f"diff64 central differences: 512 scalars, worst error / bound = {worst:.3f}")

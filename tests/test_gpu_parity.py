@@ -56,7 +56,7 @@ def compare(sc, g, o, check_bary=True, check_color=True):
     assert int(g["frag_count"][0]) == int(o["frag_count"].sum())
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(100))
 def test_tiny64_random(seed):
     _note(f"tiny64 seed={seed}")
     sc = scenes.tiny(seed=seed)

@@ -22,8 +22,9 @@ MUTANTS = {
     "horizontal_edges_wrong": ("(dy == 0 && r->s * dx < 0)", "(dy == 0 && r->s * dx > 0)"),
     # (key < zbuf versus key <= zbuf is an equivalent mutation: keys carry the
     # triangle index, so two different fragments never have equal keys)
-    "later_equal_depth_wins": ("if (key < zbuf[p]) zbuf[p] = key;",
-                               "if ((key >> 32) <= (zbuf[p] >> 32) || zbuf[p] == ~0ull) zbuf[p] = key;"),
+    "later_equal_depth_wins": ("if (key < zbuf[p - base]) zbuf[p - base] = key;",
+                               "if ((key >> 32) <= (zbuf[p - base] >> 32) || zbuf[p - base] == ~0ull) "
+                               "zbuf[p - base] = key;"),
     "bbox_off_by_one": ("floor_div256((int64_t)mnx - 128 + 255)", "floor_div256((int64_t)mnx - 128 + 256)"),
     # (cutting the upper x bound the same way is an equivalent mutation: a
     # sample exactly on the right-most vertex is never covered under this rule)

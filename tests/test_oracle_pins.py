@@ -581,3 +581,25 @@ def test_assign_bin_vs_bruteforce(B):
         lst = list(tris[off[b]:off[b + 1]])
         assert lst == sorted(lst)
         assert lst == ref.get(b, []), b
+
+
+# ---------------------------------------------------------------------------
+# the oracle on several host threads
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("make", [
+    lambda: scenes.tiny(seed=4, width=61, height=47, num_tris=300),
+    lambda: scenes.grid(seed=3, width=80, height=45, nx=32, ny=16),
+    lambda: scenes.micro(num_tris=20000, width=96, height=64, seed=2),
+    lambda: scenes.batch(num_scenes=5, size=48, tmin=50, tmax=500, seed0=8),
+])
+def test_row_bands_on_threads_equal_single_thread(make):
+    """Pixels are computed independently, so rendering bands of rows (or
+    scenes) on several threads gives the single-threaded image bit for bit,
+    fragment counts included."""
+    sc = make()
+    a = oracle.render(sc, want_cover=True)
+    for threads in (2, 7):
+        b = oracle.render(sc, want_cover=True, threads=threads)
+        for k, v in a.items():
+            if v is not None:
+                np.testing.assert_array_equal(b[k], v, err_msg=k)
