@@ -88,7 +88,9 @@ extern "C" {
 typedef enum {
     PK_OK = 0,
     PK_ERR_INVALID_ARGUMENT = 1, /* bad parameter; nothing was enqueued */
-    PK_ERR_CAPACITY = 2,         /* reserved: pair overflow is reported on the device */
+    PK_ERR_CAPACITY = 2,         /* pk_render_static only: the frame does not fit the
+                                    library's static workspace (nothing was enqueued);
+                                    pair overflow is reported on the device instead */
     PK_ERR_HIP = 3,              /* a HIP runtime call or launch failed */
     PK_ERR_UNSUPPORTED = 4       /* valid request this build does not implement */
 } pk_status;
@@ -287,6 +289,29 @@ typedef struct {
 } pk_bin_view;
 
 pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_view *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * frame -- pk_setup, pk_assign_bin, pk_raster_shade and, with
+ * PK_FLAG_DEFER_SHADE, pk_shade -- on a workspace the library owns instead
+ * of a caller's `ws`.  That workspace is a static device array of
+ * PK_STATIC_WORKSPACE_BYTES on every GPU the library runs on, placed when
+ * the library's code is loaded there and held until the process ends; the
+ * call itself allocates nothing (no hipMalloc, no allocating library
+ * routine).  Every slice of the workspace but the bin-pair list must fit in
+ * it, else PK_ERR_CAPACITY is returned and nothing is enqueued (see
+ * pk_workspace_bytes with pair_capacity 0); the pair list takes the rest.
+ * *pairs_needed (device, one int64, or NULL) receives the frame's pair count
+ * as from pk_assign_bin; when the pairs outgrow the room left, the frame
+ * writes empty pixels (colour 0, depth 1, primid -1, bary 0) to every given
+ * target.  Arguments and results are otherwise those of the four calls.
+ * All calls on one GPU share its array and it keeps the last frame's
+ * contents (every frame clears what it needs): calls that overlap on one GPU
+ * (several streams or host threads) race, and the caller must serialize
+ * them. */
+#define PK_STATIC_WORKSPACE_BYTES (64ull << 20)
+pk_status pk_render_static(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
+                           const pk_targets *out, int64_t *pairs_needed, void *stream);
 
 /* Static description of a status code.  Host-only. */
 const char *pk_status_string(pk_status s);

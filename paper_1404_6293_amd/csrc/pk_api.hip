@@ -1,10 +1,19 @@
 // pk_api.hip -- the C ABI of libpk (include/pk.h): host-side validation,
 // workspace layout and kernel launches.  No allocation, no synchronization.
+#include <mutex>
 #include <new>
 
 #include "pk_internal.h"
 
 namespace pk {
+
+// The workspace of pk_render_static: one array per GPU, placed by the code
+// object loader (no allocation call), held until the process ends.  In host
+// code `scratch` names a host-side shadow, not device memory: its device
+// address is taken once per device with hipGetSymbolAddress (with that
+// device current) and only that address is ever handed to kernels.
+__device__ __align__(256) unsigned char scratch[PK_STATIC_WORKSPACE_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -159,6 +168,29 @@ Geom geom(const pk_params *p, const pk_mesh *m, const Frame &f) {
 
 pk_status hip_status(hipError_t e) { return e == hipSuccess ? PK_OK : PK_ERR_HIP; }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's array (nullptr on failure).
+void *static_workspace(hipError_t &err) {
+    int dev = -1;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) { err = hipErrorInvalidDevice; return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr) {
+            if (err == hipSuccess) err = hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 // Validation shared by pk_raster_shade and pk_shade, and the kernels' view of
 // the attributes and targets.
 pk_status shade_args(const pk_params *p, const pk_attribs *a, const pk_targets *out,
@@ -302,6 +334,29 @@ pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
                                       (hipStream_t)stream));
 }
 
+pk_status pk_render_static(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
+                           const pk_targets *out, int64_t *pairs_needed, void *stream) {
+    Frame f;
+    pk_status st = check_params(p, f);
+    if (st != PK_OK) return st;
+    if ((st = check_mesh(p, m, f)) != PK_OK) return st;
+    Shade sh;
+    if ((st = shade_args(p, a, out, f, sh)) != PK_OK) return st;
+    // every slice but the pair list must fit; the pairs take what is left
+    const size_t fixed = layout(f, 0).total;
+    if (fixed + kAlign > (size_t)PK_STATIC_WORKSPACE_BYTES) return PK_ERR_CAPACITY;
+    int64_t cap = (int64_t)(((size_t)PK_STATIC_WORKSPACE_BYTES - fixed - kAlign) / sizeof(int32_t));
+    if (cap >= (int64_t)INT32_MAX) cap = (int64_t)INT32_MAX - 1;
+    hipError_t err = hipSuccess;
+    void *ws = static_workspace(err);
+    if (!ws) return PK_ERR_HIP;
+    if ((st = pk_setup(p, m, ws, stream)) != PK_OK) return st;
+    if ((st = pk_assign_bin(p, m, ws, cap, pairs_needed, stream)) != PK_OK) return st;
+    if ((st = pk_raster_shade(p, m, a, ws, out, stream)) != PK_OK) return st;
+    if (p->flags & PK_FLAG_DEFER_SHADE) st = pk_shade(p, m, a, ws, out, stream);
+    return st;
+}
+
 pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_view *out) {
     Frame f;
     pk_status st = check_params(p, f);
@@ -320,7 +375,7 @@ const char *pk_status_string(pk_status s) {
     switch (s) {
     case PK_OK: return "ok";
     case PK_ERR_INVALID_ARGUMENT: return "invalid argument";
-    case PK_ERR_CAPACITY: return "pair capacity exceeded";
+    case PK_ERR_CAPACITY: return "frame does not fit the static workspace";
     case PK_ERR_HIP: return "HIP runtime error";
     case PK_ERR_UNSUPPORTED: return "unsupported request";
     }

@@ -32,7 +32,9 @@ SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
             "deferred": PK_SHADE_DEFERRED}
 
 EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_shade",
-           "pk_backward", "pk_bin_lists", "pk_status_string")
+           "pk_backward", "pk_bin_lists", "pk_status_string", "pk_render_static")
+# size of the library's static workspace used by pk_render_static (pk.h)
+PK_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 class PkError(RuntimeError):
@@ -97,6 +99,8 @@ def lib():
         L.pk_backward.argtypes = [P, P, P, P, P, P, P, P, P]
         L.pk_bin_lists.restype = C.c_int
         L.pk_bin_lists.argtypes = [P, P, P, P]
+        L.pk_render_static.restype = C.c_int
+        L.pk_render_static.argtypes = [P, P, P, P, P, P]
         L.pk_status_string.restype = C.c_char_p
         L.pk_status_string.argtypes = [C.c_int]
         _lib = L
@@ -147,6 +151,12 @@ def pk_backward(params: Params, mesh: Mesh, attribs: Attribs, primid: int, bary:
                 grad_color: int, grad_vcolor: int, grad_tex: int, stream: int = 0):
     _check("pk_backward", lib().pk_backward(_ref(params), _ref(mesh), _ref(attribs), primid, bary,
                                             grad_color, grad_vcolor, grad_tex, stream))
+
+
+def pk_render_static(params: Params, mesh: Mesh, attribs: Attribs, targets: Targets,
+                     pairs_needed: Optional[int] = None, stream: int = 0):
+    _check("pk_render_static", lib().pk_render_static(_ref(params), _ref(mesh), _ref(attribs),
+                                                      _ref(targets), pairs_needed, stream))
 
 
 def pk_bin_lists(params: Params, mesh: Mesh, ws: int) -> BinView:

@@ -220,3 +220,22 @@ def test_status_strings(L):
         assert pk.status_string(s)
     assert pk.status_string(99) == "unknown status"
     assert pk.status_string(pk.PK_ERR_INVALID_ARGUMENT) == "invalid argument"
+
+
+def test_static_workspace_rejects_frames_that_do_not_fit(L):
+    """pk_render_static checks on the host, before anything is enqueued, that
+    every workspace slice but the pair list fits its static workspace."""
+    at = pk.Attribs(FAKE, None, None, None, 0, 0, None, 0, None)
+    tg = pk.Targets(FAKE, FAKE, FAKE, None, None, None, None)
+    # 8192 x 8192 keys alone take 512 MiB
+    p = _params(width=8192, height=8192, bin_size=0)
+    assert L.pk_workspace_bytes(C.byref(p), C.byref(_mesh()), 0) > pk.PK_STATIC_WORKSPACE_BYTES
+    assert L.pk_render_static(C.byref(p), C.byref(_mesh()), C.byref(at), C.byref(tg), None,
+                              None) == pk.PK_ERR_CAPACITY
+    # invalid arguments are still invalid
+    bad = _params(bin_size=12)
+    assert L.pk_render_static(C.byref(bad), C.byref(_mesh()), C.byref(at), C.byref(tg), None,
+                              None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert L.pk_render_static(C.byref(_params()), C.byref(_mesh()), None, C.byref(tg), None,
+                              None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert "static workspace" in pk.status_string(pk.PK_ERR_CAPACITY)
