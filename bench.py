@@ -56,44 +56,51 @@ def make_scene(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def bin_kernel_algorithmic_bytes(sc, npairs: int, B: int) -> int:
-    """Algorithmic bytes of one launch of the per-bin coverage + depth-test
-    kernel (k_raster, keys written for the per-pixel pass): per (bin, triangle)
-    pair the 4-byte list entry and the 36 bytes that coverage and depth need
-    of the triangle (three snapped vertices: x, y, z as 32-bit words); per bin
-    its two 4-byte CSR offsets; per pixel the 8-byte winning (depth, primitive)
-    key it writes.  The setup record's actual size (32 B) is an
-    implementation choice and is not counted."""
+def algorithmic_bytes(sc, npairs: int, covered: int, want_bary: bool, B: int) -> dict:
+    """Algorithmic HBM bytes of one whole frame, split over the frame's four
+    stages: every input read once, every (bin, triangle) pair written once
+    and read once (4 B each way), every output written once (and the
+    deferred G-buffer read back once by the lighting pass).  What a stage
+    passes to the next through the workspace (setup records, boxes, keys)
+    is an implementation choice and is not counted.  A vertex attribute
+    plane counts as read whole, or as the visible triangles' three vertex
+    values per covered pixel when that is less (independent
+    micropolygons, where most triangles are hidden or cover no sample).
+    Instanced views read the mesh once per view.
+
+    Stages: `setup` reads positions (and indices); `assign_bin` writes the
+    pairs and the CSR offsets; `raster` reads the pairs and offsets and
+    writes every pixel's depth and primitive ID; `shade` gathers the
+    attributes and writes colour (bary; G-buffer, then reads it back and
+    writes colour for deferred shading).  Returns {stage: bytes, "frame":
+    total}."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
+    views = S if getattr(sc, "instanced", False) else 1
+    V = int(sc.pos.shape[1]) * views
+    T = int(sc.num_tris) * views
     npix = S * sc.width * sc.height
-    nbins = S * (-(-sc.width // B)) * (-(-sc.height // B))
-    return 40 * npairs + 8 * nbins + 8 * npix
+    nbins = 0 if not B else S * (-(-sc.width // B)) * (-(-sc.height // B))
+    shading = getattr(sc, "shading", "gouraud")
+    indexed = sc.idx is not None
 
-
-def direct_kernel_algorithmic_bytes(sc, tris: int) -> int:
-    """Algorithmic bytes of the unbinned raster (whole-screen bins: the key
-    clear and k_direct): per input triangle the 36 bytes that coverage and
-    depth need (three snapped vertices: x, y, z as 32-bit words); per pixel
-    the 8-byte (depth, primitive) key cleared and left for the per-pixel
-    pass (16 B).  There is no bin list."""
-    S = int(getattr(sc, "num_scenes", 1) or 1)
-    return 36 * tris + 16 * S * sc.width * sc.height
-
-
-def shade_pass_algorithmic_bytes(sc, covered_px: int, want_bary: bool) -> int:
-    """Algorithmic bytes of the per-pixel resolve + shade pass (k_resolve):
-    every pixel's primitive ID read once (4 B, written by the bin kernel),
-    the colour written once (16 B; for deferred the G-buffer 24 B instead),
-    the barycentrics (8 B) when saved, and the attributes of the visible
-    triangle gathered once per covered pixel (3 vertex indices 12 B when
-    indexed, 3 x 3 colour floats 36 B, plus 36 B of normals for
-    deferred)."""
-    S = int(getattr(sc, "num_scenes", 1) or 1)
-    npix = S * sc.width * sc.height
-    deferred = getattr(sc, "shading", "gouraud") == "deferred"
-    per_px = 4 + (24 if deferred else 16) + (8 if want_bary else 0)
-    per_cov = (12 if sc.idx is not None else 0) + 36 + (36 if deferred else 0)
-    return per_px * npix + per_cov * covered_px
+    def plane(ch):   # one attribute of ch float32 channels
+        return min(4 * ch * V, 3 * 4 * ch * covered)
+    setup = 12 * V + (12 * T if indexed else 0)
+    assign = 4 * npairs + 4 * (nbins + 1)
+    raster = 4 * npairs + 4 * (nbins + 1) + 8 * npix
+    shade = plane(3)
+    if shading == "textured":
+        tex = getattr(sc, "texture", None)
+        shade += plane(2) + min(int(tex.size) * 4 * views, 4 * 12 * covered)
+    if shading == "deferred":
+        shade += plane(3) + 24 * npix + 24 * npix + 16 * npix
+    else:
+        shade += 16 * npix
+    if want_bary:
+        shade += 8 * npix
+    out = {"setup": setup, "assign_bin": assign, "raster": raster, "shade": shade}
+    out["frame"] = sum(out.values())
+    return out
 
 
 def kernel_source_hash() -> str:
@@ -149,25 +156,122 @@ def profiled_valu_busy(workload: str, kernel: str):
     return None
 
 
-def cpu_baseline(sc, budget_s: float = 12.0):
-    """The oracle as it stands (single-threaded C) timed on this host on the
-    same workload: whole scenes, one after another, until the time budget is
-    used (at least one)."""
+def host_cpus() -> int:
+    """Host threads the oracle may use: this process's CPU set, at most 16
+    (a GPU machine's CPU share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_rate(parts, budget_s, threads, frags_of=None):
+    """Render the single-scene parts one after another (cycling) with the
+    oracle on `threads` host threads until `budget_s` is used (at least one).
+    Returns (triangles, fragments, scenes, seconds)."""
     import oracle
-    parts = list(oracle.scene_parts(sc))
-    done_tris, done, t0 = 0, 0, time.perf_counter()
+    done_tris = done_frags = done = 0
+    t0 = time.perf_counter()
     while True:
         part = parts[done % len(parts)]
-        oracle.render(part, want_bary=False)
+        o = oracle.render(part, want_bary=False, threads=threads)
         done_tris += int(part.num_tris)
+        done_frags += int(o["frag_count"].sum())
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {"value": round(done_tris / dt / 1e6, 3), "unit": "Mtris/s", "cores": 1,
+    return done_tris, done_frags, done, time.perf_counter() - t0
+
+
+def cpu_baseline(sc, budget_s: float = 6.0):
+    """The oracle as it stands (plain C; one scene's pixel rows cut into
+    bands over host threads) timed on this host on the same workload, on
+    every host thread this process may use and on one: whole scenes, one
+    after another, until each time budget is used (at least one)."""
+    parts = list(__import__("oracle").scene_parts(sc))
+    n = host_cpus()
+    tris, frags, done, dt = _oracle_rate(parts, budget_s, n)
+    tris1, _, done1, dt1 = _oracle_rate(parts, budget_s, 1)
+    return {"value": round(tris / dt / 1e6, 3), "unit": "Mtris/s", "cores": n,
             "kind": "oracle",
-            "sample": f"{done} scene render(s) of the workload ({done_tris} triangles), "
-                      f"single-threaded, {dt:.1f} s"}
+            "sample": f"{done} whole-frame render(s) of the workload ({tris} triangles) on "
+                      f"{n} threads in {dt:.1f} s; {done1} on one thread in {dt1:.1f} s",
+            "gfrags_per_s": round(frags / dt / 1e9, 4),
+            "ms_per_frame": round(dt / done * 1e3, 2),
+            "single_thread": {"value": round(tris1 / dt1 / 1e6, 3), "unit": "Mtris/s",
+                              "ms_per_frame": round(dt1 / done1 * 1e3, 2)},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_baseline_configs(budget_s: float = 4.0) -> dict:
+    """The oracle on the other workloads (all host threads this process may
+    use), each on a bounded sample: micro8m whole frames; batch256 scenes
+    (scaled to the 256-scene frame by triangles); diff64 views forward, and
+    the float64 reference backward of those views, scaled to 64 views."""
+    import numpy as np
+
+    import oracle
+    from paper_1404_6293_amd import scenes
+    n = host_cpus()
+    out = {}
+    sc = scenes.micro()
+    tris, frags, done, dt = _oracle_rate([sc], budget_s, n)
+    out["micro8m"] = {"ms_per_frame": round(dt / done * 1e3, 1),
+                      "mtris_per_s": round(tris / dt / 1e6, 3),
+                      "gfrags_per_s": round(frags / dt / 1e9, 4), "frames": done}
+    del sc
+    sc = scenes.batch()
+    parts = list(oracle.scene_parts(sc))
+    total = int(sc.num_tris)
+    t0 = time.perf_counter()
+    done_tris = done_frags = k = 0
+    while time.perf_counter() - t0 < budget_s and k < len(parts):
+        o = oracle.render(parts[k], want_bary=False, threads=1)
+        done_tris += int(parts[k].num_tris)
+        done_frags += int(o["frag_count"].sum())
+        k += 1
+    dt = time.perf_counter() - t0
+    # scenes are independent: n threads render n scenes side by side; the
+    # sample ran on one thread, so the n-thread frame is scaled by n
+    out["batch256"] = {"ms_per_frame_one_thread": round(dt * total / done_tris * 1e3, 1),
+                       "ms_per_frame_est_all_threads": round(dt * total / done_tris / n * 1e3, 1),
+                       "mtris_per_s_one_thread": round(done_tris / dt / 1e6, 3),
+                       "scenes_sampled": k}
+    del sc, parts
+    sc = scenes.diffgrid()
+    views = list(oracle.scene_parts(sc))
+    t0 = time.perf_counter()
+    fwd = bwd = 0.0
+    k = 0
+    rng = np.random.default_rng(0)
+    while k < len(views) and time.perf_counter() - t0 < budget_s:
+        a = time.perf_counter()
+        o = oracle.render(views[k], want_bary=True, threads=n)
+        b = time.perf_counter()
+        g = rng.standard_normal((1, sc.height, sc.width, 4)).astype(np.float32)
+        oracle.backward(views[k], o["primid"], o["bary"], g)
+        c = time.perf_counter()
+        fwd += b - a
+        bwd += c - b
+        k += 1
+    out["diff64"] = {"forward_ms_per_64_views": round(fwd / k * 64 * 1e3, 1),
+                     "backward_fp64_ms_per_64_views": round(bwd / k * 64 * 1e3, 1),
+                     "views_sampled": k,
+                     "note": "forward on all threads; the reference backward is single-threaded"}
+    out["threads"] = n
+    return out
 
 
 def _median_ms(torch, fn, reps):
@@ -185,11 +289,11 @@ def _median_ms(torch, fn, reps):
 
 
 def _tuned(sc, cands, want_bary=False):
-    """Autotuned configuration for a scene (cached across bench runs)."""
+    """Autotuned configuration for a scene, tuned afresh on every run (no
+    cache: a stale entry from other kernels would skip the tuning)."""
     from paper_1404_6293_amd import autotune
-    cache = os.environ.get(autotune.CACHE_ENV, os.path.join(ROOT, "gpurun_out", "autotune.json"))
     best, times = autotune.autotune(sc, want_bary=want_bary, cands=cands, reps=3,
-                                    cache_path=cache)
+                                    use_cache=False)
     return best, times
 
 
@@ -228,8 +332,19 @@ def bench_batched(reps: int = 10) -> dict:
             r.frame()
     ms_p = _median_ms(torch, seq, max(3, reps // 3))
     tris = int(sc.num_tris)
+    # algorithmic bytes of the batched frame (pairs and covered pixels of the
+    # tuned configuration)
+    rb = pk.Renderer(dev, cfg)
+    rb.render()
+    torch.cuda.synchronize()
+    npairs = int(rb.pairs_needed.item())
+    covered = int((rb.out_primid >= 0).sum().item())
+    del rb
+    alg = algorithmic_bytes(sc, npairs, covered, False, cfg.bin_size)["frame"]
     return {"workload": "batch256: 256 scenes at 256x256, log-uniform 1K-200K random triangles "
                         "each (edge ~ log-normal around 4 px)",
+            "roofline_frame": {"alg_bytes": alg,
+                               "frac": round(alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "tuned": {"bin_size": cfg.bin_size, "schedule": cfg.schedule,
                       "threads_per_bin": cfg.threads_per_bin},
             "tuning_ms": {k: round(v, 4) for k, v in times.items()},
@@ -240,30 +355,80 @@ def bench_batched(reps: int = 10) -> dict:
             "batched_gfrags_per_s": round(frags / ms_b / 1e6, 3)}
 
 
+def _stage_ms(torch, r, reps):
+    """Mean ms of each of a frame's four calls (setup, assign_bin, raster,
+    shade), HIP events on the launch stream; `r` renders with defer_shade."""
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e in ev:
+        e[0].record(stream)
+        r.setup()
+        e[1].record(stream)
+        r.assign_bin()
+        e[2].record(stream)
+        r.raster_shade()
+        e[3].record(stream)
+        r.shade()
+        e[4].record(stream)
+    torch.cuda.synchronize()
+    names = ("setup", "assign_bin", "raster", "shade")
+    return {n: sum(e[i].elapsed_time(e[i + 1]) for e in ev) / reps for i, n in enumerate(names)}
+
+
 def bench_micro(reps: int = 10) -> dict:
     """2^23 micropolygons at 1920x1080 with deferred shading, bin size
-    autotuned in {0 (whole-screen bins), 8, 16, 32, 64}."""
+    autotuned in {0 (whole-screen bins), 8, 16, 32, 64}; frame and stage
+    times, the frame's fraction of the HBM roofline and, with whole-screen
+    bins, the depth test's device-scope atomics against the probe's rate at
+    the same address distribution (uniform over the screen)."""
     import torch
-    from paper_1404_6293_amd import autotune, pk, scenes
+    from paper_1404_6293_amd import autotune, pk, probe, scenes
     sc = scenes.micro()
     dev = pk.DeviceScene(sc)
     cands = list(autotune.candidates(bins=(0, 8, 16, 32, 64), schedules=("direct_map",),
                                      threads=(64, 128), fused=(False,)))
     cfg, times = _tuned(dev, cands)
     cfg.count_frags = True
+    cfg.defer_shade = True
+    cfg.want_bary = False
     r = pk.Renderer(dev, cfg)
     r.render()
     torch.cuda.synchronize()
     frags = int(r.frag_count.item())
+    npairs = int(r.pairs_needed.item())
+    covered = int((r.out_primid >= 0).sum().item())
     r.count_fragments(False)
     ms = _median_ms(torch, r.frame, reps)
+    st = _stage_ms(torch, r, reps)
     tris = int(sc.num_tris)
-    return {"workload": "micro8m: 1920x1080, 8,388,608 micropolygons (log-normal area around "
-                        "0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
-            "tuned": {"bin_size": cfg.bin_size, "schedule": cfg.schedule},
-            "tuning_ms": {k: round(v, 4) for k, v in times.items()},
-            "frame_ms": round(ms, 4), "mtris_per_s": round(tris / ms / 1e3, 1),
-            "gfrags_per_s": round(frags / ms / 1e6, 3)}
+    alg = algorithmic_bytes(sc, npairs, covered, False, cfg.bin_size)
+    out = {"workload": "micro8m: 1920x1080, 8,388,608 micropolygons (log-normal area around "
+                       "0.5 px^2), deferred shading over an fp32 G-buffer, 1 light",
+           "tuned": {"bin_size": cfg.bin_size, "schedule": cfg.schedule},
+           "tuning_ms": {k: round(v, 4) for k, v in times.items()},
+           "frame_ms": round(ms, 4), "mtris_per_s": round(tris / ms / 1e3, 1),
+           "gfrags_per_s": round(frags / ms / 1e6, 3),
+           "stage_ms": {k: round(v, 4) for k, v in st.items()},
+           "covered_pixels": covered, "bin_pairs": npairs,
+           "roofline_frame": {"alg_bytes": alg["frame"],
+                              "frac": round(alg["frame"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "roofline_stages": {n: round(alg[n] / (st[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                               for n in st if st[n] > 0}}
+    if cfg.bin_size == 0:
+        npix = sc.width * sc.height
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        addr = torch.randint(0, npix, (frags,), device="cuda", dtype=torch.int32, generator=g)
+        peak = probe.global_min_u64_rate(addr, npix)
+        del addr
+        rate = frags / (st["raster"] * 1e-3) / 1e9
+        out["atomic_roofline"] = {"ops": frags, "kind": "device-scope 64-bit atomic min",
+                                  "rate_g_per_s": round(rate, 2),
+                                  "probe_peak_g_per_s": round(peak, 2),
+                                  "probe": "pkp_global_min_u64, uniform pixel addresses",
+                                  "frac": round(rate / peak, 4)}
+    return out
 
 
 def bench_lights(reps: int = 5) -> dict:
@@ -353,18 +518,21 @@ def measured_stream_bandwidth(torch, mib: int = 1024, reps: int = 5) -> float:
     return 2 * n / (ms * 1e-3) / 1e9
 
 
-def plain_scatter_rate(torch, r, sc, reps: int = 3) -> float:
-    """Rate (G/s) of a plain float32 atomic scatter (torch index_add_) over the
-    same addresses as the textured backward: 3 vertices x 3 channels of the
-    winning triangle and 4 bilinear taps x 3 channels of the texture per
-    covered pixel.  The reference rate for the backward's atomics."""
+def scatter_rates(torch, r, sc, reps: int = 3) -> dict:
+    """Rates (G/s) of plain float32 atomic scatters over the same addresses,
+    in the same order, as the textured backward's: per covered pixel (pixel
+    by pixel) 3 vertices x 3 channels of the winning triangle and 4 bilinear
+    taps x 3 channels of the texture.  `probe`: one device-scope atomic add
+    per address (pkp_global_add_f32), the atomic roofline's denominator;
+    `index_add`: torch's index_add_ for comparison."""
+    from paper_1404_6293_amd import probe
     prim = r.out_primid.reshape(-1)
     cov = prim >= 0
     t = prim[cov].long()
     V = sc.pos.shape[1]
     idx = torch.as_tensor(sc.idx, device="cuda").long().reshape(-1, 3)
     tri = idx[t]                                     # [N, 3] vertex numbers
-    parts = [tri[:, k] + ch * V for ch in range(3) for k in range(3)]
+    parts = [tri[:, k] + ch * V for k in range(3) for ch in range(3)]
     bary = r.out_bary.reshape(-1, 2)[cov]
     b1, b2 = bary[:, 0], bary[:, 1]
     b0 = 1.0 - b1 - b2
@@ -375,20 +543,23 @@ def plain_scatter_rate(torch, r, sc, reps: int = 3) -> float:
     i0 = torch.clamp(torch.floor(u * tw - 0.5), -1, tw).long()
     j0 = torch.clamp(torch.floor(v * th - 0.5), -1, th).long()
     base = 3 * V
-    for di in (0, 1):
-        for dj in (0, 1):
+    for dj in (0, 1):
+        for di in (0, 1):
             ii = torch.clamp(i0 + di, 0, tw - 1)
             jj = torch.clamp(j0 + dj, 0, th - 1)
             for ch in range(3):
                 parts.append(base + (jj * tw + ii) * 3 + ch)
-    addr = torch.cat(parts)
+    addr = torch.stack(parts, dim=1).reshape(-1)     # pixel by pixel
     del parts, tri, bary, u, v, i0, j0
+    n = 3 * V + th * tw * 3
+    out = {"scatters": int(addr.numel()),
+           "probe": probe.global_add_f32_rate(addr.to(torch.int32).contiguous(), n)}
     vals = torch.ones(addr.numel(), dtype=torch.float32, device="cuda")
-    dst = torch.zeros(3 * V + th * tw * 3, dtype=torch.float32, device="cuda")
+    dst = torch.zeros(n, dtype=torch.float32, device="cuda")
     ms = _median_ms(torch, lambda: dst.index_add_(0, addr, vals), reps)
-    rate = addr.numel() / (ms * 1e-3) / 1e9
+    out["index_add"] = addr.numel() / (ms * 1e-3) / 1e9
     del addr, vals, dst
-    return rate
+    return out
 
 
 def bench_backward(reps: int = 10) -> dict:
@@ -415,18 +586,20 @@ def bench_backward(reps: int = 10) -> dict:
         gt.zero_()
         r.backward(g, gv, gt)
     ms_b = _median_ms(torch, bwd, reps)
-    atomics = covered * 21
-    ref_rate = plain_scatter_rate(torch, r, sc)
+    scatters = covered * 21
+    rates = scatter_rates(torch, r, sc)
+    rate = scatters / ms_b / 1e6
     return {"workload": "diff64: 64 views at 512x512 of a 1024x512-quad grid (1,048,576 "
                         "triangles), per-vertex RGB modulated by a bilinear 512x512x3 texture",
             "covered_pixels": covered, "forward_ms": round(ms_f, 4),
             "backward_ms": round(ms_b, 4), "backward_over_forward": round(ms_b / ms_f, 3),
-            "fp32_atomics": atomics,
-            "atomic_rate_g_per_s": round(atomics / ms_b / 1e6, 2),
-            "atomic_roofline": {"peak_g_per_s": round(ref_rate, 2),
-                                "peak_kind": "torch index_add_ over the same 21 addresses "
-                                             "per covered pixel",
-                                "frac": round(atomics / ms_b / 1e6 / ref_rate, 4)}}
+            "fp32_scatters": scatters,
+            "scatter_rate_g_per_s": round(rate, 2),
+            "atomic_roofline": {"peak_g_per_s": round(rates["probe"], 2),
+                                "peak_kind": "pkp_global_add_f32: one device-scope float32 "
+                                             "atomic add per scatter, same addresses and order",
+                                "frac": round(rate / rates["probe"], 4),
+                                "index_add_g_per_s": round(rates["index_add"], 2)}}
 
 
 def main():
@@ -589,35 +762,62 @@ def main():
     mtris = tris / (ms * 1e-3) / 1e6
     gfrags = frags / (ms * 1e-3) / 1e9
 
-    alg_bin = bin_kernel_algorithmic_bytes(sc, npairs, B) if B else 0
-    alg_px = shade_pass_algorithmic_bytes(sc, covered, bary)
-    if B == 0:
-        # whole-screen bins: the key clear and the unbinned raster
-        kern, t_ms = "k_direct", stage["raster"]
-        alg = direct_kernel_algorithmic_bytes(sc, tris)
-    elif fused:
-        # one kernel: no key written or read back
-        kern, t_ms = "k_raster (fused resolve)", stage["raster"]
-        alg = alg_bin + alg_px - 16 * S * sc.width * sc.height
-    else:
-        kern, alg, t_ms = "k_raster", alg_bin, stage["raster"]
-    achieved = alg / (t_ms * 1e-3) / 1e9
+    # algorithmic bytes per stage; the dominant kernel is the longest stage's
+    alg = algorithmic_bytes(sc, npairs, covered, bary, B)
+    deferred = getattr(sc, "shading", "gouraud") == "deferred"
+    kernels = {"setup": ("k_vertex + k_setup" if sc.idx is not None else "k_setup"),
+               "assign_bin": "k_scan + k_scatter" if B else "(none: whole-screen bins)",
+               "raster": "k_direct" if B == 0 else "k_raster",
+               "shade": "k_resolve" + (" + k_deferred" if deferred else "")}
+    shares = dict(alg)
+    if fused and B:
+        # the resolve runs inside the bin kernel: its bytes are that launch's
+        kernels["raster"] = "k_raster (fused resolve)"
+        shares["raster"] += shares["shade"] - 8 * S * sc.width * sc.height
+        shares["shade"] = 0
+    stages = {}
+    for n in names:
+        t_n = stage[n]
+        a_n = shares[n] / (t_n * 1e-3) / 1e9 if t_n > 0 else 0.0
+        stages[n] = {"kernel": kernels[n], "alg_bytes": shares[n], "avg_ms": round(t_n, 4),
+                     "achieved": round(a_n, 1), "frac": round(a_n / HBM_PEAK_GBS, 4)}
+    dom = max(("raster", "shade"), key=lambda n: stage[n])
+    kern = stages[dom]["kernel"]
+    t_ms, alg_k = stage[dom], shares[dom]
+    achieved = alg_k / (t_ms * 1e-3) / 1e9
+    prof_name = {"k_raster": "k_raster", "k_direct": "k_direct", "k_resolve": "k_resolve",
+                 "k_resolve + k_deferred": "k_resolve"}.get(kern)
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if fused else profiled_traffic(args.workload, kern),
-                "alg_bytes_per_launch": alg, "avg_launch_ms": round(t_ms, 4),
-                "valu_busy_pct": None if fused else profiled_valu_busy(args.workload, kern)}
+                "traffic": profiled_traffic(args.workload, prof_name) if prof_name else None,
+                "alg_bytes_per_launch": alg_k, "avg_launch_ms": round(t_ms, 4),
+                "valu_busy_pct": profiled_valu_busy(args.workload, prof_name) if prof_name else None,
+                "alg_bytes_definition": "inputs read once + 8 B per (bin, triangle) pair + "
+                                        "outputs written once; workspace records excluded",
+                "frame": {"alg_bytes": alg["frame"],
+                          "achieved": round(alg["frame"] / (ms * 1e-3) / 1e9, 1),
+                          "frac": round(alg["frame"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "frac_single_stream": round(alg["frame"] / (dt1 / K) / 1e9
+                                                      / HBM_PEAK_GBS, 4),
+                          "frac_sum_of_stages": round(alg["frame"] / (sum(stage.values()) * 1e-3)
+                                                      / 1e9 / HBM_PEAK_GBS, 4)},
+                "stages": stages}
+    if B and not fused:
+        # the bin kernel's depth test: one LDS 64-bit atomic min per covered
+        # sample in range, against the probe's rate into 16x16-pixel tiles
+        try:
+            from paper_1404_6293_amd import probe
+            lds_rate = probe.lds_min_u64_rate(B * B if B <= 64 else 4096, True)
+            roofline["lds_atomic"] = {"ops": frags, "rate_g_per_s": round(frags / (stage["raster"] * 1e-3) / 1e9, 2),
+                                      "probe_peak_g_per_s": round(lds_rate, 1),
+                                      "frac": round(frags / (stage["raster"] * 1e-3) / 1e9 / lds_rate, 4)}
+        except (RuntimeError, OSError):
+            roofline["lds_atomic"] = None
     try:
         roofline["measured_stream_gbs"] = round(measured_stream_bandwidth(torch), 1)
         roofline["frac_of_measured"] = round(achieved / roofline["measured_stream_gbs"], 4)
     except RuntimeError:      # not enough free memory for the probe
         roofline["measured_stream_gbs"] = None
-    if not fused:
-        a2 = alg_px / (stage["shade"] * 1e-3) / 1e9
-        roofline["shade_pass"] = {"kernel": "k_resolve" + (" + k_deferred" if sc.shading == "deferred" else ""),
-                                  "achieved": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4),
-                                  "alg_bytes_per_launch": alg_px,
-                                  "avg_launch_ms": round(stage["shade"], 4)}
     out = {
         "metric": "Mtris/s + Gfrags/s at 1080p (binned raster); batched/backward vs plain, 1 GPU",
         "value": round(mtris, 2), "unit": "Mtris/s", "n_gpus": 1, "steps": K,
@@ -649,9 +849,10 @@ def main():
         print("bench: light count", file=sys.stderr, flush=True)
         out["lights"] = bench_lights()
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(sc)
-        cb["host"] = platform.processor() or platform.machine()
-        cb["host_cpus"] = os.cpu_count()
+        if not args.no_extras and args.workload == "grid1080":
+            cb["other_workloads"] = cpu_baseline_configs()
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

@@ -69,6 +69,8 @@ def _load():
                "orc_assign_bin": (C.c_int64, [P, C.c_int32, P, P, C.c_int64]),
                "orc_render": (C.c_int, [P, P]),
                "orc_render_rows": (C.c_int, [P, P, C.c_int32, C.c_int32]),
+               "orc_depth_keys": (C.c_int, [P, C.c_int64, C.c_int64, P, P, P]),
+               "orc_resolve_rows": (C.c_int, [P, P, P, C.c_int32, C.c_int32]),
                "orc_render_oit": (C.c_int, [P, P, C.c_int32, P, P, P, P]),
                "orc_backward": (C.c_int, [P, P, P, P, P, P])}
         for name, (res, args) in sig.items():
@@ -91,7 +93,7 @@ class using_library:
         _load()                      # make sure the real one is set up first
         lib = C.CDLL(self.path)
         for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_render_rows",
-                     "orc_render_oit", "orc_backward"):
+                     "orc_depth_keys", "orc_resolve_rows", "orc_render_oit", "orc_backward"):
             src, dst = getattr(_lib, name), getattr(lib, name)
             dst.restype, dst.argtypes = src.restype, src.argtypes
         _lib = lib
@@ -207,9 +209,12 @@ def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool 
     gbuf_albedo, cover_count, frag_count [S].
 
     ``threads`` > 1 renders on that many host threads (the C calls release
-    the interpreter lock): several scenes run side by side, and a single
-    scene is cut into bands of pixel rows (orc_render_rows).  Every pixel is
-    computed on its own, so the result is the single-threaded one bit for
+    the interpreter lock).  Several scenes run side by side.  A single scene
+    splits its triangles into one range per thread, each range's depth test
+    into a key buffer of its own (orc_depth_keys); the element-wise minimum
+    of those buffers is the scene's (the test is a minimum over keys), and
+    bands of pixel rows are then resolved and shaded on the threads
+    (orc_resolve_rows).  The result is the single-threaded one bit for
     bit."""
     lib = _load()
     parts = list(scene_parts(sc))
@@ -223,34 +228,63 @@ def render(sc, want_bary: bool = True, want_gbuf: bool = None, want_cover: bool 
                gbuf_albedo=np.zeros((S, H, W, 3), np.float32) if want_gbuf else None,
                cover_count=np.zeros((S, H, W), np.int32) if want_cover else None,
                frag_count=np.zeros(S, np.uint64))
-    # bands of rows: one per scene, or (one scene on several threads) about
-    # four per thread so that uneven bands even out
-    nb = 1 if (threads <= 1 or S > 1) else min(H, 4 * threads)
-    edges = [H * k // nb for k in range(nb + 1)]
-    fc = np.zeros((S, nb), np.uint64)
     structs = []
     for part in parts:
         keep = _Keep()
         structs.append((_scene_struct(part, keep), keep))
 
-    def one(job):
-        i, b = job
+    def targets(i, fc):
         sel = lambda a: None if a is None else a[i].ctypes.data  # noqa: E731
-        t = _Targets(sel(out["color"]), sel(out["depth"]), sel(out["primid"]), sel(out["bary"]),
-                     sel(out["gbuf_normal"]), sel(out["gbuf_albedo"]), sel(out["cover_count"]),
-                     fc[i, b:].ctypes.data)
-        return lib.orc_render_rows(C.byref(structs[i][0]), C.byref(t), edges[b], edges[b + 1])
+        return _Targets(sel(out["color"]), sel(out["depth"]), sel(out["primid"]),
+                        sel(out["bary"]), sel(out["gbuf_normal"]), sel(out["gbuf_albedo"]),
+                        sel(out["cover_count"]), None if fc is None else fc.ctypes.data)
 
-    jobs = [(i, b) for i in range(S) for b in range(nb)]
-    if threads <= 1:
-        rcs = [one(j) for j in jobs]
-    else:
-        from concurrent.futures import ThreadPoolExecutor
-        with ThreadPoolExecutor(max_workers=threads) as ex:
-            rcs = list(ex.map(one, jobs))
-    if any(rc != 0 for rc in rcs):
-        raise MemoryError("oracle render failed")
-    out["frag_count"][:] = fc.sum(axis=1)
+    if threads <= 1 or S > 1:
+        fc = np.zeros((S, 1), np.uint64)
+
+        def one(i):
+            t = targets(i, fc[i])
+            return lib.orc_render_rows(C.byref(structs[i][0]), C.byref(t), 0, H)
+        if threads <= 1:
+            rcs = [one(i) for i in range(S)]
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                rcs = list(ex.map(one, range(S)))
+        if any(rc != 0 for rc in rcs):
+            raise MemoryError("oracle render failed")
+        out["frag_count"][:] = fc[:, 0]
+        return out
+
+    from concurrent.futures import ThreadPoolExecutor
+    s0 = C.byref(structs[0][0])
+    T = int(parts[0].num_tris)
+    edges = [T * k // threads for k in range(threads + 1)]
+    zbs = [np.full(H * W, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64) for _ in range(threads)]
+    covs = [np.zeros(H * W, np.int32) if want_cover else None for _ in range(threads)]
+    fcs = np.zeros((threads, 1), np.uint64)
+
+    def keys(k):
+        return lib.orc_depth_keys(s0, edges[k], edges[k + 1], zbs[k].ctypes.data,
+                                  None if covs[k] is None else covs[k].ctypes.data,
+                                  fcs[k].ctypes.data)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(keys, range(threads)))
+    zbuf = zbs[0]
+    for zb in zbs[1:]:
+        np.minimum(zbuf, zb, out=zbuf)
+    del zbs
+    if want_cover:
+        out["cover_count"][0] = np.sum(covs, axis=0).reshape(H, W)
+    out["frag_count"][0] = fcs.sum()
+    nb = min(H, 4 * threads)
+    rows = [H * k // nb for k in range(nb + 1)]
+    t = targets(0, None)
+
+    def shade(b):
+        return lib.orc_resolve_rows(s0, zbuf.ctypes.data, C.byref(t), rows[b], rows[b + 1])
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(shade, range(nb)))
     return out
 
 

@@ -368,28 +368,19 @@ int64_t orc_assign_bin(const orc_scene *s, int32_t bin_size, int32_t *bin_off,
  * 0 <= z < 1, then the shading of that winner.
  */
 /*
- * The same definition for the pixel rows [row0, row1) only: every pixel is
- * computed on its own, so rendering the rows in disjoint bands (for instance
- * one band per host thread) gives the whole image bit for bit.  Writes the
- * band's rows of every target; *frag_count receives the band's covered
- * samples.
+ * Steps 2, 4, 5 and 6 for the triangles [t0, t1) and the pixel rows
+ * [row0, row1): every sample of every such triangle's bbox in those rows,
+ * its key min-ed into zbuf (pixel p at zbuf[p - row0 * W], which the caller
+ * fills with all ones), covered samples added to *frags and, when given,
+ * cover_count (pixel p at cover_count[p]).
  */
-int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int32_t row1)
+static void depth_keys(const orc_scene *s, int64_t t0, int64_t t1, int32_t row0, int32_t row1,
+                       uint64_t *zbuf, int32_t *cover_count, uint64_t *frags)
 {
-    const int W = s->width, H = s->height;
-    if (row0 < 0) row0 = 0;
-    if (row1 > H) row1 = H;
-    if (row1 < row0) row1 = row0;
-    const int64_t base = (int64_t)row0 * W;           /* first pixel of the band */
-    const int64_t npx = (int64_t)(row1 - row0) * W;
-    uint64_t *zbuf = malloc(sizeof(uint64_t) * (size_t)(npx > 0 ? npx : 1));
-    if (!zbuf) return -1;
-    for (int64_t p = 0; p < npx; ++p) zbuf[p] = ~0ull;
-    if (o->cover_count) memset(o->cover_count + base, 0, sizeof(int32_t) * (size_t)npx);
-    uint64_t frags = 0;
-
-    /* steps 2, 4, 5, 6: every triangle in submission order, every sample of its bbox */
-    for (int64_t t = 0; t < s->num_tris; ++t) {
+    const int W = s->width;
+    const int64_t base = (int64_t)row0 * W;
+    uint64_t n = 0;
+    for (int64_t t = t0; t < t1; ++t) {
         otri r = setup_stage(s, t);
         if (!r.live) continue;
         const int y0 = r.by0 > row0 ? r.by0 : row0;
@@ -401,8 +392,8 @@ int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int3
                 edge_values(&r, Px, Py, E);
                 if (!covers(&r, E)) continue;
                 const int64_t p = (int64_t)py * W + px;
-                frags += 1;
-                if (o->cover_count) o->cover_count[p] += 1;
+                n += 1;
+                if (cover_count) cover_count[p] += 1;
                 double beta[3];
                 barycentrics64(&r, E, beta);
                 const float z = depth_of(&r, beta);
@@ -412,8 +403,19 @@ int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int3
             }
         }
     }
-    if (o->frag_count) *o->frag_count = frags;
+    *frags += n;
+}
 
+/*
+ * Step 7 for the pixel rows [row0, row1) from their finished keys (pixel p
+ * at zbuf[p - row0 * W]): resolve and shade every pixel, writing every
+ * target of o.
+ */
+static void resolve_rows(const orc_scene *s, const uint64_t *zbuf, const orc_targets *o,
+                         int32_t row0, int32_t row1)
+{
+    const int W = s->width;
+    const int64_t base = (int64_t)row0 * W;
     /* step 7: resolve and shade every pixel */
     for (int py = row0; py < row1; ++py) {
         for (int px = 0; px < W; ++px) {
@@ -482,7 +484,62 @@ int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int3
             if (o->bary) { o->bary[2 * p] = bp[1]; o->bary[2 * p + 1] = bp[2]; }
         }
     }
+}
+
+/*
+ * The same definition for the pixel rows [row0, row1) only: every pixel is
+ * computed on its own, so rendering the rows in disjoint bands (for instance
+ * one band per host thread) gives the whole image bit for bit.  Writes the
+ * band's rows of every target; *frag_count receives the band's covered
+ * samples.
+ */
+int orc_render_rows(const orc_scene *s, const orc_targets *o, int32_t row0, int32_t row1)
+{
+    const int W = s->width, H = s->height;
+    if (row0 < 0) row0 = 0;
+    if (row1 > H) row1 = H;
+    if (row1 < row0) row1 = row0;
+    const int64_t base = (int64_t)row0 * W;           /* first pixel of the band */
+    const int64_t npx = (int64_t)(row1 - row0) * W;
+    uint64_t *zbuf = malloc(sizeof(uint64_t) * (size_t)(npx > 0 ? npx : 1));
+    if (!zbuf) return -1;
+    for (int64_t p = 0; p < npx; ++p) zbuf[p] = ~0ull;
+    if (o->cover_count) memset(o->cover_count + base, 0, sizeof(int32_t) * (size_t)npx);
+    uint64_t frags = 0;
+    depth_keys(s, 0, s->num_tris, row0, row1, zbuf, o->cover_count, &frags);
+    if (o->frag_count) *o->frag_count = frags;
+    resolve_rows(s, zbuf, o, row0, row1);
     free(zbuf);
+    return 0;
+}
+
+/*
+ * The depth test is a minimum over keys, so it can be split over the
+ * triangles as well: orc_depth_keys takes the triangles [t0, t1) over the
+ * whole screen into zbuf [H][W] (all ones beforehand), adding their covered
+ * samples to *frag_count and cover_count [H][W] (either may be NULL); the
+ * element-wise minimum of several ranges' buffers is the whole scene's, and
+ * orc_resolve_rows then shades any band of rows from it.  Together they
+ * give orc_render's image bit for bit.
+ */
+int orc_depth_keys(const orc_scene *s, int64_t t0, int64_t t1, uint64_t *zbuf,
+                   int32_t *cover_count, uint64_t *frag_count)
+{
+    if (t0 < 0) t0 = 0;
+    if (t1 > s->num_tris) t1 = s->num_tris;
+    uint64_t frags = 0;
+    depth_keys(s, t0, t1, 0, s->height, zbuf, cover_count, &frags);
+    if (frag_count) *frag_count += frags;
+    return 0;
+}
+
+int orc_resolve_rows(const orc_scene *s, const uint64_t *zbuf, const orc_targets *o,
+                     int32_t row0, int32_t row1)
+{
+    if (row0 < 0) row0 = 0;
+    if (row1 > s->height) row1 = s->height;
+    if (row1 <= row0) return 0;
+    resolve_rows(s, zbuf + (int64_t)row0 * s->width, o, row0, row1);
     return 0;
 }
 

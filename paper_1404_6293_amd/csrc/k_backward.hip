@@ -4,79 +4,166 @@
 // barycentrics (b0, b1, b2):
 //   untextured: dC[v_k][c] += b_k G_c
 //   textured:   dC[v_k][c] += b_k G_c T_c ,  dTex[j][c] += w_j G_c Cint_c
-// Coverage is not differentiated.  Scatters are float32 global atomics.
+// Coverage is not differentiated.
+//
+// Device-scope float atomics are slow on this part (about 20 G/s at spread
+// addresses, against about 2 T/s for LDS atomics), and neighbouring pixels
+// scatter to the same vertices (shared by neighbouring triangles) and the
+// same texels (overlapping bilinear footprints).  So each workgroup takes a
+// 16 x 16 pixel tile and sums its contributions per vertex and per texel in
+// LDS hash tables (open addressing, keys claimed by compare-and-swap, values
+// added with LDS float atomics), then adds each distinct entry to the
+// gradient buffers with one global atomic per channel.
 #include "pk_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace pk {
 
-__global__ __launch_bounds__(256) void k_backward(Geom G, Shade sh, const int32_t *primid,
-                                                  const float *bary, const float *grad,
-                                                  float *gv, float *gt) {
-    const int64_t npix = (int64_t)G.S * G.W * G.H;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    const int32_t t = primid[p];
-    if (t < 0) return;
-    const int32_t s = (int32_t)(p / ((int64_t)G.W * G.H));
-    int64_t g, vb;
-    if (G.S == 1 || G.instanced) { g = t; vb = 0; }
-    else { g = (int64_t)G.tri_off[s] + t; vb = G.vtx_off[s]; }
-    int64_t v[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = vb + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)t + k);
-    const float2 bb = reinterpret_cast<const float2 *>(bary)[p];
-    const float b1 = bb.x, b2 = bb.y, b0 = (1.0f - b1) - b2;
-    const float4 Gc = reinterpret_cast<const float4 *>(grad)[p];
-    const float gc[3] = {Gc.x, Gc.y, Gc.z};
+constexpr int kBwdTile = 16;                       // 16 x 16 pixels per workgroup
+constexpr int kBwdThreads = kBwdTile * kBwdTile;
+// A tile has at most 256 x 3 distinct vertices and 256 x 4 distinct texels:
+// the tables are sized so that they are never more than 3/4 and 1/2 full
+// and an insert always finds its key or a free slot.
+constexpr int kVtxSlots = 1024;
+constexpr int kTexSlots = 2048;
+constexpr int32_t kNoKey = -1;
+
+template <int N>
+__device__ inline uint32_t slot_of(int32_t key) {
+    return ((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(N));
+}
+
+// Add (v0, v1, v2) to the entry of `key` (>= 0), claiming a slot if needed.
+// Linear probing over at most N slots; the tables never fill (see above),
+// but should one, the values go straight to the global buffer at `gaddr`
+// with channel stride `gstride`.
+template <int N>
+__device__ inline void lds_accumulate(int32_t *keys, float *vals, int32_t key, float v0, float v1,
+                                      float v2, float *gbase, int64_t gstride) {
+    uint32_t h = slot_of<N>(key);
+#pragma unroll 1
+    for (int probe = 0; probe < N; ++probe) {
+        const int32_t k = atomicCAS(&keys[h], kNoKey, key);
+        if (k == kNoKey || k == key) {
+            atomicAdd(&vals[h], v0);
+            atomicAdd(&vals[N + h], v1);
+            atomicAdd(&vals[2 * N + h], v2);
+            return;
+        }
+        h = (h + 1) & (N - 1);
+    }
+    atomicAdd(gbase, v0);
+    atomicAdd(gbase + gstride, v1);
+    atomicAdd(gbase + 2 * gstride, v2);
+}
+
+template <bool TEX>
+__global__ __launch_bounds__(kBwdThreads) void k_backward(Geom G, Shade sh, const int32_t *primid,
+                                                          const float *bary, const float *grad,
+                                                          float *gv, float *gt) {
+    __shared__ int32_t s_vkey[kVtxSlots];
+    __shared__ float s_vval[3 * kVtxSlots];
+    __shared__ int32_t s_tkey[TEX ? kTexSlots : 1];
+    __shared__ float s_tval[TEX ? 3 * kTexSlots : 1];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kVtxSlots; i += kBwdThreads) {
+        s_vkey[i] = kNoKey;
+        s_vval[i] = s_vval[kVtxSlots + i] = s_vval[2 * kVtxSlots + i] = 0.0f;
+    }
+    if (TEX) {
+        for (int i = tid; i < kTexSlots; i += kBwdThreads) {
+            s_tkey[i] = kNoKey;
+            s_tval[i] = s_tval[kTexSlots + i] = s_tval[2 * kTexSlots + i] = 0.0f;
+        }
+    }
+    __syncthreads();
+
+    // this thread's pixel: tile (scene, tx, ty), position (lx, ly) in it
+    const uint32_t ntx = (uint32_t)((G.W + kBwdTile - 1) / kBwdTile);
+    const uint32_t nty = (uint32_t)((G.H + kBwdTile - 1) / kBwdTile);
+    const uint32_t per_scene = ntx * nty;
+    const uint32_t s = blockIdx.x / per_scene;
+    const uint32_t ts = blockIdx.x - s * per_scene;
+    const uint32_t ty = ts / ntx, tx = ts - ty * ntx;
+    const int px = (int)(tx * kBwdTile) + tid % kBwdTile;
+    const int py = (int)(ty * kBwdTile) + tid / kBwdTile;
     const int64_t V = G.V;
-    if (sh.shading == PK_SHADE_TEXTURED) {
-        float rgb[3];
+    const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
+    const int32_t t = (px < G.W && py < G.H) ? primid[p] : -1;
+    if (t >= 0) {
+        int64_t g, vb;
+        if (G.S == 1 || G.instanced) { g = t; vb = 0; }
+        else { g = (int64_t)G.tri_off[s] + t; vb = G.vtx_off[s]; }
+        int32_t v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float *pl = sh.color + c * V;
-            float acc = b0 * pl[v[0]];
-            acc = acc + b1 * pl[v[1]];
-            acc = acc + b2 * pl[v[2]];
-            rgb[c] = acc;
+        for (int k = 0; k < 3; ++k)
+            v[k] = (int32_t)(vb + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)t + k));
+        const float2 bb = reinterpret_cast<const float2 *>(bary)[p];
+        const float b1 = bb.x, b2 = bb.y, b0 = (1.0f - b1) - b2;
+        const float bw[3] = {b0, b1, b2};
+        const float4 Gc = reinterpret_cast<const float4 *>(grad)[p];
+        float gvc[3] = {Gc.x, Gc.y, Gc.z};     // what multiplies b_k per channel
+        if (TEX) {
+            float rgb[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float *pl = sh.color + c * V;
+                float acc = b0 * pl[v[0]];
+                acc = acc + b1 * pl[v[1]];
+                acc = acc + b2 * pl[v[2]];
+                rgb[c] = acc;
+            }
+            float u = b0 * sh.uv[v[0]];
+            u = u + b1 * sh.uv[v[1]];
+            u = u + b2 * sh.uv[v[2]];
+            float vv = b0 * sh.uv[V + v[0]];
+            vv = vv + b1 * sh.uv[V + v[1]];
+            vv = vv + b2 * sh.uv[V + v[2]];
+            const float su = u * (float)sh.tex_w - 0.5f, sv = vv * (float)sh.tex_h - 0.5f;
+            const float fi = floorf(su), fj = floorf(sv);
+            const float fs = su - fi, ft = sv - fj;
+            const float ci = fminf(fmaxf(fi, -1.0f), (float)sh.tex_w);
+            const float cj = fminf(fmaxf(fj, -1.0f), (float)sh.tex_h);
+            const int i0 = min(max((int)ci, 0), sh.tex_w - 1), i1 = min(max((int)ci + 1, 0), sh.tex_w - 1);
+            const int j0 = min(max((int)cj, 0), sh.tex_h - 1), j1 = min(max((int)cj + 1, 0), sh.tex_h - 1);
+            const float w[4] = {(1.0f - fs) * (1.0f - ft), fs * (1.0f - ft), (1.0f - fs) * ft, fs * ft};
+            const int32_t txl[4] = {j0 * sh.tex_w + i0, j0 * sh.tex_w + i1,
+                                    j1 * sh.tex_w + i0, j1 * sh.tex_w + i1};
+            float gC[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float T = w[0] * sh.texture[3 * (int64_t)txl[0] + c];
+                T = T + w[1] * sh.texture[3 * (int64_t)txl[1] + c];
+                T = T + w[2] * sh.texture[3 * (int64_t)txl[2] + c];
+                T = T + w[3] * sh.texture[3 * (int64_t)txl[3] + c];
+                gvc[c] = gvc[c] * T;
+                gC[c] = (c == 0 ? Gc.x : c == 1 ? Gc.y : Gc.z) * rgb[c];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lds_accumulate<kTexSlots>(s_tkey, s_tval, txl[j], w[j] * gC[0], w[j] * gC[1],
+                                          w[j] * gC[2], gt + 3 * (int64_t)txl[j], 1);
         }
-        float u = b0 * sh.uv[v[0]];
-        u = u + b1 * sh.uv[v[1]];
-        u = u + b2 * sh.uv[v[2]];
-        float vv = b0 * sh.uv[V + v[0]];
-        vv = vv + b1 * sh.uv[V + v[1]];
-        vv = vv + b2 * sh.uv[V + v[2]];
-        const float su = u * (float)sh.tex_w - 0.5f, sv = vv * (float)sh.tex_h - 0.5f;
-        const float fi = floorf(su), fj = floorf(sv);
-        const float fs = su - fi, ft = sv - fj;
-        const float ci = fminf(fmaxf(fi, -1.0f), (float)sh.tex_w);
-        const float cj = fminf(fmaxf(fj, -1.0f), (float)sh.tex_h);
-        const int i0 = min(max((int)ci, 0), sh.tex_w - 1), i1 = min(max((int)ci + 1, 0), sh.tex_w - 1);
-        const int j0 = min(max((int)cj, 0), sh.tex_h - 1), j1 = min(max((int)cj + 1, 0), sh.tex_h - 1);
-        const float w[4] = {(1.0f - fs) * (1.0f - ft), fs * (1.0f - ft), (1.0f - fs) * ft, fs * ft};
-        const int64_t tx[4] = {(int64_t)j0 * sh.tex_w + i0, (int64_t)j0 * sh.tex_w + i1,
-                               (int64_t)j1 * sh.tex_w + i0, (int64_t)j1 * sh.tex_w + i1};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float T = w[0] * sh.texture[3 * tx[0] + c];
-            T = T + w[1] * sh.texture[3 * tx[1] + c];
-            T = T + w[2] * sh.texture[3 * tx[2] + c];
-            T = T + w[3] * sh.texture[3 * tx[3] + c];
-            const float gT = gc[c] * T;
-            atomicAdd(gv + c * V + v[0], b0 * gT);
-            atomicAdd(gv + c * V + v[1], b1 * gT);
-            atomicAdd(gv + c * V + v[2], b2 * gT);
-            const float gC = gc[c] * rgb[c];
+        for (int k = 0; k < 3; ++k)
+            lds_accumulate<kVtxSlots>(s_vkey, s_vval, v[k], bw[k] * gvc[0], bw[k] * gvc[1],
+                                      bw[k] * gvc[2], gv + v[k], V);
+    }
+    __syncthreads();
+    // one global atomic per channel of every distinct vertex and texel
+    for (int i = tid; i < kVtxSlots; i += kBwdThreads) {
+        const int32_t k = s_vkey[i];
+        if (k == kNoKey) continue;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) atomicAdd(gt + 3 * tx[j] + c, w[j] * gC);
-        }
-    } else {
+        for (int c = 0; c < 3; ++c) atomicAdd(gv + c * V + k, s_vval[c * kVtxSlots + i]);
+    }
+    if (TEX) {
+        for (int i = tid; i < kTexSlots; i += kBwdThreads) {
+            const int32_t k = s_tkey[i];
+            if (k == kNoKey) continue;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            atomicAdd(gv + c * V + v[0], b0 * gc[c]);
-            atomicAdd(gv + c * V + v[1], b1 * gc[c]);
-            atomicAdd(gv + c * V + v[2], b2 * gc[c]);
+            for (int c = 0; c < 3; ++c) atomicAdd(gt + 3 * (int64_t)k + c, s_tval[c * kTexSlots + i]);
         }
     }
 }
@@ -84,10 +171,18 @@ __global__ __launch_bounds__(256) void k_backward(Geom G, Shade sh, const int32_
 hipError_t launch_backward(const Geom &G, const Shade &sh, const int32_t *primid,
                            const float *bary, const float *grad, float *grad_vcolor,
                            float *grad_tex, hipStream_t st) {
-    const int64_t npix = (int64_t)G.S * G.W * G.H;
-    if (npix == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_backward, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, G, sh,
-                       primid, bary, grad, grad_vcolor, grad_tex);
+    const int64_t ntiles = (int64_t)G.S * ((G.W + kBwdTile - 1) / kBwdTile) *
+                           ((G.H + kBwdTile - 1) / kBwdTile);
+    if (ntiles == 0) return hipSuccess;
+    if (ntiles >= (int64_t)INT32_MAX || G.V >= (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    if (sh.shading == PK_SHADE_TEXTURED) {
+        if ((int64_t)sh.tex_w * sh.tex_h >= (int64_t)INT32_MAX / 3) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_backward<true>, dim3((unsigned)ntiles), dim3(kBwdThreads), 0, st, G,
+                           sh, primid, bary, grad, grad_vcolor, grad_tex);
+    } else {
+        hipLaunchKernelGGL(k_backward<false>, dim3((unsigned)ntiles), dim3(kBwdThreads), 0, st, G,
+                           sh, primid, bary, grad, grad_vcolor, grad_tex);
+    }
     return hipGetLastError();
 }
 

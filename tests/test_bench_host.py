@@ -21,24 +21,53 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def _scene(W, H, S=1, idx=True, shading="gouraud"):
+def _scene(W, H, V, T, S=1, idx=True, shading="gouraud", instanced=False, texture=None):
+    import numpy as np
     return SimpleNamespace(width=W, height=H, num_scenes=S, idx=object() if idx else None,
-                           shading=shading)
+                           shading=shading, pos=np.zeros((3, V), np.float32), num_tris=T,
+                           instanced=instanced, texture=texture)
 
 
 def test_algorithmic_bytes_formulas():
-    sc = _scene(100, 70)
-    # 40 B per pair, two 4-byte offsets per bin (7 x 5 bins of 16 px), 8 B per pixel
-    assert bench.bin_kernel_algorithmic_bytes(sc, 1000, 16) == 40 * 1000 + 8 * 35 + 8 * 7000
-    assert bench.bin_kernel_algorithmic_bytes(sc, 0, 64) == 8 * 4 + 8 * 7000   # 2 x 2 bins
-    # unbinned: 36 B per input triangle, 16 B of key per pixel
-    assert bench.direct_kernel_algorithmic_bytes(_scene(100, 70, S=3), 500) == 36 * 500 + 16 * 21000
-    # resolve: per pixel 4 B primitive ID + 16 B colour (+8 bary); per covered
-    # pixel 12 B indices (indexed) + 36 B colours (+36 B normals, deferred)
-    assert bench.shade_pass_algorithmic_bytes(sc, 300, False) == 20 * 7000 + 48 * 300
-    assert bench.shade_pass_algorithmic_bytes(sc, 300, True) == 28 * 7000 + 48 * 300
-    sd = _scene(100, 70, idx=False, shading="deferred")
-    assert bench.shade_pass_algorithmic_bytes(sd, 300, False) == 28 * 7000 + 72 * 300
+    # indexed Gouraud mesh, 16-px bins (7 x 5 bins on 100 x 70), no bary
+    sc = _scene(100, 70, V=50, T=80)
+    a = bench.algorithmic_bytes(sc, npairs=1000, covered=300, want_bary=False, B=16)
+    assert a["setup"] == 12 * 50 + 12 * 80                # positions + indices
+    assert a["assign_bin"] == 4 * 1000 + 4 * 36           # pairs written, CSR offsets
+    assert a["raster"] == 4 * 1000 + 4 * 36 + 8 * 7000    # pairs read, depth + primid
+    assert a["shade"] == 12 * 50 + 16 * 7000              # colour plane (less than
+                                                          # 36 B x 300 gathers), RGBA
+    assert a["frame"] == sum(a[k] for k in ("setup", "assign_bin", "raster", "shade"))
+    a2 = bench.algorithmic_bytes(sc, 1000, 300, True, 16)
+    assert a2["shade"] == a["shade"] + 8 * 7000           # saved barycentrics
+    # independent deferred micropolygons, whole-screen bins: the visible
+    # triangles' colours and normals (36 B each per covered pixel) are less
+    # than the planes; G-buffer written and read back, colour written
+    sd = _scene(100, 70, V=3000, T=1000, idx=False, shading="deferred")
+    d = bench.algorithmic_bytes(sd, 0, 300, False, 0)
+    assert d["setup"] == 12 * 3000
+    assert d["assign_bin"] == 4 and d["raster"] == 4 + 8 * 7000
+    assert d["shade"] == 2 * 36 * 300 + 24 * 7000 * 2 + 16 * 7000
+    # textured instanced views read the mesh once per view
+    import numpy as np
+    tv = _scene(32, 32, V=100, T=150, S=4, shading="textured", instanced=True,
+                texture=np.zeros((8, 8, 3), np.float32))
+    t = bench.algorithmic_bytes(tv, 500, 2000, True, 8)
+    assert t["setup"] == 4 * (12 * 100 + 12 * 150)
+    assert t["shade"] == (4 * 12 * 100 + 4 * 8 * 100 + 4 * 8 * 8 * 3 * 4
+                          + (16 + 8) * 4 * 1024)
+
+
+def test_grid1080_frame_bytes_match_the_workload_sizes():
+    """The 1920x1080 grid (525,825 vertices, 1,048,576 triangles, 975,046
+    pairs with 16-px bins, one fragment per pixel): pos 6.31 + RGB 6.31 +
+    indices 12.58 + pairs 7.80 + outputs 49.77 MB."""
+    sc = _scene(1920, 1080, V=525825, T=1048576)
+    a = bench.algorithmic_bytes(sc, 975046, 2073600, False, 16)
+    expect = 12 * 525825 * 2 + 12 * 1048576 + 8 * 975046 + 8 * 8161 + 24 * 2073600
+    assert a["frame"] == expect
+    assert abs(a["frame"] / 1e6 - 82.8) < 0.2
+    assert a["raster"] == 4 * 975046 + 4 * 8161 + 8 * 2073600      # about 20.55 MB
 
 
 @pytest.fixture
