@@ -101,11 +101,28 @@ typedef enum {
     PK_SCHED_LOAD_BALANCE = 0, /* one workgroup per bin, hardware dispatcher balances */
     PK_SCHED_DIRECT_MAP = 1,   /* G persistent workgroups, bins pre-assigned to them */
     PK_SCHED_DYNAMIC = 2,      /* G persistent workgroups pop bins from device counters */
-    PK_SCHED_SPLIT = 3         /* heavy bins split (the All directive with a tile split
+    PK_SCHED_SPLIT = 3,        /* heavy bins split (the All directive with a tile split
                                   size, Sec. 4.3): a bin with more than split_size pairs
                                   becomes several work items on different workgroups,
                                   whose depth tiles merge by device-scope 64-bit atomic
                                   min; G persistent workgroups take the work items */
+    PK_SCHED_FRAGMENT_BINS = 4 /* bin fragments, not triangles: the Rasterizer and
+                                  Fragment Shader run per triangle before any bin
+                                  (one stage with whole-screen bins, fused as in
+                                  Sec. 5.2.1), each shaded fragment goes to the bin
+                                  of its pixel, and Depth Test + Composite run per
+                                  bin in LDS.  For one scene (num_scenes 1), opaque,
+                                  bins of 16, 32 or 64 px and at most 8192 bins per
+                                  frame (else PK_ERR_UNSUPPORTED).  pk_setup counts
+                                  each bin's fragments, pk_assign_bin takes their
+                                  prefix sum (*pairs_needed receives the number of
+                                  fragments, which pair_capacity bounds), and
+                                  pk_raster_shade shades and scatters the fragments
+                                  and then tests and composites every bin, writing
+                                  every target; under PK_FLAG_DEFER_SHADE it leaves
+                                  only the lighting of DEFERRED to pk_shade.
+                                  threads_per_bin, persistent_groups and
+                                  PK_FLAG_FUSE_RESOLVE are ignored */
 } pk_schedule;
 
 typedef enum {

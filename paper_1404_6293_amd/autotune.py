@@ -26,7 +26,7 @@ CACHE_ENV = "PK_AUTOTUNE_CACHE"
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pk_autotune.json")
 
 BIN_SIZES = (0, 8, 16, 32, 64)   # 0: whole-screen bins (unbinned, Sec. 4.4)
-SCHEDULES = ("direct_map", "load_balance", "dynamic", "split")
+SCHEDULES = ("direct_map", "load_balance", "dynamic", "split", "fragment_bins")
 THREADS = (64, 128, 256)
 
 
@@ -39,6 +39,12 @@ def candidates(bins: Iterable[int] = BIN_SIZES, schedules: Iterable[str] = SCHED
     for b, s, t, f in itertools.product([b for b in bins if b], schedules, threads, fused):
         if s == "split" and f:
             continue                      # pieces of a bin merge before the resolve
+        if s == "fragment_bins":
+            # fragments binned after shading: 16-64 px bins, one candidate
+            # each (threads per bin and fusion do not apply)
+            if b >= 16 and t == min(threads) and not f:
+                yield pk.RenderConfig(bin_size=b, schedule=s)
+            continue
         yield pk.RenderConfig(bin_size=b, schedule=s, threads_per_bin=t, fuse_resolve=f)
 
 

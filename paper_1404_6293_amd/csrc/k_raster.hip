@@ -181,88 +181,19 @@ __device__ inline void resolve_finish(const RasterArgs &a, int32_t s, int px, in
     const float bs0 = (float)((double)E0 * sinv);
     const float bs1 = (float)((double)E1 * sinv);
     const float bs2 = (float)((double)E2 * sinv);
-    const float qq0 = bs0 * iw0, qq1 = bs1 * iw1, qq2 = bs2 * iw2;
-    const float Q = (qq0 + qq1) + qq2;
-    const float b1 = qq1 / Q, b2 = qq2 / Q;
-    const float b0 = (1.0f - b1) - b2;
-    float rgb[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        float acc = b0 * r.c[0][ch];
-        acc = acc + b1 * r.c[1][ch];
-        acc = acc + b2 * r.c[2][ch];
-        rgb[ch] = acc;
-    }
-    if (SHADE == PK_SHADE_TEXTURED) {
-        float u = b0 * r.ex[0][0];
-        u = u + b1 * r.ex[1][0];
-        u = u + b2 * r.ex[2][0];
-        float vv = b0 * r.ex[0][1];
-        vv = vv + b1 * r.ex[1][1];
-        vv = vv + b2 * r.ex[2][1];
-        const float su = u * (float)sh.tex_w - 0.5f, sv = vv * (float)sh.tex_h - 0.5f;
-        const float fi = floorf(su), fj = floorf(sv);
-        const float fs = su - fi, ft = sv - fj;
-        const float ci = fminf(fmaxf(fi, -1.0f), (float)sh.tex_w);
-        const float cj = fminf(fmaxf(fj, -1.0f), (float)sh.tex_h);
-        const int i0 = min(max((int)ci, 0), sh.tex_w - 1), i1 = min(max((int)ci + 1, 0), sh.tex_w - 1);
-        const int j0 = min(max((int)cj, 0), sh.tex_h - 1), j1 = min(max((int)cj + 1, 0), sh.tex_h - 1);
-        const float w00 = (1.0f - fs) * (1.0f - ft), w10 = fs * (1.0f - ft);
-        const float w01 = (1.0f - fs) * ft, w11 = fs * ft;
-        const float *t00 = sh.texture + 3 * ((int64_t)j0 * sh.tex_w + i0);
-        const float *t10 = sh.texture + 3 * ((int64_t)j0 * sh.tex_w + i1);
-        const float *t01 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i0);
-        const float *t11 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i1);
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float tc = w00 * t00[ch];
-            tc = tc + w10 * t10[ch];
-            tc = tc + w01 * t01[ch];
-            tc = tc + w11 * t11[ch];
-            rgb[ch] = rgb[ch] * tc;
-        }
-    }
+    FragOut o;
+    shade_fragment<SHADE>(sh, bs0, bs1, bs2, iw0, iw1, iw2, r.c, r.ex, o);
+    const float b1 = o.b1, b2 = o.b2;
     if (SHADE == PK_SHADE_DEFERRED) {
-        float n[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = b0 * r.ex[0][ch];
-            acc = acc + b1 * r.ex[1][ch];
-            acc = acc + b2 * r.ex[2][ch];
-            n[ch] = acc;
-        }
-        float nn = n[0] * n[0];
-        nn = nn + n[1] * n[1];
-        nn = nn + n[2] * n[2];
-        float nh0 = 0.0f, nh1 = 0.0f, nh2 = 0.0f;
-        if (nn != 0.0f) {
-            const float len = sqrtf(nn);
-            nh0 = n[0] / len; nh1 = n[1] / len; nh2 = n[2] / len;
-        }
-        *reinterpret_cast<Float3 *>(sh.gbuf_n + 3 * p) = Float3{nh0, nh1, nh2};
-        *reinterpret_cast<Float3 *>(sh.gbuf_a + 3 * p) = Float3{rgb[0], rgb[1], rgb[2]};
+        *reinterpret_cast<Float3 *>(sh.gbuf_n + 3 * p) = Float3{o.n[0], o.n[1], o.n[2]};
+        *reinterpret_cast<Float3 *>(sh.gbuf_a + 3 * p) = Float3{o.rgb[0], o.rgb[1], o.rgb[2]};
     } else if (sh.out_color) {
-        reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(rgb[0], rgb[1], rgb[2], 1.0f);
+        reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(o.rgb[0], o.rgb[1], o.rgb[2], 1.0f);
     }
     if (write_dp && sh.out_depth) sh.out_depth[p] = r.depth;
     if (write_dp && sh.out_primid) sh.out_primid[p] = (int32_t)r.t;
     if (sh.out_bary) reinterpret_cast<float2 *>(sh.out_bary)[p] = make_float2(b1, b2);
 }
-
-// One staged triangle of a bin, in registers: edge functions normalised so
-// that a sample is covered iff all three are > 0 (the top-left ownership bit
-// is folded into the constant), clipped candidate rectangle, depth inputs.
-// Edge values are integers below 2^48 held in float64: every product, sum and
-// step below stays an integer below 2^53, so the float64 arithmetic is exact
-// and equals the integer definition bit for bit (and feeds the float64
-// barycentrics without conversions).
-struct EdgeTri {
-    int32_t A[3], Bc[3];   // e_k(P) = A_k Px + B_k Py + C_k   (P in 1/256 px)
-    double C[3];
-    float z[3];
-    double inv;            // 1 / |A2|
-    int32_t x0, y0, wdt, cnt, own, prim;
-};
 
 struct RawTri {
     uint4 q0, q1;   // the 32-byte setup record
@@ -308,53 +239,8 @@ __device__ inline void decode_tri(const RawTri &r, int32_t item, int64_t item_ba
                                   EdgeTri &t) {
     int32_t X[3], Y[3];
     unpack_xy(r.q0.x, r.q0.y, r.q0.z, r.q0.w, r.q1.x, X, Y);
-    const int64_t A2 = area2(X, Y);
-    const double sinv = signed_inv_area(A2);
-    const int sgn = A2 > 0 ? 1 : -1;
-    t.own = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int ka = (k + 1) % 3, kb = (k + 2) % 3;   // edge v_ka -> v_kb, opposite v_k
-        const int32_t dx = X[kb] - X[ka], dy = Y[kb] - Y[ka];
-        const int32_t Ak = -sgn * dy, Bk = sgn * dx;
-        const int own = (Ak > 0) || (Ak == 0 && Bk < 0);
-        t.own |= own << k;
-        t.A[k] = Ak;
-        t.Bc[k] = Bk;
-        t.C[k] = (double)(-((int64_t)Ak * X[ka] + (int64_t)Bk * Y[ka]) + own);
-    }
-    t.z[0] = __uint_as_float(r.q1.y);
-    t.z[1] = __uint_as_float(r.q1.z);
-    t.z[2] = __uint_as_float(r.q1.w);
-    t.inv = sinv > 0.0 ? sinv : -sinv;
-    int32_t bx0, bx1, by0, by1;
-    sample_bbox(X, Y, W, H, bx0, bx1, by0, by1);
-    t.x0 = max(bx0, px0);
-    t.y0 = max(by0, py0);
-    const int32_t x1 = min(bx1, px0 + pw - 1);
-    const int32_t y1 = min(by1, py0 + ph - 1);
-    t.wdt = x1 - t.x0 + 1;
-    const int32_t hgt = y1 - t.y0 + 1;
-    t.cnt = (t.wdt > 0 && hgt > 0) ? t.wdt * hgt : 0;
-    t.prim = (int32_t)(item - item_base);
-}
-
-// Depth of a covered sample from its biased edge values: the float64
-// barycentric form, then the (depth, primitive) key.  Returns false when the
-// fragment is outside [0, 1).
-__device__ inline bool depth_key(double e0, double e1, double e2, int own, double inv,
-                                 float z0, float z1, float z2, uint32_t prim,
-                                 unsigned long long &key) {
-    const double be0 = (e0 - (double)(own & 1)) * inv;
-    const double be1 = (e1 - (double)((own >> 1) & 1)) * inv;
-    const double be2 = (e2 - (double)((own >> 2) & 1)) * inv;
-    double zd = be0 * (double)z0;
-    zd = zd + be1 * (double)z1;
-    zd = zd + be2 * (double)z2;
-    float z = (float)zd;
-    z = z + 0.0f;
-    key = ((unsigned long long)__float_as_uint(z) << 32) | prim;
-    return 0.0f <= z && z < 1.0f;
+    edge_setup(X, Y, __uint_as_float(r.q1.y), __uint_as_float(r.q1.z), __uint_as_float(r.q1.w),
+               (int32_t)(item - item_base), px0, py0, pw, ph, W, H, t);
 }
 
 // SHADE value of a bin kernel that ends by storing its tile of winning keys
@@ -918,6 +804,13 @@ __global__ __launch_bounds__(kFragSlots) void k_raster_epilogue(uint32_t *misc,
     if (rewind && threadIdx.x < kXcd) misc[8 + threadIdx.x] = 0u;
 }
 
+hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewind,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_raster_epilogue, dim3(1), dim3(kFragSlots), 0, st, w.misc, frag_count,
+                       rewind);
+    return hipGetLastError();
+}
+
 // Whole-screen bins (bin size 0, the unbinned pipeline of Sec. 4.4 and the
 // paper's full-screen-bin baseline of Sec. 7): no bin lists, one thread per
 // triangle over its sample bounding box on the screen, and the depth test as
@@ -1345,16 +1238,7 @@ __global__ __launch_bounds__(256) void k_deferred(Shade sh, int64_t npix) {
         return;
     }
     const Float3 nn = *reinterpret_cast<const Float3 *>(sh.gbuf_n + 3 * p);
-    const float n0 = nn.x, n1 = nn.y, n2 = nn.z;
-    float lit = 0.0f;
-    for (int l = 0; l < sh.num_lights; ++l) {
-        const float *L = sh.lights + 3 * l;
-        float d = n0 * L[0];
-        d = d + n1 * L[1];
-        d = d + n2 * L[2];
-        d = d < 0.0f ? 0.0f : d;
-        lit = (l == 0) ? d : lit + d;
-    }
+    const float lit = light_sum(sh, nn.x, nn.y, nn.z);
     const Float3 al = *reinterpret_cast<const Float3 *>(sh.gbuf_a + 3 * p);
     reinterpret_cast<float4 *>(sh.out_color)[p] = make_float4(al.x * lit, al.y * lit, al.z * lit, 1.0f);
 }

@@ -311,6 +311,7 @@ hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st) {
         e = launch_fill_u32(w.bin_count, words, 0u, st);
     }
     if (e != hipSuccess || G.items == 0) return e;
+    if (w.fb_groups) return launch_fb_count(G, w, st);
     const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
     const size_t hist = G.B ? kHist * sizeof(uint32_t) : 0;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), hist, st, G, w);

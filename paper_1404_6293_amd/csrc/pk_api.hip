@@ -1,5 +1,6 @@
 // pk_api.hip -- the C ABI of libpk (include/pk.h): host-side validation,
 // workspace layout and kernel launches.  No allocation, no synchronization.
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -35,6 +36,8 @@ struct Frame {
     int64_t nbins_scene = 0;
     int64_t nbins_total = 0;
     int nbx = 0, nby = 0;
+    bool fragbins = false; // PK_SCHED_FRAGMENT_BINS
+    int32_t fb_groups = 0, fb_rounds = 0, fb_planes = 0;
 };
 
 pk_status check_params(const pk_params *p, Frame &f) {
@@ -42,7 +45,7 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->width < 1 || p->width > 8192 || p->height < 1 || p->height > 8192)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->bin_size != 0 && !is_pow2_bin(p->bin_size)) return PK_ERR_INVALID_ARGUMENT;
-    if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_SPLIT)
+    if (p->schedule < PK_SCHED_LOAD_BALANCE || p->schedule > PK_SCHED_FRAGMENT_BINS)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->split_size < 0) return PK_ERR_INVALID_ARGUMENT;
     if (p->layers < 0 || p->layers > 8) return PK_ERR_INVALID_ARGUMENT;
@@ -78,6 +81,14 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
     f.npix = (int64_t)p->num_scenes * p->width * p->height;
     if (f.npix > (int64_t)1 << 40) return PK_ERR_INVALID_ARGUMENT;
+    if (p->schedule == PK_SCHED_FRAGMENT_BINS) {
+        // one scene, opaque, the bins' counters in one workgroup's LDS
+        if (p->bin_size < 16 || p->num_scenes != 1 || p->layers != 0 ||
+            f.nbins_total > kFbMaxBins)
+            return PK_ERR_UNSUPPORTED;
+        f.fragbins = true;
+        f.fb_planes = p->shading == PK_SHADE_DEFERRED ? 3 : 2;
+    }
     // the per-pixel pass runs one workgroup per 64 x 4 tile
     if ((int64_t)p->num_scenes * ((p->width + 63) / 64) * ((p->height + 3) / 4) >=
         (int64_t)INT32_MAX)
@@ -95,28 +106,44 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
     if (f.items >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
     f.indexed = m->indices != nullptr;
     f.vrecs = m->indices ? (int64_t)m->num_vertices * (p->instanced ? p->num_scenes : 1) : 0;
+    if (f.fragbins) {
+        // workgroups of fb_rounds rounds of 1024 triangles: about 1024 of
+        // them (at least 256 when the scene allows), fewer when the bins are
+        // many, so that the count matrix stays near 2^22 words
+        const int64_t target = std::max<int64_t>(256, std::min<int64_t>(1024, ((int64_t)1 << 22) / f.nbins_total));
+        const int64_t rounds = (f.items + kFbRoundTris * target - 1) / (kFbRoundTris * target);
+        f.fb_rounds = (int32_t)std::max<int64_t>(1, rounds);
+        const int64_t per = (int64_t)kFbRoundTris * f.fb_rounds;
+        f.fb_groups = (int32_t)std::max<int64_t>(1, (f.items + per - 1) / per);
+    }
     return PK_OK;
 }
 
 struct Layout {
-    size_t vtx, rec, iw, bbox, bin_count, bin_off, vbin_off, cursor, misc, keys, pairs, total;
+    size_t vtx, rec, iw, bbox, fb_mat, bin_count, bin_off, vbin_off, cursor, misc, keys, pairs,
+        total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
     Layout L;
     size_t o = 0;
+    // fragment bins keep no per-triangle records, boxes or keys; their "pairs"
+    // are fragments of fb_planes 16-byte planes
+    const size_t tri = f.fragbins ? 0 : (size_t)f.items;
     L.vtx = o;       o = align_up(o + sizeof(VtxRec) * (size_t)f.vrecs);
-    L.rec = o;       o = align_up(o + sizeof(TriRec) * (size_t)f.items);
-    L.iw = o;        o = align_up(o + sizeof(float4) * (size_t)(f.indexed ? 0 : f.items));
-    L.bbox = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.items);
+    L.rec = o;       o = align_up(o + sizeof(TriRec) * tri);
+    L.iw = o;        o = align_up(o + sizeof(float4) * (f.indexed ? 0 : tri));
+    L.bbox = o;      o = align_up(o + sizeof(uint64_t) * tri);
+    L.fb_mat = o;    o = align_up(o + sizeof(uint32_t) * (size_t)f.fb_groups * (size_t)(f.fragbins ? f.nbins_total : 0));
     // counters, cursors and misc words are adjacent so one clear covers them
     L.bin_count = o; o = align_up(o + sizeof(uint32_t) * (size_t)f.nbins_total);
     L.cursor = o;    o = align_up(o + sizeof(int32_t) * (size_t)f.nbins_total);
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.vbin_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)(f.split ? f.nbins_total + 1 : 0));
-    L.keys = o;      o = align_up(o + sizeof(uint64_t) * (size_t)f.npix * (size_t)(f.layers > 0 ? f.layers : 1));
-    L.pairs = o;     o = align_up(o + sizeof(int32_t) * (size_t)pair_capacity);
+    L.keys = o;      o = align_up(o + sizeof(uint64_t) * (f.fragbins ? 0 : (size_t)f.npix * (size_t)(f.layers > 0 ? f.layers : 1)));
+    L.pairs = o;     o = align_up(o + (f.fragbins ? 16 * (size_t)f.fb_planes * (size_t)((pair_capacity + 63) / 64 * 64)
+                                                 : sizeof(int32_t) * (size_t)pair_capacity));
     L.total = o;
     return L;
 }
@@ -140,6 +167,9 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.misc = reinterpret_cast<uint32_t *>(b + L.misc);
     w.pairs = reinterpret_cast<int32_t *>(b + L.pairs);
     w.pair_capacity = pair_capacity;
+    w.fb_mat = reinterpret_cast<uint32_t *>(b + L.fb_mat);
+    w.fb_groups = f.fragbins ? f.fb_groups : 0;
+    w.fb_rounds = f.fb_rounds;
     return w;
 }
 
@@ -256,6 +286,7 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
         return PK_ERR_INVALID_ARGUMENT;
     const Geom G = geom(p, m, f);
     const Ws w = carve(ws, f, pair_capacity);
+    if (f.fragbins) return hip_status(launch_fb_assign(G, w, pairs_needed, (hipStream_t)stream));
     return hip_status(launch_assign(G, w, pairs_needed, (hipStream_t)stream));
 }
 
@@ -286,6 +317,10 @@ pk_status pk_raster_shade(const pk_params *p, const pk_mesh *m, const pk_attribs
     // the pair list is the last slice, so its address does not depend on the
     // capacity; the lists are read through bin_off only
     const Ws w = carve(ws, f, 0);
+    if (f.fragbins) {
+        const bool light = p->shading == PK_SHADE_DEFERRED && mode != kRasterKeysOnly;
+        return hip_status(launch_fb_raster(G, w, sh, light, (hipStream_t)stream));
+    }
     // transparency layers keep per-pixel LDS state for a whole bin (slots or
     // peeling passes): one workgroup per bin
     const int sched = p->layers > 0 ? PK_SCHED_LOAD_BALANCE : p->schedule;
@@ -307,6 +342,12 @@ pk_status pk_shade(const pk_params *p, const pk_mesh *m, const pk_attribs *a, vo
     sh.frag_count = nullptr;
     const Geom G = geom(p, m, f);
     const Ws w = carve(ws, f, 0);
+    if (f.fragbins) {
+        // the fragments were shaded before the depth test: only the
+        // lighting of the deferred pass is left
+        return hip_status(p->shading == PK_SHADE_DEFERRED ? launch_deferred(G, sh, (hipStream_t)stream)
+                                                          : hipSuccess);
+    }
     hipError_t e = launch_resolve_pass(G, w, sh, (hipStream_t)stream);
     if (e == hipSuccess && p->shading == PK_SHADE_DEFERRED)
         e = launch_deferred(G, sh, (hipStream_t)stream);
@@ -363,7 +404,8 @@ pk_status pk_bin_lists(const pk_params *p, const pk_mesh *m, void *ws, pk_bin_vi
     if (st != PK_OK) return st;
     if ((st = check_mesh(p, m, f)) != PK_OK) return st;
     if (!ws || !out) return PK_ERR_INVALID_ARGUMENT;
-    if (p->bin_size == 0) return PK_ERR_UNSUPPORTED;   // whole-screen bins keep no lists
+    // whole-screen bins keep no lists; fragment bins hold fragments
+    if (p->bin_size == 0 || p->schedule == PK_SCHED_FRAGMENT_BINS) return PK_ERR_UNSUPPORTED;
     const Ws w = carve(ws, f, 0);
     out->bin_offsets = w.bin_off;
     out->bin_tris = w.pairs;

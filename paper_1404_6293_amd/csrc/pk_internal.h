@@ -80,6 +80,76 @@ __device__ inline void sample_bbox(const int32_t X[3], const int32_t Y[3], int32
     y1 = min((mxy - 128) >> 8, H - 1);
 }
 
+// One staged triangle of a bin, in registers: edge functions normalised so
+// that a sample is covered iff all three are > 0 (the top-left ownership bit
+// is folded into the constant), clipped candidate rectangle, depth inputs.
+// Edge values are integers below 2^48 held in float64: every product, sum and
+// step below stays an integer below 2^53, so the float64 arithmetic is exact
+// and equals the integer definition bit for bit (and feeds the float64
+// barycentrics without conversions).
+struct EdgeTri {
+    int32_t A[3], Bc[3];   // e_k(P) = A_k Px + B_k Py + C_k   (P in 1/256 px)
+    double C[3];
+    float z[3];
+    double inv;            // 1 / |A2|
+    int32_t x0, y0, wdt, cnt, own, prim;
+};
+
+// Edge functions, ownership bits, depth inputs and the candidate rectangle
+// (the sample bbox clipped to the pw x ph pixel window at (px0, py0)) of a
+// snapped triangle; prim is the primitive number carried into the keys.
+__device__ inline void edge_setup(const int32_t X[3], const int32_t Y[3], float z0, float z1,
+                                  float z2, int32_t prim, int32_t px0, int32_t py0, int32_t pw,
+                                  int32_t ph, int32_t W, int32_t H, EdgeTri &t) {
+    const int64_t A2 = area2(X, Y);
+    const double sinv = signed_inv_area(A2);
+    const int sgn = A2 > 0 ? 1 : -1;
+    t.own = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int ka = (k + 1) % 3, kb = (k + 2) % 3;   // edge v_ka -> v_kb, opposite v_k
+        const int32_t dx = X[kb] - X[ka], dy = Y[kb] - Y[ka];
+        const int32_t Ak = -sgn * dy, Bk = sgn * dx;
+        const int own = (Ak > 0) || (Ak == 0 && Bk < 0);
+        t.own |= own << k;
+        t.A[k] = Ak;
+        t.Bc[k] = Bk;
+        t.C[k] = (double)(-((int64_t)Ak * X[ka] + (int64_t)Bk * Y[ka]) + own);
+    }
+    t.z[0] = z0;
+    t.z[1] = z1;
+    t.z[2] = z2;
+    t.inv = sinv > 0.0 ? sinv : -sinv;
+    int32_t bx0, bx1, by0, by1;
+    sample_bbox(X, Y, W, H, bx0, bx1, by0, by1);
+    t.x0 = max(bx0, px0);
+    t.y0 = max(by0, py0);
+    const int32_t x1 = min(bx1, px0 + pw - 1);
+    const int32_t y1 = min(by1, py0 + ph - 1);
+    t.wdt = x1 - t.x0 + 1;
+    const int32_t hgt = y1 - t.y0 + 1;
+    t.cnt = (t.wdt > 0 && hgt > 0) ? t.wdt * hgt : 0;
+    t.prim = prim;
+}
+
+// Depth of a covered sample from its biased edge values: the float64
+// barycentric form, then the (depth, primitive) key.  Returns false when the
+// fragment is outside [0, 1).
+__device__ inline bool depth_key(double e0, double e1, double e2, int own, double inv,
+                                 float z0, float z1, float z2, uint32_t prim,
+                                 unsigned long long &key) {
+    const double be0 = (e0 - (double)(own & 1)) * inv;
+    const double be1 = (e1 - (double)((own >> 1) & 1)) * inv;
+    const double be2 = (e2 - (double)((own >> 2) & 1)) * inv;
+    double zd = be0 * (double)z0;
+    zd = zd + be1 * (double)z1;
+    zd = zd + be2 * (double)z2;
+    float z = (float)zd;
+    z = z + 0.0f;
+    key = ((unsigned long long)__float_as_uint(z) << 32) | prim;
+    return 0.0f <= z && z < 1.0f;
+}
+
 // Everything the geometry kernels need about the mesh and the bin grid.
 struct Geom {
     const float *pos;
@@ -127,6 +197,12 @@ struct Ws {
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
     int32_t split;             // PK_SCHED_SPLIT: pairs per work item; 0 otherwise
+    // PK_SCHED_FRAGMENT_BINS: `pairs` holds the fragments instead, as
+    // kFbPlanes planes of pair_capacity 16-byte entries; fb_mat [fb_groups]
+    // [nbins] the per-workgroup fragment counts of each bin
+    uint32_t *fb_mat;
+    int32_t fb_groups;         // 0 = not this schedule
+    int32_t fb_rounds;         // rounds of 1024 triangles per workgroup
 };
 
 struct Shade {
@@ -139,6 +215,99 @@ struct Shade {
     const float *alpha;        // [V] per-vertex opacity (layers > 0)
     int32_t layers;            // 0 = opaque, else layers composited per pixel
 };
+
+// Fragment shader of one covered sample from its float32 screen-space
+// barycentrics bs_k and the three vertices' 1/w: perspective-correct b1, b2
+// (b0 = 1 - b1 - b2), then the interpolated colour (modulated by the bilinear
+// texture for TEXTURED), or for DEFERRED the interpolated albedo and the unit
+// interpolated normal.  c[k][ch] are vertex colours, ex[k][ch] the uv
+// (TEXTURED) or normal (DEFERRED) of vertex k.
+struct FragOut {
+    float b1, b2;
+    float rgb[3];
+    float n[3];
+};
+
+template <int SHADE>
+__device__ inline void shade_fragment(const Shade &sh, float bs0, float bs1, float bs2, float iw0,
+                                      float iw1, float iw2, const float c[3][3],
+                                      const float ex[3][3], FragOut &o) {
+    const float qq0 = bs0 * iw0, qq1 = bs1 * iw1, qq2 = bs2 * iw2;
+    const float Q = (qq0 + qq1) + qq2;
+    const float b1 = qq1 / Q, b2 = qq2 / Q;
+    const float b0 = (1.0f - b1) - b2;
+    o.b1 = b1;
+    o.b2 = b2;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = b0 * c[0][ch];
+        acc = acc + b1 * c[1][ch];
+        acc = acc + b2 * c[2][ch];
+        o.rgb[ch] = acc;
+    }
+    if (SHADE == PK_SHADE_TEXTURED) {
+        float u = b0 * ex[0][0];
+        u = u + b1 * ex[1][0];
+        u = u + b2 * ex[2][0];
+        float vv = b0 * ex[0][1];
+        vv = vv + b1 * ex[1][1];
+        vv = vv + b2 * ex[2][1];
+        const float su = u * (float)sh.tex_w - 0.5f, sv = vv * (float)sh.tex_h - 0.5f;
+        const float fi = floorf(su), fj = floorf(sv);
+        const float fs = su - fi, ft = sv - fj;
+        const float ci = fminf(fmaxf(fi, -1.0f), (float)sh.tex_w);
+        const float cj = fminf(fmaxf(fj, -1.0f), (float)sh.tex_h);
+        const int i0 = min(max((int)ci, 0), sh.tex_w - 1), i1 = min(max((int)ci + 1, 0), sh.tex_w - 1);
+        const int j0 = min(max((int)cj, 0), sh.tex_h - 1), j1 = min(max((int)cj + 1, 0), sh.tex_h - 1);
+        const float w00 = (1.0f - fs) * (1.0f - ft), w10 = fs * (1.0f - ft);
+        const float w01 = (1.0f - fs) * ft, w11 = fs * ft;
+        const float *t00 = sh.texture + 3 * ((int64_t)j0 * sh.tex_w + i0);
+        const float *t10 = sh.texture + 3 * ((int64_t)j0 * sh.tex_w + i1);
+        const float *t01 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i0);
+        const float *t11 = sh.texture + 3 * ((int64_t)j1 * sh.tex_w + i1);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float tc = w00 * t00[ch];
+            tc = tc + w10 * t10[ch];
+            tc = tc + w01 * t01[ch];
+            tc = tc + w11 * t11[ch];
+            o.rgb[ch] = o.rgb[ch] * tc;
+        }
+    }
+    if (SHADE == PK_SHADE_DEFERRED) {
+        float n[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = b0 * ex[0][ch];
+            acc = acc + b1 * ex[1][ch];
+            acc = acc + b2 * ex[2][ch];
+            n[ch] = acc;
+        }
+        float nn = n[0] * n[0];
+        nn = nn + n[1] * n[1];
+        nn = nn + n[2] * n[2];
+        o.n[0] = o.n[1] = o.n[2] = 0.0f;
+        if (nn != 0.0f) {
+            const float len = sqrtf(nn);
+            o.n[0] = n[0] / len; o.n[1] = n[1] / len; o.n[2] = n[2] / len;
+        }
+    }
+}
+
+// Lighting of the deferred pass: sum over the lights of max(0, n . l), in
+// the lights' order.
+__device__ inline float light_sum(const Shade &sh, float n0, float n1, float n2) {
+    float lit = 0.0f;
+    for (int l = 0; l < sh.num_lights; ++l) {
+        const float *L = sh.lights + 3 * l;
+        float d = n0 * L[0];
+        d = d + n1 * L[1];
+        d = d + n2 * L[2];
+        d = d < 0.0f ? 0.0f : d;
+        lit = (l == 0) ? d : lit + d;
+    }
+    return lit;
+}
 
 // Which scene an item belongs to and which triangle of the mesh it is.
 struct ItemRef {
@@ -194,7 +363,9 @@ __device__ inline bool vertex_stage_xyz(const Geom &G, float x, float y, float z
     }
     bool ok = __builtin_isfinite(c0) && __builtin_isfinite(c1) && __builtin_isfinite(c2) &&
               __builtin_isfinite(c3) && c3 > 0.0f;
-    const float w1 = 1.0f / c3;     // correctly rounded; NDC = clip * (1/w)
+    // correctly rounded; NDC = clip * (1/w).  Without a matrix w is 1 and so
+    // is its reciprocal: the division is skipped, the value is the same
+    const float w1 = m ? 1.0f / c3 : 1.0f;
     const float xn = c0 * w1;
     const float yn = c1 * w1;
     const float zn = c2 * w1;
@@ -331,6 +502,18 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
                          int groups, RasterMode mode, hipStream_t st);
 hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipStream_t st);
 hipError_t launch_deferred(const Geom &G, const Shade &sh, hipStream_t st);
+// PK_SCHED_FRAGMENT_BINS (k_fragbin.hip): fragment counts per bin (pk_setup),
+// the prefix sum (pk_assign_bin), fragment shading and scatter, then the
+// per-bin depth test and composite (pk_raster_shade).
+hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewind,
+                           hipStream_t st);
+hipError_t launch_fb_count(const Geom &G, const Ws &w, hipStream_t st);
+hipError_t launch_fb_assign(const Geom &G, const Ws &w, int64_t *pairs_needed, hipStream_t st);
+hipError_t launch_fb_raster(const Geom &G, const Ws &w, const Shade &sh, bool light,
+                            hipStream_t st);
+constexpr int kFbThreads = 256;        // threads of a fragment workgroup
+constexpr int kFbRoundTris = 1024;     // triangles per round (4 per thread)
+constexpr int kFbMaxBins = 8192;       // LDS counters of a fragment workgroup
 hipError_t launch_backward(const Geom &G, const Shade &sh, const int32_t *primid,
                            const float *bary, const float *grad, float *grad_vcolor,
                            float *grad_tex, hipStream_t st);

@@ -59,7 +59,7 @@ def _mesh(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=-1), dict(width=8193), dict(bin_size=12), dict(bin_size=128),
-    dict(bin_size=-8), dict(schedule=4), dict(schedule=-1), dict(threads_per_bin=32),
+    dict(bin_size=-8), dict(schedule=5), dict(schedule=-1), dict(threads_per_bin=32),
     dict(split_size=-1), dict(schedule=3, flags=2), dict(layers=-1), dict(layers=9),
     dict(layers=2, flags=2),
     dict(threads_per_bin=512), dict(shading=3), dict(flags=8), dict(flags=6), dict(num_scenes=0),
@@ -85,7 +85,7 @@ def test_whole_screen_bins(L):
         assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == want
         v = pk.BinView()
         assert L.pk_bin_lists(C.byref(p), C.byref(m), 1 << 20, C.byref(v)) == pk.PK_ERR_UNSUPPORTED
-    for bad in (dict(schedule=4), dict(threads_per_bin=32), dict(width=0)):
+    for bad in (dict(schedule=5), dict(threads_per_bin=32), dict(width=0)):
         p = _params(bin_size=0, **bad)
         assert L.pk_setup(C.byref(p), C.byref(_mesh()), FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
 
@@ -239,3 +239,27 @@ def test_static_workspace_rejects_frames_that_do_not_fit(L):
     assert L.pk_render_static(C.byref(_params()), C.byref(_mesh()), None, C.byref(tg), None,
                               None) == pk.PK_ERR_INVALID_ARGUMENT
     assert "static workspace" in pk.status_string(pk.PK_ERR_CAPACITY)
+
+
+def test_fragment_bins_restrictions_and_workspace(L):
+    """PK_SCHED_FRAGMENT_BINS: one opaque scene, 16-64 px bins, at most 8192
+    bins; its workspace holds no per-triangle records or keys, a count
+    matrix (one row of bin counts per workgroup of 1024-triangle rounds) and
+    the fragments (2 planes of 16 bytes, 3 for deferred shading, in blocks
+    of 64)."""
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    m = _mesh(num_tris=1000, num_vertices=3000)
+    for bad in (dict(bin_size=8), dict(bin_size=0), dict(num_scenes=2, instanced=1),
+                dict(layers=2, bin_size=16), dict(width=8192, height=8192, bin_size=16)):
+        p = _params(schedule=4, **{"bin_size": 16, **bad})
+        assert L.pk_setup(C.byref(p), C.byref(m), FAKE, None) == pk.PK_ERR_UNSUPPORTED, bad
+        assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 100) == 0
+    p = _params(width=100, height=70, bin_size=32, schedule=4)         # 4 x 3 bins
+    nb = 12
+    for shading, planes in ((0, 2), (2, 3)):
+        p.shading = shading
+        want = (al(4 * 1 * nb) + al(4 * nb) + al(4 * nb) + al(4 * 576) + al(4 * (nb + 1))
+                + al(16 * planes * 128))
+        assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 100) == want
+    v = pk.BinView()
+    assert L.pk_bin_lists(C.byref(p), C.byref(m), 1 << 20, C.byref(v)) == pk.PK_ERR_UNSUPPORTED

@@ -146,15 +146,16 @@ def _micro8m():
     return _MICRO["scene"], _MICRO["oracle"]
 
 
-@pytest.mark.parametrize("bin_size", [16, 0])
-def test_micro8m_full_frame_deferred(bin_size):
+@pytest.mark.parametrize("bin_size,schedule", [(16, "direct_map"), (0, "direct_map"),
+                                               (32, "fragment_bins"), (64, "fragment_bins")])
+def test_micro8m_full_frame_deferred(bin_size, schedule):
     """8,388,608 micropolygons at 1920x1080, deferred, full frame against the
     oracle: with 16-px bins, and with whole-screen bins, the benchmark's
     (autotuned) launch configuration for this workload."""
     import torch
-    _note(f"micro8m full frame bin_size={bin_size}")
+    _note(f"micro8m full frame bin_size={bin_size} {schedule}")
     sc, o = _micro8m()
-    r = pk.Renderer(sc, pk.RenderConfig(bin_size=bin_size, schedule="direct_map", threads_per_bin=0,
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=bin_size, schedule=schedule, threads_per_bin=0,
                                         count_frags=True, want_bary=False))
     out = r.render()
     torch.cuda.synchronize()
