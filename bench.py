@@ -432,29 +432,45 @@ def bench_micro(reps: int = 10) -> dict:
 
 
 def bench_lights(reps: int = 5) -> dict:
-    """Shader complexity swept by the light count, the knob of the paper's
-    fusion experiments (Sec. 7.2), on micro8m (deferred shading): one whole
-    frame with 1, 4, 16 and 64 lights for the unbinned baseline (whole-screen
-    bins), 16-px bins with the resolve in its own pass, and 16-px bins with
-    the resolve fused into the bin kernel.  Lighting runs once per pixel in
-    the deferred pass in all three."""
+    """The paper's fusion and binning experiments (Sec. 7.2) with shader
+    complexity as a light count: forward lighting in the fragment shader
+    (colour = vertex colour x the sum of max(0, n . l) over L lights), one
+    whole frame for L = 1, 4, 16, 64 in four pipelines:
+      baseline       whole-screen bins, one kernel per stage (vertex/setup,
+                     raster with a device-scope depth test, per-pixel
+                     resolve that shades the visible fragment);
+      freepipe       Rasterizer and Fragment Shader fused per triangle (every
+                     covered fragment shaded, before the depth test), then
+                     Depth Test + Composite per 32-px bin (fragment bins);
+      binned         16-px bins, LOAD_BALANCE, shading in a per-pixel pass;
+      binned_fused   16-px bins, DIRECT_MAP, shading fused into the bin kernel.
+    Scenes: the 1080p grid (about 1M tiny regular triangles), micro8m (8.4M
+    micropolygons) and a mixed frame of 1M small and 512 large triangles
+    (many small and large), each with random unit normals."""
     import torch
-    from types import SimpleNamespace
     from paper_1404_6293_amd import pk, scenes
-    base = scenes.micro()
-    cfgs = {"B0": dict(bin_size=0), "B16": dict(bin_size=16),
-            "B16/fused": dict(bin_size=16, fuse_resolve=True)}
+    pipes = {"baseline": dict(bin_size=0),
+             "freepipe": dict(bin_size=32, schedule="fragment_bins"),
+             "binned": dict(bin_size=16, schedule="load_balance"),
+             "binned_fused": dict(bin_size=16, schedule="direct_map", fuse_resolve=True)}
     out = {}
-    for L in (1, 4, 16, 64):
-        dev = pk.DeviceScene(SimpleNamespace(**{**vars(base), "lights": scenes.lights(L)}))
-        for name, c in cfgs.items():
-            r = pk.Renderer(dev, pk.RenderConfig(want_bary=False, **c))
-            r.render()
-            torch.cuda.synchronize()
-            out[f"{name}/lights{L}"] = round(_median_ms(torch, r.frame, reps), 4)
-            del r
-        del dev
-    return {"workload": "micro8m, deferred shading with 1-64 lights", "frame_ms": out}
+    for name, make in (("grid1080", scenes.grid), ("micro8m", scenes.micro),
+                       ("mixed", scenes.mixed)):
+        base = make()
+        res = {}
+        for L in (1, 4, 16, 64):
+            dev = pk.DeviceScene(scenes.with_lighting(base, L))
+            for pname, c in pipes.items():
+                r = pk.Renderer(dev, pk.RenderConfig(want_bary=False, **c))
+                r.render()
+                torch.cuda.synchronize()
+                res[f"{pname}/L{L}"] = round(_median_ms(torch, r.frame, reps), 4)
+                del r
+            del dev
+        out[name] = res
+        del base
+    return {"workload": "forward-lit frames (L lights) of grid1080, micro8m and a mixed "
+                        "1M-small + 512-large frame in four pipelines", "frame_ms": out}
 
 
 def bench_ablation(reps: int = 5) -> dict:

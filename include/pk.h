@@ -128,8 +128,13 @@ typedef enum {
 typedef enum {
     PK_SHADE_GOURAUD = 0,  /* colour = perspective-correct vertex colour */
     PK_SHADE_TEXTURED = 1, /* colour = Gouraud colour * bilinear texture(uv) */
-    PK_SHADE_DEFERRED = 2  /* write G-buffer (unit normal, albedo), then
+    PK_SHADE_DEFERRED = 2, /* write G-buffer (unit normal, albedo), then
                               colour = albedo * sum_l max(0, n . l_l) */
+    PK_SHADE_LIT = 3       /* forward lighting in the fragment shader itself:
+                              colour = vertex colour * sum_l max(0, n . l_l) with
+                              the unit interpolated normal n (the same value as
+                              DEFERRED, without a G-buffer); needs normals and
+                              lights, no G-buffer targets */
 } pk_shading;
 
 enum {
@@ -200,11 +205,11 @@ typedef struct {                 /* [host] struct of device pointers */
 typedef struct {                 /* [host] struct of device pointers */
     const float *color;          /* [3][V] per-vertex RGB (albedo for DEFERRED) */
     const float *uv;             /* [2][V] texture coordinates, TEXTURED only */
-    const float *normal;         /* [3][V] per-vertex normals, DEFERRED only */
+    const float *normal;         /* [3][V] per-vertex normals, DEFERRED and LIT only */
     const float *texture;        /* [tex_h][tex_w][3] float32, TEXTURED only; texel
                                     centres at ((i+1/2)/tex_w, (j+1/2)/tex_h), clamp to edge */
     int32_t tex_w, tex_h;
-    const float *lights;         /* [num_lights][3] unit directions, DEFERRED only */
+    const float *lights;         /* [num_lights][3] unit directions, DEFERRED and LIT only */
     int32_t num_lights;
     const float *alpha;          /* [V] per-vertex opacity in [0, 1]; pk_params.layers > 0 only */
 } pk_attribs;

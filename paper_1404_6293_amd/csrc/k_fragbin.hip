@@ -120,7 +120,7 @@ __device__ inline void fb_attribs(const Geom &G, const Shade &sh, const FbTri &t
                 ex[0][ch] = a.x; ex[1][ch] = a.y; ex[2][ch] = a.z;
             }
         }
-        if (SHADE == PK_SHADE_DEFERRED) {
+        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const F3 a = *reinterpret_cast<const F3 *>(sh.normal + ch * V + v0);
@@ -137,7 +137,7 @@ __device__ inline void fb_attribs(const Geom &G, const Shade &sh, const FbTri &t
             ex[k][0] = sh.uv[t.v[k]];
             ex[k][1] = sh.uv[V + t.v[k]];
         }
-        if (SHADE == PK_SHADE_DEFERRED) {
+        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) ex[k][ch] = sh.normal[ch * V + t.v[k]];
         }
@@ -488,6 +488,7 @@ hipError_t launch_fb_raster(const Geom &G, const Ws &w, const Shade &sh, bool li
         case PK_SHADE_GOURAUD:  e = launch_pass<false, PK_SHADE_GOURAUD>(G, w, sh, st); break;
         case PK_SHADE_TEXTURED: e = launch_pass<false, PK_SHADE_TEXTURED>(G, w, sh, st); break;
         case PK_SHADE_DEFERRED: e = launch_pass<false, PK_SHADE_DEFERRED>(G, w, sh, st); break;
+        case PK_SHADE_LIT:      e = launch_pass<false, PK_SHADE_LIT>(G, w, sh, st); break;
         default:                e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
@@ -495,6 +496,7 @@ hipError_t launch_fb_raster(const Geom &G, const Ws &w, const Shade &sh, bool li
     switch (sh.shading) {
     case PK_SHADE_GOURAUD:  e = launch_composite<PK_SHADE_GOURAUD, false>(G, w, sh, st); break;
     case PK_SHADE_TEXTURED: e = launch_composite<PK_SHADE_TEXTURED, false>(G, w, sh, st); break;
+    case PK_SHADE_LIT:      e = launch_composite<PK_SHADE_LIT, false>(G, w, sh, st); break;
     case PK_SHADE_DEFERRED:
         e = light ? launch_composite<PK_SHADE_DEFERRED, true>(G, w, sh, st)
                   : launch_composite<PK_SHADE_DEFERRED, false>(G, w, sh, st);

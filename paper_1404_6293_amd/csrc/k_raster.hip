@@ -40,7 +40,6 @@ struct RasterArgs {
     Ws w;
     Shade sh;
     int32_t schedule;
-    int32_t dyn_batch;      // bins taken per pop of a DYNAMIC queue
 };
 
 // Resolve of one pixel in three phases so that the loads of several pixels
@@ -129,7 +128,7 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
                 r.ex[0][ch] = u.x; r.ex[1][ch] = u.y; r.ex[2][ch] = u.z;
             }
         }
-        if (SHADE == PK_SHADE_DEFERRED) {
+        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 const Float3 n = *reinterpret_cast<const Float3 *>(sh.normal + ch * V + v0);
@@ -146,7 +145,7 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
             r.ex[k][0] = sh.uv[r.v[k]];
             r.ex[k][1] = sh.uv[V + r.v[k]];
         }
-        if (SHADE == PK_SHADE_DEFERRED) {
+        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) r.ex[k][ch] = sh.normal[ch * V + r.v[k]];
         }
@@ -373,33 +372,67 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
     const int64_t nwork = (!piped && a.w.split && !overflow) ? (int64_t)voff[nb] : 0;
     int32_t piece = 0;
     // DYNAMIC: current queue (range) and the bins of the last batch taken
-    int qx = xcd, q_tried = 0;
     int64_t batch_beg = 0, batch_end = 0;
     for (int64_t it = 0;; ++it) {
         int64_t bin;
         if (!piped && a.schedule == PK_SCHED_DYNAMIC) {
+            // Each die's bins, heaviest first (the order the scan built):
+            // the first min(groups, bins) of a die's order go one to each of
+            // its workgroups without any atomic.  The rest (the tail) are
+            // dealt round-robin to kSubQueues queues per die and popped one
+            // at a time: a workgroup starts at queue (its number mod
+            // kSubQueues) of its die, then tries the die's other queues,
+            // then the other dies'.
+            if (it == 0) {
+                const int64_t nstat = min<int64_t>(groups_in_xcd, r_len);
+                if (lane_in_xcd < nstat) {
+                    batch_beg = r_beg + lane_in_xcd;
+                    batch_end = batch_beg + 1;
+                }
+            }
             if (batch_beg >= batch_end) {
-                // take a batch of bins from this die's queue; when it is
-                // empty, move on to the other dies' queues
-                if (tid == 0) {
+                if (tid < kWave) {
+                    // the first wave looks at the heads at once, lane l at
+                    // this workgroup's l-th choice, and pops the first
+                    // non-empty one; a queue found drained by a pop is never
+                    // chosen again, so this ends
                     int64_t b0 = 0, b1 = 0;
-                    while (q_tried < kXcd) {
-                        const int64_t qb = qx * q + min<int64_t>(qx, rem);
-                        const int64_t ql = q + (qx < rem ? 1 : 0);
-                        // look before popping: once a queue is drained every
-                        // workgroup would otherwise add to its head, and
-                        // read-modify-writes on one address serialize
-                        const uint32_t seen = __hip_atomic_load(&a.w.misc[8 + qx], __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                        if ((int64_t)seen < ql) {
-                            const int64_t t = (int64_t)atomicAdd(&a.w.misc[8 + qx], (uint32_t)a.dyn_batch);
-                            if (t < ql) { b0 = qb + t; b1 = qb + min<int64_t>(t + a.dyn_batch, ql); break; }
+                    const int s0 = (int)(lane_in_xcd % kSubQueues);
+                    const int qd = (xcd + lane / kSubQueues) % kXcd;
+                    const int qsub = (s0 + lane) % kSubQueues;
+                    const int64_t qb = qd * q + min<int64_t>(qd, rem);
+                    const int64_t ql = q + (qd < rem ? 1 : 0);
+                    const int64_t qg = ((int64_t)gridDim.x - qd + kXcd - 1) / kXcd;
+                    const int64_t tail = ql - min<int64_t>(qg, ql);   // after the static part
+                    uint32_t *head = &a.w.misc[kQueueBase + kQueueStride * (qd * kSubQueues + qsub)];
+                    // first the die's own queues (lanes 0..kSubQueues-1), and
+                    // only when they are drained all of them
+                    int nq = kSubQueues;
+#pragma unroll 1
+                    for (int tries = 0; tries < kSubQueues + kXcd * kSubQueues; ++tries) {
+                        uint32_t seen = 0xffffffffu;
+                        if (lane < nq)
+                            seen = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const uint64_t avail = __ballot(lane < nq &&
+                                                        qsub + (int64_t)kSubQueues * seen < tail);
+                        if (!avail) {
+                            if (nq == kWave) break;
+                            nq = kWave;
+                            continue;
                         }
-                        qx = (qx + 1) % kXcd;
-                        ++q_tried;
+                        const int f = __ffsll((unsigned long long)avail) - 1;
+                        int64_t got = -1;
+                        if (lane == f) {
+                            const int64_t i = qsub + (int64_t)kSubQueues * (int64_t)atomicAdd(head, 1u);
+                            if (i < tail) got = qb + (ql - tail) + i;
+                        }
+                        got = __shfl(got, f, kWave);
+                        if (got >= 0) { b0 = got; b1 = got + 1; break; }
                     }
-                    s_bin = b0;
-                    s_bin_end = b1;
+                    if (tid == 0) {
+                        s_bin = b0;
+                        s_bin_end = b1;
+                    }
                 }
                 __syncthreads();
                 batch_beg = __builtin_amdgcn_readfirstlane((int)s_bin);
@@ -407,7 +440,8 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 __syncthreads();
                 if (batch_beg >= batch_end) break;
             }
-            bin = batch_beg++;
+            // a position in the order; the bin itself is the order's entry
+            bin = a.w.order[batch_beg++];
         } else if (piped) {
             bin = dm_bin(it);
             if (bin < 0) break;
@@ -801,7 +835,7 @@ __global__ __launch_bounds__(kFragSlots) void k_raster_epilogue(uint32_t *misc,
             *frag_count += tot;
         }
     }
-    if (rewind && threadIdx.x < kXcd) misc[8 + threadIdx.x] = 0u;
+    if (rewind && threadIdx.x < kXcd * kSubQueues) misc[kQueueBase + kQueueStride * threadIdx.x] = 0u;
 }
 
 hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewind,
@@ -939,7 +973,7 @@ hipError_t launch_direct(const Geom &G, const Ws &w, const Shade &sh, RasterMode
     const int64_t npix = (int64_t)G.S * G.W * G.H;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(w.keys), 2 * npix, 0xffffffffu, st);
     if (e != hipSuccess) return e;
-    RasterArgs a{G, w, sh, 0, 1};
+    RasterArgs a{G, w, sh, 0};
     if (G.items > 0) {
         const int64_t blocks = (G.items + kDirectThreads - 1) / kDirectThreads;
         hipLaunchKernelGGL(k_direct, dim3((unsigned)blocks), dim3(kDirectThreads), 0, st, a);
@@ -1173,7 +1207,7 @@ static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
 
 hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
-    RasterArgs a{G, w, sh, 0, 1};
+    RasterArgs a{G, w, sh, 0};
     if (sh.layers > 0) {
         const int64_t ntiles = (int64_t)((G.W + kResW - 1) / kResW) *
                                ((G.H + kResRows - 1) / kResRows) * G.S;
@@ -1184,6 +1218,7 @@ hipError_t launch_resolve_pass(const Geom &G, const Ws &w, const Shade &sh, hipS
     case PK_SHADE_GOURAUD:  return launch_resolve<PK_SHADE_GOURAUD>(a, st);
     case PK_SHADE_TEXTURED: return launch_resolve<PK_SHADE_TEXTURED>(a, st);
     case PK_SHADE_DEFERRED: return launch_resolve<PK_SHADE_DEFERRED>(a, st);
+    case PK_SHADE_LIT:      return launch_resolve<PK_SHADE_LIT>(a, st);
     default:                return hipErrorInvalidValue;
     }
 }
@@ -1192,11 +1227,7 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
                          int groups, RasterMode mode, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
     if (G.B == 0) return launch_direct(G, w, sh, mode, st);
-    // DYNAMIC pops are device-scope atomics on eight counters; take enough
-    // bins per pop that each workgroup pops about four times
-    int64_t per = G.nbins_total / ((int64_t)groups * 4);
-    const int32_t dyn_batch = (int32_t)(per < 1 ? 1 : (per > 64 ? 64 : per));
-    RasterArgs a{G, w, sh, schedule, dyn_batch};
+    RasterArgs a{G, w, sh, schedule};
     int64_t nblk = G.nbins_total;
     if (schedule != PK_SCHED_LOAD_BALANCE) nblk = groups < G.nbins_total ? groups : G.nbins_total;
     const dim3 grid((unsigned)nblk);
@@ -1215,6 +1246,7 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
         case PK_SHADE_GOURAUD:  e = launch_shade<PK_SHADE_GOURAUD>(a, tpb, grid, st); break;
         case PK_SHADE_TEXTURED: e = launch_shade<PK_SHADE_TEXTURED>(a, tpb, grid, st); break;
         case PK_SHADE_DEFERRED: e = launch_shade<PK_SHADE_DEFERRED>(a, tpb, grid, st); break;
+        case PK_SHADE_LIT:      e = launch_shade<PK_SHADE_LIT>(a, tpb, grid, st); break;
         default:                e = hipErrorInvalidValue;
         }
     }

@@ -378,6 +378,7 @@ __device__ inline int64_t block_scan(int64_t n, Get get, Put put, uint32_t *s_v,
 __global__ __launch_bounds__(kScanThreads) void k_scan(Ws w, int64_t n, int64_t *pairs_needed) {
     __shared__ uint32_t s_v[kScanTile];
     __shared__ int64_t s_part[kScanThreads / kWave];
+    __shared__ int s_hist[33];
     const int64_t carry = block_scan(
         n, [&](int64_t i) { return w.bin_count[i]; },
         [&](int64_t i, int32_t o) { w.bin_off[i] = o; w.cursor[i] = o; }, s_v, s_part);
@@ -386,6 +387,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(Ws w, int64_t n, int64_t 
         w.bin_off[n] = fits ? (int32_t)carry : 0;
         w.misc[1] = fits ? 0u : 1u;
         if (pairs_needed) *pairs_needed = carry;
+    }
+    if (w.order) {
+        // DYNAMIC: each die's range of bins (the bin kernel's ranges) ordered
+        // by descending pair count, in buckets of equal bit length (empty
+        // bins last), by a counting sort per range
+        const int64_t q = n / kXcd, rem = n % kXcd;
+        for (int d = 0; d < kXcd; ++d) {
+            const int64_t beg = d * q + min<int64_t>(d, rem), len = q + (d < rem ? 1 : 0);
+            if (threadIdx.x < 33) s_hist[threadIdx.x] = 0;
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < len; i += kScanThreads) {
+                const uint32_t c = w.bin_count[beg + i];
+                atomicAdd(&s_hist[c ? 32 - __clz((int)c) : 0], 1);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int run = 0;
+                for (int bk = 32; bk >= 0; --bk) {
+                    const int t = s_hist[bk];
+                    s_hist[bk] = run;
+                    run += t;
+                }
+            }
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < len; i += kScanThreads) {
+                const uint32_t c = w.bin_count[beg + i];
+                const int pos = atomicAdd(&s_hist[c ? 32 - __clz((int)c) : 0], 1);
+                w.order[beg + pos] = (int32_t)(beg + i);
+            }
+            __syncthreads();
+        }
     }
     if (w.split && fits) {
         // PK_SCHED_SPLIT: bin b is ceil(count / split) work items (none when

@@ -37,6 +37,7 @@ struct Frame {
     int64_t nbins_total = 0;
     int nbx = 0, nby = 0;
     bool fragbins = false; // PK_SCHED_FRAGMENT_BINS
+    bool dynamic = false;  // PK_SCHED_DYNAMIC with bins: the bins' order
     int32_t fb_groups = 0, fb_rounds = 0, fb_planes = 0;
 };
 
@@ -59,12 +60,13 @@ pk_status check_params(const pk_params *p, Frame &f) {
     if (p->schedule == PK_SCHED_SPLIT && (p->flags & PK_FLAG_FUSE_RESOLVE))
         return PK_ERR_INVALID_ARGUMENT;
     f.layers = p->layers;
+    f.dynamic = p->schedule == PK_SCHED_DYNAMIC && p->bin_size != 0 && p->layers == 0;
     f.split = (p->schedule == PK_SCHED_SPLIT && p->bin_size != 0)
                   ? (p->split_size ? p->split_size : 256) : 0;
     if (p->threads_per_bin != 0 && p->threads_per_bin != 64 && p->threads_per_bin != 128 &&
         p->threads_per_bin != 256)
         return PK_ERR_INVALID_ARGUMENT;
-    if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_DEFERRED)
+    if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_LIT)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE | PK_FLAG_DEFER_SHADE))
         return PK_ERR_INVALID_ARGUMENT;
@@ -120,8 +122,8 @@ pk_status check_mesh(const pk_params *p, const pk_mesh *m, Frame &f) {
 }
 
 struct Layout {
-    size_t vtx, rec, iw, bbox, fb_mat, bin_count, bin_off, vbin_off, cursor, misc, keys, pairs,
-        total;
+    size_t vtx, rec, iw, bbox, fb_mat, bin_count, bin_off, vbin_off, order, cursor, misc, keys,
+        pairs, total;
 };
 
 Layout layout(const Frame &f, int64_t pair_capacity) {
@@ -141,6 +143,7 @@ Layout layout(const Frame &f, int64_t pair_capacity) {
     L.misc = o;      o = align_up(o + sizeof(uint32_t) * kMiscWords);
     L.bin_off = o;   o = align_up(o + sizeof(int32_t) * (size_t)(f.nbins_total + 1));
     L.vbin_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)(f.split ? f.nbins_total + 1 : 0));
+    L.order = o;     o = align_up(o + sizeof(int32_t) * (size_t)(f.dynamic ? f.nbins_total : 0));
     L.keys = o;      o = align_up(o + sizeof(uint64_t) * (f.fragbins ? 0 : (size_t)f.npix * (size_t)(f.layers > 0 ? f.layers : 1)));
     L.pairs = o;     o = align_up(o + (f.fragbins ? 16 * (size_t)f.fb_planes * (size_t)((pair_capacity + 63) / 64 * 64)
                                                  : sizeof(int32_t) * (size_t)pair_capacity));
@@ -161,6 +164,7 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.bin_count = reinterpret_cast<uint32_t *>(b + L.bin_count);
     w.bin_off = reinterpret_cast<int32_t *>(b + L.bin_off);
     w.vbin_off = f.split ? reinterpret_cast<int32_t *>(b + L.vbin_off) : nullptr;
+    w.order = f.dynamic ? reinterpret_cast<int32_t *>(b + L.order) : nullptr;
     w.split = f.split;
     w.cursor = reinterpret_cast<int32_t *>(b + L.cursor);
     w.keys = reinterpret_cast<unsigned long long *>(b + L.keys);
@@ -233,6 +237,9 @@ pk_status shade_args(const pk_params *p, const pk_attribs *a, const pk_targets *
     if (p->shading == PK_SHADE_DEFERRED &&
         (!a->normal || !out->gbuf_normal || !out->gbuf_albedo || !out->primid || !out->color ||
          a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
+        return PK_ERR_INVALID_ARGUMENT;
+    if (p->shading == PK_SHADE_LIT &&
+        (!a->normal || a->num_lights < 0 || (a->num_lights > 0 && !a->lights)))
         return PK_ERR_INVALID_ARGUMENT;
     if ((p->flags & PK_FLAG_COUNT_FRAGS) && !out->frag_count) return PK_ERR_INVALID_ARGUMENT;
     if (p->layers > 0 && !a->alpha) return PK_ERR_INVALID_ARGUMENT;
@@ -361,7 +368,8 @@ pk_status pk_backward(const pk_params *p, const pk_mesh *m, const pk_attribs *a,
     pk_status st = check_params(p, f);
     if (st != PK_OK) return st;
     if ((st = check_mesh(p, m, f)) != PK_OK) return st;
-    if (p->shading == PK_SHADE_DEFERRED || p->layers > 0) return PK_ERR_UNSUPPORTED;
+    if (p->shading == PK_SHADE_DEFERRED || p->shading == PK_SHADE_LIT || p->layers > 0)
+        return PK_ERR_UNSUPPORTED;
     if (!a || !primid || !bary || !grad_color || !grad_vcolor || !a->color)
         return PK_ERR_INVALID_ARGUMENT;
     if (p->shading == PK_SHADE_TEXTURED &&

@@ -18,7 +18,13 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 // kernel: device-scope atomics on a single address serialize, thousands of
 // them cost more than the kernel they count in.
 constexpr int kFragSlots = 256;
-constexpr int kMiscWords = 64 + 2 * kFragSlots;
+// DYNAMIC queue heads: kSubQueues per die, each on a 256-byte line of its
+// own (atomics on words of one line serialize at the memory side as if on
+// one address): head q at misc[kQueueBase + kQueueStride * q]
+constexpr int kSubQueues = 8;
+constexpr int kQueueBase = 64 + 2 * kFragSlots;
+constexpr int kQueueStride = 64;
+constexpr int kMiscWords = kQueueBase + kXcd * kSubQueues * kQueueStride;
 
 // Per-triangle setup record, 32 bytes (a quarter of a 128-byte cache line,
 // two dwordx4 loads): the six fixed-point screen coordinates X0 Y0 X1 Y1 X2
@@ -184,13 +190,15 @@ struct Ws {
     uint64_t *bbox;            // [items], kEmptyKey for culled triangles
     uint32_t *bin_count;       // [nbins_total]
     int32_t *bin_off;          // [nbins_total + 1]
+    int32_t *order;            // [nbins_total] DYNAMIC only (else NULL): each die's
+                               // range of bins, heaviest first
     int32_t *vbin_off;         // [nbins_total + 1] first work item of each bin
                                // (PK_SCHED_SPLIT only, else NULL)
     int32_t *cursor;           // [nbins_total], between bin_count and misc: next
                                // free slot of each bin (set by the scan)
     uint32_t *misc;            // [kMiscWords], right after bin_count: [1] pair
-                               // overflow flag, [8..15] DYNAMIC queue heads,
-                               // [64..) kFragSlots 64-bit fragment partial sums;
+                               // overflow flag, [64..) kFragSlots 64-bit fragment
+                               // partial sums, [kQueueBase..) DYNAMIC queue heads;
                                // zeroed by pk_setup, heads and sums re-zeroed
                                // after each bin kernel that used them
     unsigned long long *keys;  // [S][H][W] winning (depth, primitive) keys
@@ -216,11 +224,27 @@ struct Shade {
     int32_t layers;            // 0 = opaque, else layers composited per pixel
 };
 
+// Lighting of the deferred pass: sum over the lights of max(0, n . l), in
+// the lights' order.
+__device__ inline float light_sum(const Shade &sh, float n0, float n1, float n2) {
+    float lit = 0.0f;
+    for (int l = 0; l < sh.num_lights; ++l) {
+        const float *L = sh.lights + 3 * l;
+        float d = n0 * L[0];
+        d = d + n1 * L[1];
+        d = d + n2 * L[2];
+        d = d < 0.0f ? 0.0f : d;
+        lit = (l == 0) ? d : lit + d;
+    }
+    return lit;
+}
+
 // Fragment shader of one covered sample from its float32 screen-space
 // barycentrics bs_k and the three vertices' 1/w: perspective-correct b1, b2
 // (b0 = 1 - b1 - b2), then the interpolated colour (modulated by the bilinear
-// texture for TEXTURED), or for DEFERRED the interpolated albedo and the unit
-// interpolated normal.  c[k][ch] are vertex colours, ex[k][ch] the uv
+// texture for TEXTURED), for DEFERRED the interpolated albedo and the unit
+// interpolated normal, and for LIT that albedo times the sum over the lights
+// of max(0, n . l).  c[k][ch] are vertex colours, ex[k][ch] the uv
 // (TEXTURED) or normal (DEFERRED) of vertex k.
 struct FragOut {
     float b1, b2;
@@ -274,7 +298,7 @@ __device__ inline void shade_fragment(const Shade &sh, float bs0, float bs1, flo
             o.rgb[ch] = o.rgb[ch] * tc;
         }
     }
-    if (SHADE == PK_SHADE_DEFERRED) {
+    if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
         float n[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -292,21 +316,11 @@ __device__ inline void shade_fragment(const Shade &sh, float bs0, float bs1, flo
             o.n[0] = n[0] / len; o.n[1] = n[1] / len; o.n[2] = n[2] / len;
         }
     }
-}
-
-// Lighting of the deferred pass: sum over the lights of max(0, n . l), in
-// the lights' order.
-__device__ inline float light_sum(const Shade &sh, float n0, float n1, float n2) {
-    float lit = 0.0f;
-    for (int l = 0; l < sh.num_lights; ++l) {
-        const float *L = sh.lights + 3 * l;
-        float d = n0 * L[0];
-        d = d + n1 * L[1];
-        d = d + n2 * L[2];
-        d = d < 0.0f ? 0.0f : d;
-        lit = (l == 0) ? d : lit + d;
+    if (SHADE == PK_SHADE_LIT) {
+        const float lit = light_sum(sh, o.n[0], o.n[1], o.n[2]);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) o.rgb[ch] = o.rgb[ch] * lit;
     }
-    return lit;
 }
 
 // Which scene an item belongs to and which triangle of the mesh it is.

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpk.so")
 # enums of pk.h
 PK_OK, PK_ERR_INVALID_ARGUMENT, PK_ERR_CAPACITY, PK_ERR_HIP, PK_ERR_UNSUPPORTED = range(5)
 PK_SCHED_LOAD_BALANCE, PK_SCHED_DIRECT_MAP, PK_SCHED_DYNAMIC, PK_SCHED_SPLIT, PK_SCHED_FRAGMENT_BINS = range(5)
-PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED = range(3)
+PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED, PK_SHADE_LIT = range(4)
 PK_FLAG_COUNT_FRAGS = 1
 PK_FLAG_FUSE_RESOLVE = 2
 PK_FLAG_DEFER_SHADE = 4
@@ -30,7 +30,7 @@ SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIREC
              "dynamic": PK_SCHED_DYNAMIC, "split": PK_SCHED_SPLIT,
              "fragment_bins": PK_SCHED_FRAGMENT_BINS}
 SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
-            "deferred": PK_SHADE_DEFERRED}
+            "deferred": PK_SHADE_DEFERRED, "lit": PK_SHADE_LIT}
 
 EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_shade",
            "pk_backward", "pk_bin_lists", "pk_status_string", "pk_render_static")

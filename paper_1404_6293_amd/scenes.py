@@ -54,7 +54,7 @@ class Scene:
     texture: Optional[np.ndarray] = None  # [Nh][Nw][3] float32
     lights: Optional[np.ndarray] = None  # [L][3] float32 unit vectors
     bin_size: int = 16
-    shading: str = "gouraud"             # gouraud | textured | deferred
+    shading: str = "gouraud"             # gouraud | textured | deferred | lit
     name: str = ""
 
     @property
@@ -80,6 +80,19 @@ def lights(num: int) -> np.ndarray:
         v = np.array([math.cos(a), math.sin(a), 1.0])
         out.append(v / np.linalg.norm(v))
     return np.asarray(out, dtype=np.float64).astype(np.float32)
+
+
+def with_lighting(sc: Scene, num_lights: int = 1, seed: int = 7,
+                  shading: str = "lit") -> Scene:
+    """A copy of ``sc`` lit by ``num_lights`` lights (see ``lights``): per-vertex
+    unit normals drawn as normalize(N(0, I)) with z made non-negative, and
+    forward-lit (or deferred) shading."""
+    rng = np.random.default_rng(seed)
+    n = rng.standard_normal(size=(3, sc.pos.shape[1]))
+    n[2] = np.abs(n[2])
+    n /= np.linalg.norm(n, axis=0, keepdims=True)
+    return dataclasses.replace(sc, normal=n.astype(np.float32), lights=lights(num_lights),
+                               shading=shading, name=f"{sc.name}_{shading}{num_lights}")
 
 
 # ---------------------------------------------------------------------------
@@ -239,6 +252,30 @@ def batch(num_scenes: int = 256, size: int = 256, tmin: int = 1000, tmax: int = 
                  scene_tri_off=np.asarray(tri_off, dtype=np.int32),
                  scene_vtx_off=np.asarray(vtx_off, dtype=np.int32),
                  bin_size=bin_size, name=f"batch{num_scenes}x{size}")
+
+
+def mixed(seed: int = 6006, width: int = 1920, height: int = 1080, num_small: int = 1 << 20,
+          num_large: int = 512, small_len: float = math.log(4.0), large_len: float = math.log(150.0),
+          sigma: float = 0.5) -> Scene:
+    """One frame of many small and some large triangles (the Fairy Forest
+    class, "many small and large"): ``num_small`` triangles with edges
+    log-normal around 4 px and ``num_large`` around 150 px, in random
+    submission order, one z ~ U[0, 1) per vertex, RGB ~ U[0, 1); NDC input,
+    w = 1."""
+    rng = np.random.default_rng(seed)
+    T = num_small + num_large
+    mu = np.where(rng.permutation(T) < num_large, large_len, small_len)
+    v0 = rng.uniform(0.0, 1.0, size=(2, T)) * np.array([[width], [height]])
+    L = rng.lognormal(mu, sigma, size=(2, T))
+    th = rng.uniform(0.0, 2 * math.pi, size=(2, T))
+    v1 = v0 + L[0] * np.stack([np.cos(th[0]), np.sin(th[0])])
+    v2 = v0 + L[1] * np.stack([np.cos(th[1]), np.sin(th[1])])
+    xy = np.stack([v0, v1, v2], axis=2).reshape(2, 3 * T)        # vertex 3t+k
+    ndc = xy / np.array([[width / 2.0], [height / 2.0]]) - 1.0
+    z = rng.uniform(0.0, 1.0, size=(1, 3 * T))
+    pos = np.concatenate([ndc, z]).astype(np.float32)
+    color = rng.uniform(0.0, 1.0, size=(3, 3 * T)).astype(np.float32)
+    return Scene(width, height, pos, color, None, T, name=f"mixed{num_small}+{num_large}")
 
 
 def split_batch(sc: Scene, s: int) -> Scene:

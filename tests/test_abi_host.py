@@ -62,7 +62,7 @@ def _mesh(**kw):
     dict(bin_size=-8), dict(schedule=5), dict(schedule=-1), dict(threads_per_bin=32),
     dict(split_size=-1), dict(schedule=3, flags=2), dict(layers=-1), dict(layers=9),
     dict(layers=2, flags=2),
-    dict(threads_per_bin=512), dict(shading=3), dict(flags=8), dict(flags=6), dict(num_scenes=0),
+    dict(threads_per_bin=512), dict(shading=4), dict(flags=8), dict(flags=6), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
     p = _params(**bad)
@@ -80,7 +80,7 @@ def test_whole_screen_bins(L):
     for S in (1, 3):
         p = _params(width=100, height=70, bin_size=0, num_scenes=S, instanced=int(S > 1))
         nb = S
-        want = (al(32 * S * T) + al(16 * S * T) + al(8 * S * T) + al(4 * nb) + al(4 * 576)
+        want = (al(32 * S * T) + al(16 * S * T) + al(8 * S * T) + al(4 * nb) + al(4 * 4672)
                 + al(4 * (nb + 1)) + al(4 * nb) + al(8 * S * 100 * 70))
         assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 0) == want
         v = pk.BinView()
@@ -145,7 +145,7 @@ def test_workspace_bytes_arithmetic(L):
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     # 32-byte setup records, 16 bytes of 1/w per triangle (unindexed only),
     # 8-byte bboxes, counts, misc words, offsets, cursors, keys
-    common = (al(8 * T) + al(4 * nbins) + al(4 * 576) + al(4 * (nbins + 1)) + al(4 * nbins)
+    common = (al(8 * T) + al(4 * nbins) + al(4 * 4672) + al(4 * (nbins + 1)) + al(4 * nbins)
               + al(8 * 100 * 70))
     assert b0 == al(32 * T) + al(16 * T) + common
     # an indexed mesh has one 16-byte snapped record per vertex (per view)
@@ -155,7 +155,7 @@ def test_workspace_bytes_arithmetic(L):
     # instanced views multiply the per-triangle and per-vertex slices
     pi = _params(width=100, height=70, bin_size=16, num_scenes=3, instanced=1)
     nb3 = 3 * nbins
-    common3 = (al(8 * 3 * T) + al(4 * nb3) + al(4 * 576) + al(4 * (nb3 + 1)) + al(4 * nb3)
+    common3 = (al(8 * 3 * T) + al(4 * nb3) + al(4 * 4672) + al(4 * (nb3 + 1)) + al(4 * nb3)
                + al(8 * 3 * 100 * 70))
     assert L.pk_workspace_bytes(C.byref(pi), C.byref(m), 0) == al(32 * 3 * T) + al(16 * 3 * T) + common3
     assert L.pk_workspace_bytes(C.byref(pi), C.byref(mi), 0) == (al(16 * 3 * 600) + al(32 * 3 * T)
@@ -167,7 +167,8 @@ def test_workspace_bytes_arithmetic(L):
 
 def test_split_schedule_workspace(L):
     """PK_SCHED_SPLIT adds one work-item number per bin (+1) to the
-    workspace; other schedules and whole-screen bins do not."""
+    workspace and PK_SCHED_DYNAMIC one bin number per bin; other schedules
+    and whole-screen bins add nothing."""
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
     m = _mesh(num_tris=1000, num_vertices=3000)
     base = L.pk_workspace_bytes(C.byref(_params(width=100, height=70, bin_size=16, schedule=1)),
@@ -178,6 +179,9 @@ def test_split_schedule_workspace(L):
     p0 = _params(width=100, height=70, bin_size=0, schedule=3)
     assert L.pk_workspace_bytes(C.byref(p0), C.byref(m), 0) == L.pk_workspace_bytes(
         C.byref(_params(width=100, height=70, bin_size=0)), C.byref(m), 0)
+    # DYNAMIC keeps each die's bins in heaviest-first order: one word per bin
+    pd = _params(width=100, height=70, bin_size=16, schedule=2)
+    assert L.pk_workspace_bytes(C.byref(pd), C.byref(m), 0) == base + al(4 * 35)
 
 
 @pytest.mark.parametrize("kw", [dict(shading=1), dict(shading=2), dict(bin_size=0), dict(bin_size=64),
@@ -258,7 +262,7 @@ def test_fragment_bins_restrictions_and_workspace(L):
     nb = 12
     for shading, planes in ((0, 2), (2, 3)):
         p.shading = shading
-        want = (al(4 * 1 * nb) + al(4 * nb) + al(4 * nb) + al(4 * 576) + al(4 * (nb + 1))
+        want = (al(4 * 1 * nb) + al(4 * nb) + al(4 * nb) + al(4 * 4672) + al(4 * (nb + 1))
                 + al(16 * planes * 128))
         assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 100) == want
     v = pk.BinView()

@@ -164,3 +164,34 @@ def test_unsupported_requests_are_refused():
         pk.Renderer(sc, pk.RenderConfig(bin_size=16, **FB)).render()
     with pytest.raises(pk.PkError):
         pk.Renderer(scenes.tiny(seed=2), pk.RenderConfig(bin_size=8, **FB)).render()
+
+
+# ---------------------------------------------------------------------------
+# forward lighting in the fragment shader (PK_SHADE_LIT), every pipeline
+# ---------------------------------------------------------------------------
+LIT_MODES = {"split": dict(bin_size=16), "fused": dict(bin_size=16, fuse_resolve=True),
+             "defer": dict(bin_size=32, defer_shade=True), "unbinned": dict(bin_size=0),
+             "fragment_bins": dict(bin_size=32, schedule="fragment_bins"),
+             "load_balance": dict(bin_size=8, schedule="load_balance", fuse_resolve=True)}
+
+
+@pytest.mark.parametrize("mode", sorted(LIT_MODES))
+@pytest.mark.parametrize("L", [1, 5])
+def test_forward_lit_matches_oracle(mode, L):
+    """colour = vertex colour x the sum over the lights of max(0, n . l),
+    computed in the fragment shader: the oracle's forward-lit image (whose
+    colour equals the deferred one bit for bit) on random triangles and on
+    an indexed perspective grid."""
+    _note(f"forward lit mode={mode} lights={L}")
+    for sc in (scenes.with_lighting(scenes.tiny(seed=21 + L, width=90, height=70, num_tris=300), L),
+               scenes.with_lighting(scenes.grid(seed=4, width=160, height=96, nx=48, ny=24), L,
+                                    seed=9)):
+        compare(gpu_render(sc, **LIT_MODES[mode]), oracle.render(sc))
+
+
+def test_forward_lit_batched_scenes():
+    sc = scenes.with_lighting(scenes.batch(num_scenes=4, size=64, tmin=50, tmax=2000), 3)
+    o = oracle.render(sc)
+    for cfg in (dict(bin_size=16), dict(bin_size=0), dict(bin_size=8, schedule="split",
+                                                          split_size=16)):
+        compare(gpu_render(sc, **cfg), o)
