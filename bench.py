@@ -801,8 +801,8 @@ def main():
     kern = stages[dom]["kernel"]
     t_ms, alg_k = stage[dom], shares[dom]
     achieved = alg_k / (t_ms * 1e-3) / 1e9
-    prof_name = {"k_raster": "k_raster", "k_direct": "k_direct", "k_resolve": "k_resolve",
-                 "k_resolve + k_deferred": "k_resolve"}.get(kern)
+    # the committed profile's name for the stage's kernels (no spaces)
+    prof_name = kern.replace(" ", "") if not kern.startswith("(") else None
     roofline = {"bound": "hbm", "kernel": kern, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(args.workload, prof_name) if prof_name else None,
