@@ -473,6 +473,36 @@ def bench_lights(reps: int = 5) -> dict:
                         "1M-small + 512-large frame in four pipelines", "frame_ms": out}
 
 
+def bench_two_level(reps: int = 5) -> dict:
+    """Two bin levels (hierarchical bins, the paper's non-uniform bins of
+    Sec. 8) against one level: one whole frame per configuration on one
+    stream (ms), with the (bin, triangle) pairs of each, on the mixed frame
+    (1M small + 512 large triangles), batch256 and grid1080."""
+    import torch
+    from paper_1404_6293_amd import pk, scenes
+    out = {}
+    for name, make in (("mixed", scenes.mixed), ("batch256", scenes.batch),
+                       ("grid1080", scenes.grid)):
+        dev = pk.DeviceScene(make())
+        res = {}
+        for B in (8, 16):
+            for sched in ("load_balance", "direct_map"):
+                for tl in (False, True):
+                    r = pk.Renderer(dev, pk.RenderConfig(bin_size=B, schedule=sched,
+                                                         two_level=tl, want_bary=False))
+                    r.render()
+                    torch.cuda.synchronize()
+                    key = f"B{B}/{sched}/{'two_level' if tl else 'one_level'}"
+                    res[key] = {"frame_ms": round(_median_ms(torch, r.frame, reps), 4),
+                                "pairs": int(r.pairs_needed.item())}
+                    del r
+        out[name] = res
+        del dev
+    return {"workload": "mixed, batch256 and grid1080 with 8/16-px bins, one or two bin levels "
+                        "(coarse bins of 4x the size for triangles spanning more than 2x2 bins)",
+            "frames": out}
+
+
 def bench_ablation(reps: int = 5) -> dict:
     """The schedule ablation of Sec. 7.2 on grid1080: whole-screen bins (the
     unbinned baseline) and every bin size with each schedule, the resolve in
@@ -864,6 +894,8 @@ def main():
         out["transparency"] = bench_transparency()
         print("bench: light count", file=sys.stderr, flush=True)
         out["lights"] = bench_lights()
+        print("bench: two bin levels", file=sys.stderr, flush=True)
+        out["two_level"] = bench_two_level()
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(sc)

@@ -144,12 +144,25 @@ enum {
                                  (Rasterizer and Fragment Shader fused, Sec. 7.2)
                                  instead of in a separate per-pixel pass over the
                                  bins' winning keys; the image is the same */
-    PK_FLAG_DEFER_SHADE = 4   /* pk_raster_shade stops after the depth test:
+    PK_FLAG_DEFER_SHADE = 4,  /* pk_raster_shade stops after the depth test:
                                  every pixel's winning (depth, primitive) key
                                  goes to the depth and primid targets when both
                                  are given (they are then final), else to the
                                  workspace; pk_shade then resolves and shades.
                                  Excludes PK_FLAG_FUSE_RESOLVE. */
+    PK_FLAG_TWO_LEVEL_BINS = 8 /* two bin sizes (hierarchical bins, the paper's
+                                 non-uniform bins of Sec. 8): a triangle whose box
+                                 spans more than 2 x 2 bins is assigned to coarse
+                                 bins of four times bin_size instead of to the fine
+                                 ones.  The fine bins are tested first, then each
+                                 coarse bin starts from its pixels' keys and tests
+                                 its own triangles; the per-pixel resolve follows.
+                                 bin_size 8 or 16, LOAD_BALANCE or DIRECT_MAP,
+                                 opaque, not fused (else PK_ERR_UNSUPPORTED).  The
+                                 lists of pk_bin_lists then number each scene's
+                                 fine bins first, then its coarse bins (row-major,
+                                 ceil(W / (4 bin_size)) wide).  The image is the
+                                 same */
 };
 
 typedef struct {               /* [host] */

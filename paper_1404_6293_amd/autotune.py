@@ -31,7 +31,8 @@ THREADS = (64, 128, 256)
 
 
 def candidates(bins: Iterable[int] = BIN_SIZES, schedules: Iterable[str] = SCHEDULES,
-               threads: Iterable[int] = THREADS, fused: Iterable[bool] = (False, True)):
+               threads: Iterable[int] = THREADS, fused: Iterable[bool] = (False, True),
+               two_level: bool = True):
     if 0 in bins:
         # whole-screen bins ignore the schedule, the bin workgroup size and
         # fusion: one candidate
@@ -46,6 +47,9 @@ def candidates(bins: Iterable[int] = BIN_SIZES, schedules: Iterable[str] = SCHED
                 yield pk.RenderConfig(bin_size=b, schedule=s)
             continue
         yield pk.RenderConfig(bin_size=b, schedule=s, threads_per_bin=t, fuse_resolve=f)
+        if (two_level and b <= 16 and s in ("load_balance", "direct_map") and not f):
+            # large triangles to coarse bins of 4x the size
+            yield pk.RenderConfig(bin_size=b, schedule=s, threads_per_bin=t, two_level=True)
 
 
 def _key(dev: "pk.DeviceScene", frags_per_tri: float, want_bary: bool) -> str:
@@ -104,7 +108,8 @@ def autotune(scene, want_bary: bool = False, cands: Optional[Iterable] = None, r
             continue
         finally:
             r = None
-        desc = f"B{c.bin_size}/{c.schedule}/t{c.threads_per_bin}/{'fused' if c.fuse_resolve else 'split'}"
+        desc = (f"B{c.bin_size}/{c.schedule}/t{c.threads_per_bin}/"
+                f"{'fused' if c.fuse_resolve else 'split'}{'/two_level' if c.two_level else ''}")
         times[desc] = ms
         if verbose:
             print(f"autotune {key}: {desc} {ms:.4f} ms", flush=True)

@@ -40,7 +40,20 @@ struct RasterArgs {
     Ws w;
     Shade sh;
     int32_t schedule;
+    // Two bin levels: this launch's bins are one level of each scene's CSR
+    // block (csr_stride bins per scene, this level's first at csr_base;
+    // csr_stride 0: the launch's bins are the CSR bins).  init_keys: the key
+    // tile starts from the workspace keys (the finer level's result)
+    // instead of empty.
+    int32_t csr_stride, csr_base, init_keys;
 };
+
+// CSR number of bin b of the launch's bin grid.
+__device__ inline int64_t csr_bin(const RasterArgs &a, int64_t b) {
+    if (a.csr_stride == 0) return b;
+    const uint32_t s = (uint32_t)b / (uint32_t)a.G.nbins_scene;
+    return (int64_t)s * a.csr_stride + a.csr_base + (b - (int64_t)s * a.G.nbins_scene);
+}
 
 // Resolve of one pixel in three phases so that the loads of several pixels
 // can be in flight together: (1) unpack the winning key and load the
@@ -336,7 +349,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         o_it = b >= 0 ? it : -1;
         o_beg = 0;
         o_end = 0;
-        if (b >= 0 && !overflow) bin_range(a.w, b, o_beg, o_end);
+        if (b >= 0 && !overflow) bin_range(a.w, csr_bin(a, b), o_beg, o_end);
     };
     // move chunk n+2 one chunk on, and start loading its pair numbers
     auto advance_nn = [&]() {
@@ -504,14 +517,25 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 atomicMin(&s_key[sl], key);
             }
         };
-        for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
+        if (a.init_keys) {
+            // the coarse level starts from the fine level's keys
+            const int64_t sb = (int64_t)s * G.W * G.H;
+            for (int i = tid; i < NPIX; i += TPB) {
+                const int lx = i % B, ly = i / B;
+                s_key[i] = (lx < pw && ly < ph) ? a.w.keys[sb + (int64_t)(py0 + ly) * G.W + px0 + lx]
+                                                : kEmptyKey;
+            }
+        } else {
+            for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
+        }
         if (KBUF)
             for (int i = tid; i < (a.sh.layers - 1) * NPIX; i += TPB) s_kbuf[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
         bool shared = false;   // PK_SCHED_SPLIT: the bin has several pieces
         if (!overflow && !piped) {
-            lbeg = a.w.bin_off[bin];
-            lend = a.w.bin_off[bin + 1];
+            const int64_t cb = csr_bin(a, bin);
+            lbeg = a.w.bin_off[cb];
+            lend = a.w.bin_off[cb + 1];
             if (a.w.split) {
                 shared = lend - lbeg > a.w.split;
                 lbeg += piece * a.w.split;
@@ -737,7 +761,8 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             // as the final depth and primitive-ID targets when the caller
             // has both (the two halves of the key), else as keys
             const int64_t sb = (int64_t)s * G.W * G.H;
-            const bool split = !OIT && !KBUF && !a.w.split && a.sh.out_depth && a.sh.out_primid;
+            const bool split = !OIT && !KBUF && !a.w.split && !a.w.two_level && a.sh.out_depth &&
+                               a.sh.out_primid;
             // layer l's keys follow the whole key buffer of layers 0..l-1
             const int64_t lofs = OIT ? (int64_t)layer * G.S * G.W * G.H : 0;
 #pragma unroll 1
@@ -1023,7 +1048,7 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
     // keys in the workspace: whole-screen bins and split bins always, other
     // bins when a depth or primitive-ID target is missing
-    const bool split = G.B != 0 && !a.w.split && a.sh.out_depth && a.sh.out_primid;
+    const bool split = G.B != 0 && !a.w.split && !a.w.two_level && a.sh.out_depth && a.sh.out_primid;
     Resolve r[kResPPT];
     bool on[kResPPT];
 #pragma unroll
@@ -1227,6 +1252,37 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
                          int groups, RasterMode mode, hipStream_t st) {
     if (G.nbins_total == 0) return hipSuccess;
     if (G.B == 0) return launch_direct(G, w, sh, mode, st);
+    if (G.two_level) {
+        // fine bins (keys to the workspace), then coarse bins starting from
+        // those keys, then the per-pixel resolve
+        Geom Gf = G, Gc = G;
+        Gf.nbins_scene = G.nbins_f;
+        Gf.nbins_total = (int64_t)G.S * G.nbins_f;
+        Gc.B = 4 * G.B;
+        Gc.log2B = G.log2B + 2;
+        Gc.nbx = G.nbx_c;
+        Gc.nby = G.nby_c;
+        Gc.nbins_scene = G.nbx_c * G.nby_c;
+        Gc.nbins_total = (int64_t)G.S * Gc.nbins_scene;
+        hipError_t e = hipSuccess;
+        for (int level = 0; level < 2 && e == hipSuccess; ++level) {
+            const Geom &Gl = level ? Gc : Gf;
+            const int tl = level ? 256 : tpb;
+            RasterArgs al{Gl, w, sh, schedule, G.nbins_scene, level ? G.nbins_f : 0, level};
+            const int gl = level ? 256 * 16 * kWave / 256 : groups;
+            const int64_t nb = schedule == PK_SCHED_LOAD_BALANCE ? Gl.nbins_total
+                               : (gl < Gl.nbins_total ? gl : Gl.nbins_total);
+            e = launch_shade<kKeysOnly>(al, tl, dim3((unsigned)nb), st);
+        }
+        if (e != hipSuccess) return e;
+        if (sh.frag_count) {
+            hipLaunchKernelGGL(k_raster_epilogue, dim3(1), dim3(kFragSlots), 0, st, w.misc,
+                               sh.frag_count, 0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (mode == kRasterSplit) return launch_resolve_pass(G, w, sh, st);
+        return hipSuccess;
+    }
     RasterArgs a{G, w, sh, schedule};
     int64_t nblk = G.nbins_total;
     if (schedule != PK_SCHED_LOAD_BALANCE) nblk = groups < G.nbins_total ? groups : G.nbins_total;

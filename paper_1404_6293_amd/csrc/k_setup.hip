@@ -176,20 +176,38 @@ __device__ inline uint64_t setup_finish(const Geom &G, const Ws &w, int64_t item
     return bb;
 }
 
-// Bin rectangle of a packed bbox: nb bins starting at (bx0, by0), nbx_t wide.
+// Bin rectangle of a packed bbox: nb bins starting at (bx0, by0), nbx_t wide,
+// numbered base + by * stride + bx within the scene.  With two bin levels a
+// triangle whose box spans more than 2 x 2 fine bins goes to the coarse bins
+// (four times the size) instead.
 struct BinRect {
-    int bx0, by0, nbx_t, nb;
+    int bx0, by0, nbx_t, nb, base, stride;
 };
 
 __device__ inline BinRect bin_rect(const Geom &G, uint64_t bb) {
     BinRect r;
+    r.base = 0;
+    r.stride = G.nbx;
     if (bb == kEmptyKey) { r.bx0 = r.by0 = 0; r.nbx_t = 1; r.nb = 0; return r; }
-    r.bx0 = bb_x0(bb) >> G.log2B;
-    r.by0 = bb_y0(bb) >> G.log2B;
-    r.nbx_t = (bb_x1(bb) >> G.log2B) - r.bx0 + 1;
-    r.nb = r.nbx_t * ((bb_y1(bb) >> G.log2B) - r.by0 + 1);
+    int sh = G.log2B;
+    r.bx0 = bb_x0(bb) >> sh;
+    r.by0 = bb_y0(bb) >> sh;
+    r.nbx_t = (bb_x1(bb) >> sh) - r.bx0 + 1;
+    int rows = (bb_y1(bb) >> sh) - r.by0 + 1;
+    if (G.two_level && (r.nbx_t > 2 || rows > 2)) {
+        sh += 2;
+        r.bx0 = bb_x0(bb) >> sh;
+        r.by0 = bb_y0(bb) >> sh;
+        r.nbx_t = (bb_x1(bb) >> sh) - r.bx0 + 1;
+        rows = (bb_y1(bb) >> sh) - r.by0 + 1;
+        r.base = G.nbins_f;
+        r.stride = G.nbx_c;
+    }
+    r.nb = r.nbx_t * rows;
     return r;
 }
+
+__device__ inline int bin_of(const BinRect &br, int cx, int cy) { return br.base + cy * br.stride + cx; }
 
 // Range [lo, hi] of LDS window indices ((scene - s_lo) * bins per scene +
 // bin) that a triangle's bin rectangle touches; lo > hi when it touches none.
@@ -198,8 +216,8 @@ __device__ inline void window_span(const Geom &G, const BinRect &br, int32_t s, 
     if (br.nb == 0) { lo = INT_MAX; hi = INT_MIN; return; }
     const int base = (s - s_lo) * G.nbins_scene;
     const int rows = br.nb / br.nbx_t;
-    lo = base + br.by0 * G.nbx + br.bx0;
-    hi = base + (br.by0 + rows - 1) * G.nbx + br.bx0 + br.nbx_t - 1;
+    lo = base + bin_of(br, br.bx0, br.by0);
+    hi = base + bin_of(br, br.bx0 + br.nbx_t - 1, br.by0 + rows - 1);
 }
 
 // Smallest lo and largest hi over the workgroup.  Contains barriers: call
@@ -271,7 +289,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
             uint32_t *h = s_hist + (s - s_lo) * G.nbins_scene;
             int cx = br[k].bx0, cy = br[k].by0;
             for (int r = 0; r < br[k].nb; ++r) {
-                atomicAdd(h + cy * G.nbx + cx, 1u);
+                atomicAdd(h + bin_of(br[k], cx, cy), 1u);
                 if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
         } else {
@@ -280,7 +298,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
             const int base = s * G.nbins_scene;
             int cx = br[k].bx0, cy = br[k].by0;
             for (int r = 0; r < rounds; ++r) {
-                agg_count(w.bin_count, r < br[k].nb ? base + cy * G.nbx + cx : -1);
+                agg_count(w.bin_count, r < br[k].nb ? base + bin_of(br[k], cx, cy) : -1);
                 if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
         }
@@ -474,7 +492,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
             uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
             int cx = br.bx0, cy = br.by0;
             for (int r = 0; r < br.nb; ++r) {
-                atomicAdd(h + cy * G.nbx + cx, 1u);
+                atomicAdd(h + bin_of(br, cx, cy), 1u);
                 if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
         }
@@ -494,7 +512,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
             uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
             int cx = br.bx0, cy = br.by0;
             for (int r = 0; r < br.nb; ++r) {
-                const uint32_t slot = atomicAdd(h + cy * G.nbx + cx, 1u);
+                const uint32_t slot = atomicAdd(h + bin_of(br, cx, cy), 1u);
                 w.pairs[slot] = (int32_t)item;
                 if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
@@ -509,7 +527,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         const int base = sc[k] * G.nbins_scene;
         int cx = br.bx0, cy = br.by0;
         for (int r = 0; r < rounds; ++r) {
-            const int key = r < br.nb ? base + cy * G.nbx + cx : -1;
+            const int key = r < br.nb ? base + bin_of(br, cx, cy) : -1;
             const int32_t slot = agg_slot(w.cursor, key);
             if (key >= 0) w.pairs[slot] = (int32_t)item;
             if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }

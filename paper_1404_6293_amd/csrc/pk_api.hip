@@ -38,6 +38,9 @@ struct Frame {
     int nbx = 0, nby = 0;
     bool fragbins = false; // PK_SCHED_FRAGMENT_BINS
     bool dynamic = false;  // PK_SCHED_DYNAMIC with bins: the bins' order
+    bool two_level = false;                 // PK_FLAG_TWO_LEVEL_BINS
+    int64_t nbins_f = 0;
+    int nbx_c = 0, nby_c = 0;
     int32_t fb_groups = 0, fb_rounds = 0, fb_planes = 0;
 };
 
@@ -68,8 +71,14 @@ pk_status check_params(const pk_params *p, Frame &f) {
         return PK_ERR_INVALID_ARGUMENT;
     if (p->shading < PK_SHADE_GOURAUD || p->shading > PK_SHADE_LIT)
         return PK_ERR_INVALID_ARGUMENT;
-    if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE | PK_FLAG_DEFER_SHADE))
+    if (p->flags & ~(PK_FLAG_COUNT_FRAGS | PK_FLAG_FUSE_RESOLVE | PK_FLAG_DEFER_SHADE |
+                     PK_FLAG_TWO_LEVEL_BINS))
         return PK_ERR_INVALID_ARGUMENT;
+    if ((p->flags & PK_FLAG_TWO_LEVEL_BINS) &&
+        ((p->bin_size != 8 && p->bin_size != 16) || p->layers != 0 ||
+         (p->flags & PK_FLAG_FUSE_RESOLVE) ||
+         (p->schedule != PK_SCHED_LOAD_BALANCE && p->schedule != PK_SCHED_DIRECT_MAP)))
+        return PK_ERR_UNSUPPORTED;
     if ((p->flags & PK_FLAG_FUSE_RESOLVE) && (p->flags & PK_FLAG_DEFER_SHADE))
         return PK_ERR_INVALID_ARGUMENT;
     if (p->num_scenes < 1 || p->num_scenes > 65535) return PK_ERR_INVALID_ARGUMENT;
@@ -79,6 +88,14 @@ pk_status check_params(const pk_params *p, Frame &f) {
     f.nbx = p->bin_size ? (p->width + p->bin_size - 1) / p->bin_size : 1;
     f.nby = p->bin_size ? (p->height + p->bin_size - 1) / p->bin_size : 1;
     f.nbins_scene = (int64_t)f.nbx * f.nby;
+    if (p->flags & PK_FLAG_TWO_LEVEL_BINS) {
+        // the coarse bins follow each scene's fine bins
+        f.two_level = true;
+        f.nbins_f = f.nbins_scene;
+        f.nbx_c = (p->width + 4 * p->bin_size - 1) / (4 * p->bin_size);
+        f.nby_c = (p->height + 4 * p->bin_size - 1) / (4 * p->bin_size);
+        f.nbins_scene += (int64_t)f.nbx_c * f.nby_c;
+    }
     f.nbins_total = f.nbins_scene * p->num_scenes;
     if (f.nbins_total >= (int64_t)INT32_MAX) return PK_ERR_INVALID_ARGUMENT;
     f.npix = (int64_t)p->num_scenes * p->width * p->height;
@@ -174,6 +191,7 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.fb_mat = reinterpret_cast<uint32_t *>(b + L.fb_mat);
     w.fb_groups = f.fragbins ? f.fb_groups : 0;
     w.fb_rounds = f.fb_rounds;
+    w.two_level = f.two_level ? 1 : 0;
     return w;
 }
 
@@ -197,6 +215,10 @@ Geom geom(const pk_params *p, const pk_mesh *m, const Frame &f) {
     G.instanced = (p->num_scenes > 1) ? p->instanced : 0;
     G.items = f.items;
     G.nbins_total = f.nbins_total;
+    G.two_level = f.two_level ? 1 : 0;
+    G.nbins_f = (int32_t)f.nbins_f;
+    G.nbx_c = f.nbx_c;
+    G.nby_c = f.nby_c;
     return G;
 }
 

@@ -170,6 +170,9 @@ struct Geom {
     int32_t S, instanced;
     int64_t items;             // instanced ? S*T : T
     int64_t nbins_total;       // S * nbins_scene
+    // PK_FLAG_TWO_LEVEL_BINS: a scene's bins are its nbins_f fine bins (B px)
+    // followed by its coarse bins (4B px, nbx_c wide); nbins_scene counts both
+    int32_t two_level, nbins_f, nbx_c, nby_c;
 };
 
 // Snapped vertex of an indexed mesh (the Vertex Shader stage's output),
@@ -205,6 +208,7 @@ struct Ws {
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
     int32_t split;             // PK_SCHED_SPLIT: pairs per work item; 0 otherwise
+    int32_t two_level;         // PK_FLAG_TWO_LEVEL_BINS: keys always in `keys`
     // PK_SCHED_FRAGMENT_BINS: `pairs` holds the fragments instead, as
     // kFbPlanes planes of pair_capacity 16-byte entries; fb_mat [fb_groups]
     // [nbins] the per-workgroup fragment counts of each bin

@@ -25,6 +25,7 @@ PK_SHADE_GOURAUD, PK_SHADE_TEXTURED, PK_SHADE_DEFERRED, PK_SHADE_LIT = range(4)
 PK_FLAG_COUNT_FRAGS = 1
 PK_FLAG_FUSE_RESOLVE = 2
 PK_FLAG_DEFER_SHADE = 4
+PK_FLAG_TWO_LEVEL_BINS = 8
 
 SCHEDULES = {"load_balance": PK_SCHED_LOAD_BALANCE, "direct_map": PK_SCHED_DIRECT_MAP,
              "dynamic": PK_SCHED_DYNAMIC, "split": PK_SCHED_SPLIT,
@@ -191,6 +192,8 @@ class RenderConfig:
     # raster_shade() stops after the depth test and shade() resolves; frame()
     # calls both (lets a caller time or overlap the two passes)
     defer_shade: bool = False
+    # two bin levels: large triangles go to coarse bins of 4x the size
+    two_level: bool = False
 
 
 def _light_default():
@@ -283,7 +286,8 @@ class Renderer:
                              int(cfg.threads_per_bin), self.shading,
                              (PK_FLAG_COUNT_FRAGS if cfg.count_frags else 0)
                              | (PK_FLAG_FUSE_RESOLVE if cfg.fuse_resolve else 0)
-                             | (PK_FLAG_DEFER_SHADE if cfg.defer_shade else 0), self.S,
+                             | (PK_FLAG_DEFER_SHADE if cfg.defer_shade else 0)
+                             | (PK_FLAG_TWO_LEVEL_BINS if cfg.two_level else 0), self.S,
                              int(d.instanced), int(cfg.persistent_groups), int(cfg.split_size),
                              int(cfg.layers))
         self.mesh = d.mesh()

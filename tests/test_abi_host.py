@@ -62,7 +62,7 @@ def _mesh(**kw):
     dict(bin_size=-8), dict(schedule=5), dict(schedule=-1), dict(threads_per_bin=32),
     dict(split_size=-1), dict(schedule=3, flags=2), dict(layers=-1), dict(layers=9),
     dict(layers=2, flags=2),
-    dict(threads_per_bin=512), dict(shading=4), dict(flags=8), dict(flags=6), dict(num_scenes=0),
+    dict(threads_per_bin=512), dict(shading=4), dict(flags=16), dict(flags=6), dict(num_scenes=0),
     dict(instanced=2), dict(persistent_groups=-1)])
 def test_invalid_params_rejected_on_host(L, bad):
     p = _params(**bad)
@@ -267,3 +267,23 @@ def test_fragment_bins_restrictions_and_workspace(L):
         assert L.pk_workspace_bytes(C.byref(p), C.byref(m), 100) == want
     v = pk.BinView()
     assert L.pk_bin_lists(C.byref(p), C.byref(m), 1 << 20, C.byref(v)) == pk.PK_ERR_UNSUPPORTED
+
+
+def test_two_level_bins_workspace_and_restrictions(L):
+    """PK_FLAG_TWO_LEVEL_BINS: each scene's coarse bins (4x the size) follow
+    its fine bins in the counts, cursors and offsets; 8- or 16-px bins,
+    LOAD_BALANCE or DIRECT_MAP, opaque and not fused."""
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    m = _mesh(num_tris=1000, num_vertices=3000)
+    one = L.pk_workspace_bytes(C.byref(_params(width=100, height=70, bin_size=8)), C.byref(m), 0)
+    two = L.pk_workspace_bytes(C.byref(_params(width=100, height=70, bin_size=8, flags=8)),
+                               C.byref(m), 0)
+    nf, nc = 13 * 9, 4 * 3                  # fine 8-px bins, coarse 32-px bins
+    assert two - one == ((al(4 * (nf + nc)) - al(4 * nf)) * 2
+                         + al(4 * (nf + nc + 1)) - al(4 * (nf + 1)))
+    for bad in (dict(bin_size=32), dict(bin_size=0), dict(schedule=2), dict(schedule=3),
+                dict(flags=8 | 2), dict(layers=2)):
+        p = _params(**{"flags": 8, **bad})
+        p.flags |= 8
+        assert L.pk_setup(C.byref(p), C.byref(m), FAKE, None) in (pk.PK_ERR_UNSUPPORTED,
+                                                                   pk.PK_ERR_INVALID_ARGUMENT)
