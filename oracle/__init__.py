@@ -72,7 +72,12 @@ def _load():
                "orc_depth_keys": (C.c_int, [P, C.c_int64, C.c_int64, P, P, P]),
                "orc_resolve_rows": (C.c_int, [P, P, P, C.c_int32, C.c_int32]),
                "orc_render_oit": (C.c_int, [P, P, C.c_int32, P, P, P, P]),
-               "orc_backward": (C.c_int, [P, P, P, P, P, P])}
+               "orc_backward": (C.c_int, [P, P, P, P, P, P]),
+               "orc_reyes_halve": (None, [P, C.c_int, P, P]),
+               "orc_reyes_decide": (C.c_int, [P, P, C.c_int, C.c_int, C.c_float, C.c_int]),
+               "orc_reyes_split": (C.c_int64, [P, C.c_int64, P, C.c_int, C.c_int, C.c_float,
+                                               C.c_int, P, P, C.c_int64]),
+               "orc_reyes_dice": (None, [P, P, P, C.c_int64, C.c_int, P, P, P, P])}
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
             fn.restype, fn.argtypes = res, args
@@ -93,7 +98,8 @@ class using_library:
         _load()                      # make sure the real one is set up first
         lib = C.CDLL(self.path)
         for name in ("orc_vertices", "orc_setup", "orc_assign_bin", "orc_render", "orc_render_rows",
-                     "orc_depth_keys", "orc_resolve_rows", "orc_render_oit", "orc_backward"):
+                     "orc_depth_keys", "orc_resolve_rows", "orc_render_oit", "orc_backward",
+                     "orc_reyes_halve", "orc_reyes_decide", "orc_reyes_split", "orc_reyes_dice"):
             src, dst = getattr(_lib, name), getattr(lib, name)
             dst.restype, dst.argtypes = src.restype, src.argtypes
         _lib = lib
@@ -332,3 +338,77 @@ def backward(sc, primid, bary, grad):
             lib.orc_backward(C.byref(s), _ptr(pid), _ptr(ba), _ptr(g), _ptr(sub), _ptr(gt))
             gv[:, v0:v1] += sub
     return gv, (gt if tex is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# Reyes front end (Split and Dice of bicubic Bezier patches, Sec. 7.1)
+# ---------------------------------------------------------------------------
+def _mvp(mvp):
+    return None if mvp is None else np.ascontiguousarray(np.asarray(mvp, np.float32).reshape(16))
+
+
+def reyes_halve(cp, direction: int):
+    """Halves of one patch [16][3] at u = 1/2 (direction 0) or v = 1/2 (1)."""
+    lib = _load()
+    cp = np.ascontiguousarray(cp, np.float32).reshape(16, 3)
+    lo, hi = np.zeros((16, 3), np.float32), np.zeros((16, 3), np.float32)
+    lib.orc_reyes_halve(_ptr(cp), int(direction), _ptr(lo), _ptr(hi))
+    return lo, hi
+
+
+def reyes_decide(cp, mvp, width: int, height: int, dice_px: float, last: bool = False) -> int:
+    """0 drop, 1 dice, 2 split in u, 3 split in v (see orc_reyes_decide)."""
+    lib = _load()
+    cp = np.ascontiguousarray(cp, np.float32).reshape(16, 3)
+    m = _mvp(mvp)
+    return int(lib.orc_reyes_decide(_ptr(cp), _ptr(m), int(width), int(height),
+                                    float(dice_px), int(bool(last))))
+
+
+def reyes_split(patches, mvp, width: int, height: int, dice_px: float, max_depth: int):
+    """Breadth-first Split of patches [P][16][3]: (leaves [L][16][3], source
+    patch of each leaf [L]) in the order the rounds emit them."""
+    lib = _load()
+    pt = np.ascontiguousarray(patches, np.float32).reshape(-1, 16, 3)
+    m = _mvp(mvp)
+    cap = max(4 * len(pt), 16)
+    while True:
+        leaves = np.zeros((cap, 16, 3), np.float32)
+        src = np.zeros(cap, np.int32)
+        n = int(lib.orc_reyes_split(_ptr(pt), len(pt), _ptr(m), int(width), int(height),
+                                    float(dice_px), int(max_depth), _ptr(leaves), _ptr(src), cap))
+        if n < 0:
+            raise MemoryError("oracle split failed")
+        if n <= cap:
+            return leaves[:n].copy(), src[:n].copy()
+        cap = n
+
+
+def reyes_dice(leaves, src, patch_color, n: int):
+    """Dice every leaf into an (n+1) x (n+1) vertex grid: (pos [3][V], color
+    [3][V], normal [3][V], idx [2 n^2 L][3]) with V = L (n+1)^2."""
+    lib = _load()
+    lv = np.ascontiguousarray(leaves, np.float32).reshape(-1, 16, 3)
+    sr = np.ascontiguousarray(src, np.int32)
+    pc = np.ascontiguousarray(patch_color, np.float32).reshape(-1, 3)
+    L, m = len(lv), int(n) + 1
+    V, T = L * m * m, 2 * int(n) * int(n) * L
+    pos, col, nrm = (np.zeros((3, V), np.float32) for _ in range(3))
+    idx = np.zeros((T, 3), np.int32)
+    lib.orc_reyes_dice(_ptr(lv), _ptr(sr), _ptr(pc), L, int(n), _ptr(pos), _ptr(col), _ptr(nrm),
+                       _ptr(idx))
+    return pos, col, nrm, idx
+
+
+def reyes_scene(ps):
+    """The micropolygon scene a patch scene dices into: Split, then Dice, as
+    a one-scene indexed mesh with forward-lit shading (Shade's diffuse model)
+    that ``render`` draws.  ``ps`` carries width, height, mvp, patches
+    [P][16][3], patch_color [P][3], dice_px, max_depth, dice_n and lights."""
+    leaves, src = reyes_split(ps.patches, ps.mvp, ps.width, ps.height, ps.dice_px, ps.max_depth)
+    pos, col, nrm, idx = reyes_dice(leaves, src, ps.patch_color, ps.dice_n)
+    return SimpleNamespace(width=int(ps.width), height=int(ps.height), pos=pos, color=col, idx=idx,
+                           num_tris=len(idx), mvp=ps.mvp, num_scenes=1, scene_tri_off=None,
+                           scene_vtx_off=None, instanced=False, uv=None, normal=nrm, texture=None,
+                           lights=ps.lights, shading="lit", num_leaves=len(leaves),
+                           leaf_src=src)

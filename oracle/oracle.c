@@ -681,3 +681,216 @@ int orc_backward(const orc_scene *s, const int32_t *primid, const float *bary,
     }
     return 0;
 }
+
+/* ======================================================================== */
+/* Reyes front end: Split and Dice of bicubic Bezier patches.  The Reyes    */
+/* pipeline of Sec. 7.1 has Split as a self-loop stage with one output back  */
+/* to itself and one to Dice, and Dice turns a patch into micropolygons for  */
+/* Sample and Shade; Sec. 5.1 runs such a self-loop by launching the stage   */
+/* again until nothing is left.  The paper fixes no split test, split        */
+/* direction or dice rate.  Readings used here: breadth-first rounds; a      */
+/* patch is diced once the screen box of its control points is at most      */
+/* dice_px on both axes; otherwise it is halved by de Casteljau at 1/2 along */
+/* the parameter whose control polygon is longer on screen; an n x n dice    */
+/* grid with central-difference normals.                                     */
+/* ======================================================================== */
+
+/* a patch: 16 control points, row-major over (v, u): point 4*i + j has u
+ * index j and v index i; 3 float32 coordinates each (48 floats) */
+enum { ORC_CP = 48 };
+
+/* x + t (y - x), three rounded operations in this order */
+static float lerpf(float x, float y, float t) { return x + t * (y - x); }
+
+/* one cubic (a, b, c, d) at t by de Casteljau; also its two halves when
+ * asked (left = a, ab, abc, p; right = p, bcd, cd, d) */
+static float casteljau(float a, float b, float c, float d, float t, float *left, float *right)
+{
+    const float ab = lerpf(a, b, t), bc = lerpf(b, c, t), cd = lerpf(c, d, t);
+    const float abc = lerpf(ab, bc, t), bcd = lerpf(bc, cd, t);
+    const float p = lerpf(abc, bcd, t);
+    if (left) { left[0] = a; left[1] = ab; left[2] = abc; left[3] = p; }
+    if (right) { right[0] = p; right[1] = bcd; right[2] = cd; right[3] = d; }
+    return p;
+}
+
+/* Halve a patch at u = 1/2 (dir 0: every row is a cubic in u) or v = 1/2
+ * (dir 1: every column is a cubic in v). */
+void orc_reyes_halve(const float *cp, int dir, float *lo, float *hi)
+{
+    for (int a = 0; a < 4; ++a) {
+        for (int c = 0; c < 3; ++c) {
+            float in[4], l[4], h[4];
+            for (int k = 0; k < 4; ++k)
+                in[k] = dir == 0 ? cp[3 * (4 * a + k) + c] : cp[3 * (4 * k + a) + c];
+            casteljau(in[0], in[1], in[2], in[3], 0.5f, l, h);
+            for (int k = 0; k < 4; ++k) {
+                const int pt = dir == 0 ? 4 * a + k : 4 * k + a;
+                lo[3 * pt + c] = l[k];
+                hi[3 * pt + c] = h[k];
+            }
+        }
+    }
+}
+
+/* Screen position of a control point through the same transform as the
+ * vertex stage (each product rounded, sums left to right, one reciprocal of
+ * w; no matrix: the identity), without snapping; 0 when w <= 0 or a value
+ * is not finite. */
+static int screen_point(const float *mvp, int W, int H, const float *p, float *xs, float *ys)
+{
+    float c[4] = {p[0], p[1], p[2], 1.0f};
+    if (mvp) {
+        for (int r = 0; r < 4; ++r) {
+            float t = mvp[4 * r + 0] * p[0];
+            t = t + mvp[4 * r + 1] * p[1];
+            t = t + mvp[4 * r + 2] * p[2];
+            t = t + mvp[4 * r + 3];
+            c[r] = t;
+        }
+    }
+    if (!(isfinite(c[0]) && isfinite(c[1]) && isfinite(c[3]) && c[3] > 0.0f)) return 0;
+    const float iw = 1.0f / c[3];
+    *xs = (c[0] * iw + 1.0f) * (0.5f * (float)W);
+    *ys = (c[1] * iw + 1.0f) * (0.5f * (float)H);
+    return isfinite(*xs) && isfinite(*ys);
+}
+
+/* What Split does with one patch: 0 drop (a control point behind the eye or
+ * not finite, or the control points' screen bound outside the screen),
+ * 1 dice (bound at most dice_px on both axes, or the last round), 2 split in u,
+ * 3 split in v (the direction whose control polygon is longer on screen:
+ * the largest squared screen distance between the end points of a row,
+ * against that of a column; u on ties). */
+int orc_reyes_decide(const float *cp, const float *mvp, int W, int H, float dice_px, int last)
+{
+    float xs[16], ys[16];
+    for (int k = 0; k < 16; ++k)
+        if (!screen_point(mvp, W, H, cp + 3 * k, &xs[k], &ys[k])) return 0;
+    float x0 = xs[0], x1 = xs[0], y0 = ys[0], y1 = ys[0];
+    for (int k = 1; k < 16; ++k) {
+        x0 = fminf(x0, xs[k]); x1 = fmaxf(x1, xs[k]);
+        y0 = fminf(y0, ys[k]); y1 = fmaxf(y1, ys[k]);
+    }
+    if (x1 < 0.0f || x0 > (float)W || y1 < 0.0f || y0 > (float)H) return 0;
+    if ((x1 - x0 <= dice_px && y1 - y0 <= dice_px) || last) return 1;
+    float du = 0.0f, dv = 0.0f;
+    for (int a = 0; a < 4; ++a) {
+        const float ux = xs[4 * a + 3] - xs[4 * a], uy = ys[4 * a + 3] - ys[4 * a];
+        const float vx = xs[12 + a] - xs[a], vy = ys[12 + a] - ys[a];
+        du = fmaxf(du, ux * ux + uy * uy);
+        dv = fmaxf(dv, vx * vx + vy * vy);
+    }
+    return du >= dv ? 2 : 3;
+}
+
+/* Split: breadth-first rounds r = 0..max_depth.  Round 0 takes the input
+ * patches in order; every patch of round r is dropped, kept for Dice
+ * (appended to the leaves, in order) or halved, its two halves (lower
+ * parameter first) going in order to round r + 1; round max_depth dices
+ * whatever it holds.  Writes up to cap leaves (48 floats each) and their
+ * input patch numbers; returns the number of leaves (-1 when out of memory). */
+int64_t orc_reyes_split(const float *patches, int64_t np, const float *mvp, int W, int H,
+                        float dice_px, int max_depth, float *leaf_cp, int32_t *leaf_src,
+                        int64_t cap)
+{
+    int64_t qn = np, nleaf = 0;
+    float *q = malloc(sizeof(float) * ORC_CP * (size_t)(np > 0 ? np : 1));
+    int32_t *qs = malloc(sizeof(int32_t) * (size_t)(np > 0 ? np : 1));
+    if (!q || !qs) { free(q); free(qs); return -1; }
+    memcpy(q, patches, sizeof(float) * ORC_CP * (size_t)np);
+    for (int64_t i = 0; i < np; ++i) qs[i] = (int32_t)i;
+    for (int r = 0; r <= max_depth && qn > 0; ++r) {
+        int64_t nn = 0;
+        for (int64_t i = 0; i < qn; ++i)
+            if (orc_reyes_decide(q + ORC_CP * i, mvp, W, H, dice_px, r == max_depth) >= 2) nn += 2;
+        float *q2 = malloc(sizeof(float) * ORC_CP * (size_t)(nn > 0 ? nn : 1));
+        int32_t *qs2 = malloc(sizeof(int32_t) * (size_t)(nn > 0 ? nn : 1));
+        if (!q2 || !qs2) { free(q); free(qs); free(q2); free(qs2); return -1; }
+        int64_t k = 0;
+        for (int64_t i = 0; i < qn; ++i) {
+            const float *cp = q + ORC_CP * i;
+            const int d = orc_reyes_decide(cp, mvp, W, H, dice_px, r == max_depth);
+            if (d == 1) {
+                if (nleaf < cap) {
+                    memcpy(leaf_cp + ORC_CP * nleaf, cp, sizeof(float) * ORC_CP);
+                    leaf_src[nleaf] = qs[i];
+                }
+                ++nleaf;
+            } else if (d >= 2) {
+                orc_reyes_halve(cp, d - 2, q2 + ORC_CP * k, q2 + ORC_CP * (k + 1));
+                qs2[k] = qs2[k + 1] = qs[i];
+                k += 2;
+            }
+        }
+        free(q); free(qs);
+        q = q2; qs = qs2; qn = nn;
+    }
+    free(q); free(qs);
+    return nleaf;
+}
+
+/* Dice: leaf l becomes an (n+1) x (n+1) grid of vertices at u = j/n, v = i/n
+ * (every row of control points evaluated at u by de Casteljau, then the
+ * resulting column at v), vertex l (n+1)^2 + i (n+1) + j, with the patch's
+ * colour and the normal cross(Pu, Pv) of central differences of the grid
+ * (one-sided at the border); and 2 n^2 triangles, quad (i, j) giving
+ * (v00, v10, v11) and (v00, v11, v01) with v10 one step in u and v01 one in
+ * v, triangle l 2n^2 + 2(i n + j) + {0, 1}.  Planes are [3][V] with
+ * V = nl (n+1)^2. */
+void orc_reyes_dice(const float *leaf_cp, const int32_t *leaf_src, const float *patch_color,
+                    int64_t nl, int n, float *pos, float *color, float *normal, int32_t *idx)
+{
+    const int m = n + 1;
+    const int64_t V = nl * (int64_t)m * m;
+    float *g = malloc(sizeof(float) * 3 * (size_t)m * (size_t)m);
+    if (!g) return;
+    for (int64_t l = 0; l < nl; ++l) {
+        const float *cp = leaf_cp + ORC_CP * l;
+        for (int i = 0; i < m; ++i) {
+            const float v = (float)i / (float)n;
+            for (int j = 0; j < m; ++j) {
+                const float u = (float)j / (float)n;
+                for (int c = 0; c < 3; ++c) {
+                    float col[4];
+                    for (int a = 0; a < 4; ++a)
+                        col[a] = casteljau(cp[3 * (4 * a) + c], cp[3 * (4 * a + 1) + c],
+                                           cp[3 * (4 * a + 2) + c], cp[3 * (4 * a + 3) + c], u,
+                                           NULL, NULL);
+                    g[3 * (i * m + j) + c] = casteljau(col[0], col[1], col[2], col[3], v, NULL, NULL);
+                }
+            }
+        }
+        const int64_t vb = l * (int64_t)m * m;
+        for (int i = 0; i < m; ++i) {
+            for (int j = 0; j < m; ++j) {
+                const int jp = j < n ? j + 1 : n, jm = j > 0 ? j - 1 : 0;
+                const int ip = i < n ? i + 1 : n, im = i > 0 ? i - 1 : 0;
+                float pu[3], pv[3];
+                for (int c = 0; c < 3; ++c) {
+                    pu[c] = g[3 * (i * m + jp) + c] - g[3 * (i * m + jm) + c];
+                    pv[c] = g[3 * (ip * m + j) + c] - g[3 * (im * m + j) + c];
+                }
+                const int64_t vtx = vb + i * m + j;
+                for (int c = 0; c < 3; ++c) {
+                    pos[c * V + vtx] = g[3 * (i * m + j) + c];
+                    color[c * V + vtx] = patch_color[3 * leaf_src[l] + c];
+                }
+                normal[vtx] = pu[1] * pv[2] - pu[2] * pv[1];
+                normal[V + vtx] = pu[2] * pv[0] - pu[0] * pv[2];
+                normal[2 * V + vtx] = pu[0] * pv[1] - pu[1] * pv[0];
+            }
+        }
+        const int64_t tb = l * 2 * (int64_t)n * n;
+        for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < n; ++j) {
+                const int32_t v00 = (int32_t)(vb + i * m + j), v10 = v00 + 1;
+                const int32_t v01 = v00 + m, v11 = v01 + 1;
+                int32_t *t = idx + 3 * (tb + 2 * (i * n + j));
+                t[0] = v00; t[1] = v10; t[2] = v11;
+                t[3] = v00; t[4] = v11; t[5] = v01;
+            }
+        }
+    }
+    free(g);
+}

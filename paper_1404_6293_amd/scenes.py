@@ -20,6 +20,9 @@ generators below stand in for them by shape class:
 * ``batch``    -- many independent small scenes of uneven triangle counts.
 * ``diffgrid`` -- the grid mesh with per-vertex UVs and a texture, seen from
                   many viewpoints.
+* ``patches``  -- a bumpy sheet of bicubic Bezier patches seen at a grazing
+                  angle, for the Reyes front end (the paper's Bigguy and
+                  Teapot patch models are not available).
 
 All arrays are NumPy, float32 unless noted, with positions and per-vertex
 attributes stored as SoA planes ``[channels][V]``.  Every generator takes a
@@ -314,3 +317,60 @@ def diffgrid(seed: int = 5000, size: int = 512, num_views: int = 64, nx: int = 1
     return Scene(size, size, pos, color, idx, idx.shape[0], mvp=view_mvps(num_views),
                  num_scenes=num_views, instanced=True, uv=uv, texture=tex,
                  bin_size=bin_size, shading="textured", name=f"diffgrid{num_views}x{size}")
+
+
+# ---------------------------------------------------------------------------
+# patches: a bumpy surface of bicubic Bezier patches for the Reyes front end
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class PatchScene:
+    """Inputs of the Reyes front end: bicubic Bezier patches, each 16 control
+    points row-major over (v, u) (point 4i + j has u index j, v index i), a
+    colour per patch, one camera, the dice threshold and grid, and lights."""
+
+    width: int
+    height: int
+    patches: np.ndarray                  # [P][16][3] float32
+    patch_color: np.ndarray              # [P][3] float32
+    mvp: Optional[np.ndarray]            # [16] float32 row-major, None -> identity
+    dice_px: float = 16.0                # dice once the screen box is <= this on both axes
+    max_depth: int = 20                  # splits per patch at most
+    dice_n: int = 8                      # n x n quads per diced patch
+    lights: Optional[np.ndarray] = None  # [L][3] float32 unit vectors
+    name: str = ""
+
+    @property
+    def num_patches(self) -> int:
+        return int(self.patches.shape[0])
+
+
+def patches(seed: int = 7007, width: int = 1920, height: int = 1080, pa: int = 64,
+            pb: int = 32, dice_px: float = 16.0, dice_n: int = 8, max_depth: int = 20,
+            num_lights: int = 1, tilt_deg: float = -60.0, noise: float = 0.03) -> PatchScene:
+    """A pa x pb sheet of patches sharing their border control points (a C0
+    surface): the control net spans x in [-2.3, 2.3], y in [-1.3, 1.3] with
+    z = 0.1 sin(2pi(3u+p1)) sin(2pi(2v+p2)) plus N(0, noise^2) bumps per
+    control point, tilted about x so that it recedes from the camera (near
+    patches are many times larger on screen than far ones: uneven split
+    depths, as in the paper's Reyes scenes)."""
+    rng = np.random.default_rng(seed)
+    p1, p2 = rng.uniform(0.0, 1.0, size=2)
+    nu, nv = 3 * pa + 1, 3 * pb + 1
+    u = np.arange(nu, dtype=np.float64) / (nu - 1)
+    v = np.arange(nv, dtype=np.float64) / (nv - 1)
+    U, Vv = np.meshgrid(u, v)            # [nv][nu]
+    x = (2.0 * U - 1.0) * 2.3
+    y = (2.0 * Vv - 1.0) * 1.3
+    z = 0.1 * np.sin(2 * math.pi * (3 * U + p1)) * np.sin(2 * math.pi * (2 * Vv + p2))
+    z = z + noise * rng.standard_normal(z.shape)
+    net = np.stack([x, y, z], axis=-1)   # [nv][nu][3]
+    out = np.empty((pb, pa, 4, 4, 3), np.float64)
+    for b in range(pb):
+        for a in range(pa):
+            out[b, a] = net[3 * b:3 * b + 4, 3 * a:3 * a + 4]
+    color = rng.uniform(0.2, 1.0, size=(pa * pb, 3)).astype(np.float32)
+    mvp = (perspective(60.0, width / height, 0.1, 10.0) @ translate(0.0, 0.1, 2.0)
+           @ rot_x(tilt_deg))
+    return PatchScene(width, height, out.reshape(pa * pb, 16, 3).astype(np.float32), color,
+                      mvp.astype(np.float32).reshape(16), dice_px, max_depth, dice_n,
+                      lights(num_lights), name=f"patches{pa}x{pb}_{width}x{height}")

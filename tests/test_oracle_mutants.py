@@ -12,6 +12,7 @@ import pytest
 
 import bruteforce as bf
 import oracle
+import reyes_pins
 from paper_1404_6293_amd import scenes
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
@@ -47,6 +48,30 @@ MUTANTS = {
                            "if (key > list[j] || list[j] == ~0ull) { const uint64_t tmp = list[j];"),
     "oit_no_transmittance": ("T = T * (1.0f - a);", "T = T * 1.0f;"),
     "oit_weight_without_transmittance": ("const float w = T * a;", "const float w = a;"),
+    "reyes_halve_at_quarter": ("casteljau(in[0], in[1], in[2], in[3], 0.5f, l, h);",
+                               "casteljau(in[0], in[1], in[2], in[3], 0.25f, l, h);"),
+    "reyes_halves_swapped": ("lo[3 * pt + c] = l[k];\n                hi[3 * pt + c] = h[k];",
+                             "lo[3 * pt + c] = h[k];\n                hi[3 * pt + c] = l[k];"),
+    "reyes_casteljau_mid_term": ("const float abc = lerpf(ab, bc, t), bcd = lerpf(bc, cd, t);",
+                                 "const float abc = lerpf(ab, bc, t), bcd = lerpf(bc, bc, t);"),
+    "reyes_ties_split_v": ("return du >= dv ? 2 : 3;", "return du > dv ? 2 : 3;"),
+    "reyes_direction_by_box": ("return du >= dv ? 2 : 3;", "return x1 - x0 >= y1 - y0 ? 2 : 3;"),
+    "reyes_strict_dice_test": ("(x1 - x0 <= dice_px && y1 - y0 <= dice_px)",
+                               "(x1 - x0 < dice_px && y1 - y0 < dice_px)"),
+    "reyes_dice_test_either_axis": ("(x1 - x0 <= dice_px && y1 - y0 <= dice_px)",
+                                    "(x1 - x0 <= dice_px || y1 - y0 <= dice_px)"),
+    "reyes_no_offscreen_cull": ("if (x1 < 0.0f || x0 > (float)W || y1 < 0.0f || y0 > (float)H) return 0;", ""),
+    "reyes_last_round_drops": ("dice_px && y1 - y0 <= dice_px) || last) return 1;",
+                               "dice_px && y1 - y0 <= dice_px)) return 1;\n    if (last) return 0;"),
+    "reyes_no_w_cull": ("isfinite(c[3]) && c[3] > 0.0f)) return 0;", "isfinite(c[3]))) return 0;"),
+    "reyes_dice_uv_swapped": ("g[3 * (i * m + j) + c] = casteljau(col[0], col[1], col[2], col[3], v, NULL, NULL);",
+                              "g[3 * (i * m + j) + c] = casteljau(col[0], col[1], col[2], col[3], u, NULL, NULL);"),
+    "reyes_normal_flipped": ("normal[2 * V + vtx] = pu[0] * pv[1] - pu[1] * pv[0];",
+                             "normal[2 * V + vtx] = pu[1] * pv[0] - pu[0] * pv[1];"),
+    "reyes_one_sided_differences": ("const int jp = j < n ? j + 1 : n, jm = j > 0 ? j - 1 : 0;",
+                                    "const int jp = j < n ? j + 1 : n, jm = j;"),
+    "reyes_winding": ("t[0] = v00; t[1] = v10; t[2] = v11;", "t[0] = v00; t[1] = v11; t[2] = v10;"),
+    "reyes_second_triangle": ("t[3] = v00; t[4] = v11; t[5] = v01;", "t[3] = v10; t[4] = v11; t[5] = v01;"),
     "backward_weight": ("grad_vcolor[c * V + vid[k]] += (double)bp[k] * (double)G[c];",
                         "grad_vcolor[c * V + vid[k]] += (double)bp[2 - k] * (double)G[c];"),
 }
@@ -229,6 +254,8 @@ def _pins_fail() -> list:
                 return False
         return True
     check("oit", oit)
+    for name, fn in reyes_pins.PINS.items():
+        check(f"reyes_{name}", fn)
     return failed
 
 
