@@ -15,7 +15,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpk.so")
-SOURCES = ["pk_api.hip", "k_setup.hip", "k_raster.hip", "k_fragbin.hip", "k_backward.hip"]
+SOURCES = ["pk_api.hip", "k_setup.hip", "k_raster.hip", "k_fragbin.hip", "k_backward.hip",
+           "k_reyes.hip"]
 # atomic-throughput probes (include/pk_probe.h), a library of their own
 PROBE_SOURCES = ["probe_atomics.hip"]
 PROBE_LIB = os.path.join(HERE, "libpk_probe.so")

@@ -34,7 +34,8 @@ SHADINGS = {"gouraud": PK_SHADE_GOURAUD, "textured": PK_SHADE_TEXTURED,
             "deferred": PK_SHADE_DEFERRED, "lit": PK_SHADE_LIT}
 
 EXPORTS = ("pk_workspace_bytes", "pk_setup", "pk_assign_bin", "pk_raster_shade", "pk_shade",
-           "pk_backward", "pk_bin_lists", "pk_status_string", "pk_render_static")
+           "pk_backward", "pk_bin_lists", "pk_status_string", "pk_render_static",
+           "pk_reyes_workspace_bytes", "pk_reyes_split", "pk_reyes_dice")
 # size of the library's static workspace used by pk_render_static (pk.h)
 PK_STATIC_WORKSPACE_BYTES = 64 << 20
 
@@ -63,6 +64,15 @@ class Attribs(C.Structure):
     _fields_ = [("color", C.c_void_p), ("uv", C.c_void_p), ("normal", C.c_void_p),
                 ("texture", C.c_void_p), ("tex_w", C.c_int32), ("tex_h", C.c_int32),
                 ("lights", C.c_void_p), ("num_lights", C.c_int32), ("alpha", C.c_void_p)]
+
+
+class ReyesParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("dice_px", C.c_float),
+                ("max_depth", C.c_int32), ("dice_n", C.c_int32)]
+
+
+# most patches one Split round may queue (pk_reyes.h)
+PK_REYES_MAX_QUEUE = 1 << 28
 
 
 class BinView(C.Structure):
@@ -103,6 +113,12 @@ def lib():
         L.pk_bin_lists.argtypes = [P, P, P, P]
         L.pk_render_static.restype = C.c_int
         L.pk_render_static.argtypes = [P, P, P, P, P, P]
+        L.pk_reyes_workspace_bytes.restype = C.c_size_t
+        L.pk_reyes_workspace_bytes.argtypes = [P, C.c_int64, C.c_int64]
+        L.pk_reyes_split.restype = C.c_int
+        L.pk_reyes_split.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P, P, C.c_int64, P, P]
+        L.pk_reyes_dice.restype = C.c_int
+        L.pk_reyes_dice.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, P, P, P, P]
         L.pk_status_string.restype = C.c_char_p
         L.pk_status_string.argtypes = [C.c_int]
         _lib = L
@@ -165,6 +181,28 @@ def pk_bin_lists(params: Params, mesh: Mesh, ws: int) -> BinView:
     v = BinView()
     _check("pk_bin_lists", lib().pk_bin_lists(_ref(params), _ref(mesh), ws, C.byref(v)))
     return v
+
+
+# --- the Reyes front end (include/pk_reyes.h) ---------------------------
+def pk_reyes_workspace_bytes(params: ReyesParams, num_patches: int, queue_capacity: int) -> int:
+    return int(lib().pk_reyes_workspace_bytes(C.byref(params), int(num_patches),
+                                              int(queue_capacity)))
+
+
+def pk_reyes_split(params: ReyesParams, patches: int, num_patches: int, mvp: Optional[int],
+                   ws: int, queue_capacity: int, leaves: Optional[int], leaf_src: Optional[int],
+                   leaf_capacity: int, counts: int, stream: int = 0):
+    _check("pk_reyes_split", lib().pk_reyes_split(_ref(params), patches, int(num_patches), mvp, ws,
+                                                  int(queue_capacity), leaves, leaf_src,
+                                                  int(leaf_capacity), counts, stream))
+
+
+def pk_reyes_dice(params: ReyesParams, leaves: int, leaf_src: int, num_leaves: int,
+                  patch_color: int, num_patches: int, pos: int, color: int, normal: int,
+                  indices: int, stream: int = 0):
+    _check("pk_reyes_dice", lib().pk_reyes_dice(_ref(params), leaves, leaf_src, int(num_leaves),
+                                                patch_color, int(num_patches), pos, color, normal,
+                                                indices, stream))
 
 
 # --- convenience layer over torch device memory ---------------------------
@@ -423,3 +461,146 @@ class Renderer:
         pk_backward(self.params, self.mesh, self.attribs, _ptr(self.out_primid),
                     _ptr(self.out_bary), _ptr(grad_color), _ptr(grad_vcolor), _ptr(grad_tex),
                     _stream())
+
+
+class Reyes:
+    """The Reyes pipeline of a patch scene on the GPU (Sec. 7.1): Split and
+    Dice (include/pk_reyes.h), then Sample and Shade by the binned
+    rasterizer drawing the diced micropolygons with forward-lit diffuse
+    shading.
+
+    ``split()`` enqueues every Split round; ``leaves()`` reads the leaf count
+    (one device-to-host read, the host's check that the self-loop drained)
+    and grows the queue or leaf buffer and splits again when they were too
+    small; ``dice()`` enqueues Dice; ``render()`` runs the whole frame.
+    ``ps`` carries width, height, patches [P][16][3], patch_color [P][3],
+    mvp [16] (or None), dice_px, max_depth, dice_n and lights.
+    """
+
+    def __init__(self, ps, cfg: Optional[RenderConfig] = None, device: str = "cuda",
+                 queue_capacity: Optional[int] = None, leaf_capacity: Optional[int] = None):
+        import torch
+        lib()
+        self.torch = torch
+        dev = torch.device(device)
+        self.device = dev
+        self.cfg = cfg if cfg is not None else RenderConfig(bin_size=16)
+        self.W, self.H = int(ps.width), int(ps.height)
+        f32 = torch.float32
+        self.patches = torch.from_numpy(np.ascontiguousarray(
+            np.asarray(ps.patches, np.float32).reshape(-1, 16, 3))).to(dev)
+        self.num_patches = int(self.patches.shape[0])
+        self.patch_color = torch.from_numpy(np.ascontiguousarray(
+            np.asarray(ps.patch_color, np.float32).reshape(-1, 3))).to(dev)
+        self.mvp = (None if ps.mvp is None else torch.from_numpy(np.ascontiguousarray(
+            np.asarray(ps.mvp, np.float32).reshape(16))).to(dev))
+        lights = ps.lights if getattr(ps, "lights", None) is not None else _light_default()
+        self.lights = np.asarray(lights, np.float64).astype(np.float32).reshape(-1, 3)
+        self.params = ReyesParams(self.W, self.H, float(ps.dice_px), int(ps.max_depth),
+                                  int(ps.dice_n))
+        self.counts = torch.zeros(4, dtype=torch.int64, device=dev)
+        P = max(self.num_patches, 1)
+        self._alloc_queue(queue_capacity if queue_capacity is not None else 8 * P + 1024)
+        self._alloc_leaves(leaf_capacity if leaf_capacity is not None else 8 * P + 1024)
+        self.num_leaves = None
+        self._mesh_leaves = None
+        self.renderer = None
+        del f32
+
+    def _alloc_queue(self, cap: int):
+        nbytes = pk_reyes_workspace_bytes(self.params, self.num_patches, cap)
+        if nbytes == 0:
+            raise PkError("pk_reyes_workspace_bytes", PK_ERR_INVALID_ARGUMENT,
+                          "invalid parameters")
+        self.queue_capacity = int(cap)
+        self.ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+
+    def _alloc_leaves(self, cap: int):
+        self.leaf_capacity = int(cap)
+        self.leaf_cp = self.torch.empty((max(cap, 1), 16, 3), dtype=self.torch.float32,
+                                        device=self.device)
+        self.leaf_src = self.torch.empty(max(cap, 1), dtype=self.torch.int32, device=self.device)
+
+    def split(self):
+        """Enqueue every Split round; no synchronization."""
+        pk_reyes_split(self.params, self.patches.data_ptr(), self.num_patches, _ptr(self.mvp),
+                       self.ws.data_ptr(), self.queue_capacity, self.leaf_cp.data_ptr(),
+                       self.leaf_src.data_ptr(), self.leaf_capacity, self.counts.data_ptr(),
+                       _stream())
+
+    def read_counts(self):
+        """(leaves, largest queue, patches visited, overflow) of the last split."""
+        return tuple(int(x) for x in self.counts.cpu().tolist())
+
+    def leaves(self) -> int:
+        """Number of leaves of the last split(), after growing the buffers and
+        splitting again until both the queue and the leaf list were large
+        enough."""
+        for _ in range(64):
+            nl, need, _, overflow = self.read_counts()
+            if overflow:
+                self._alloc_queue(max(int(need * 1.25) + 1024, 2 * self.queue_capacity))
+            elif nl > self.leaf_capacity:
+                self._alloc_leaves(int(nl * 1.25) + 1024)
+            else:
+                self.num_leaves = nl
+                return nl
+            self.split()
+        raise PkError("pk_reyes_split", PK_ERR_CAPACITY, "queue kept overflowing")
+
+    def _alloc_mesh(self, nl: int):
+        torch = self.torch
+        n = int(self.params.dice_n)
+        V, T = nl * (n + 1) ** 2, 2 * n * n * nl
+        f32 = torch.float32
+        self.pos = torch.empty((3, V), dtype=f32, device=self.device)
+        self.color = torch.empty((3, V), dtype=f32, device=self.device)
+        self.normal = torch.empty((3, V), dtype=f32, device=self.device)
+        self.idx = torch.empty((T, 3), dtype=torch.int32, device=self.device)
+        self._mesh_leaves = nl
+        self.renderer = None
+
+    def dice(self, nl: Optional[int] = None):
+        """Enqueue Dice of the first ``nl`` leaves (default: the last count)."""
+        nl = self.num_leaves if nl is None else int(nl)
+        if self._mesh_leaves != nl:
+            self._alloc_mesh(nl)
+        pk_reyes_dice(self.params, self.leaf_cp.data_ptr(), self.leaf_src.data_ptr(), nl,
+                      self.patch_color.data_ptr(), self.num_patches, self.pos.data_ptr(),
+                      self.color.data_ptr(), self.normal.data_ptr(), self.idx.data_ptr(),
+                      _stream())
+
+    def mesh_scene(self):
+        """The diced micropolygons as a one-scene indexed, forward-lit scene
+        (device tensors, used in place)."""
+        from types import SimpleNamespace
+        return SimpleNamespace(width=self.W, height=self.H, pos=self.pos, color=self.color,
+                               idx=self.idx, num_tris=int(self.idx.shape[0]),
+                               mvp=None if self.mvp is None else self.mvp.reshape(1, 16),
+                               num_scenes=1, scene_tri_off=None, scene_vtx_off=None,
+                               instanced=False, uv=None, normal=self.normal, texture=None,
+                               lights=self.lights, shading="lit")
+
+    def sample_shade(self) -> "Renderer":
+        """The rasterizer for the current dice buffers (built once per leaf
+        count); its frame() runs Sample and Shade."""
+        if self.renderer is None:
+            self.renderer = Renderer(self.mesh_scene(), self.cfg, device=str(self.device))
+        return self.renderer
+
+    def frame(self):
+        """One whole frame: Split, the leaf-count read, Dice, Sample and
+        Shade (the rasterizer's pair capacity is checked by render())."""
+        self.split()
+        nl = self.leaves()
+        self.dice(nl)
+        self.sample_shade().frame()
+
+    def render(self) -> dict:
+        self.split()
+        nl = self.leaves()
+        self.dice(nl)
+        out = self.sample_shade().render()
+        out = dict(out)
+        out["num_leaves"] = nl
+        return out

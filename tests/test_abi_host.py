@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
-every function include/pk.h declares, validates arguments before it enqueues
+every function include/pk.h and include/pk_reyes.h declare, validates arguments before it enqueues
 anything, and computes the workspace size and status strings on the host."""
 import ctypes as C
 import os
@@ -10,7 +10,8 @@ import pytest
 from paper_1404_6293_amd import pk
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pk.h")
+# the headers of libpk (include/pk_probe.h belongs to the probe library)
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pk.h", "pk_reyes.h")]
 
 
 @pytest.fixture(scope="module")
@@ -22,7 +23,7 @@ def L():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pk_\w+)\s*\(", src, flags=re.M)))
 
@@ -287,3 +288,57 @@ def test_two_level_bins_workspace_and_restrictions(L):
         p.flags |= 8
         assert L.pk_setup(C.byref(p), C.byref(m), FAKE, None) in (pk.PK_ERR_UNSUPPORTED,
                                                                    pk.PK_ERR_INVALID_ARGUMENT)
+
+
+# ---------------------------------------------------------------------------
+# Reyes front end (include/pk_reyes.h): host-side validation and sizes
+# ---------------------------------------------------------------------------
+def _rp(**kw):
+    d = dict(width=64, height=48, dice_px=8.0, max_depth=10, dice_n=4)
+    d.update(kw)
+    return pk.ReyesParams(**d)
+
+
+def test_reyes_workspace_bytes(L):
+    f = L.pk_reyes_workspace_bytes
+    base = f(C.byref(_rp()), 0, 0)
+    assert base > 0 and base % 256 == 0
+    # two queues of 192-byte patches and int32 sources, a decision byte per patch
+    big = f(C.byref(_rp()), 1000, 1 << 16)
+    assert big - base >= 2 * (1 << 16) * (192 + 4) + (1 << 16)
+    # the decision bytes cover the input round too
+    assert f(C.byref(_rp()), 1 << 20, 16) >= f(C.byref(_rp()), 0, 16) + (1 << 20) - 256
+    for bad in (dict(width=0), dict(height=8193), dict(dice_px=0.0), dict(dice_px=float("nan")),
+                dict(dice_px=float("inf")), dict(max_depth=-1), dict(max_depth=31),
+                dict(dice_n=0), dict(dice_n=17)):
+        assert f(C.byref(_rp(**bad)), 10, 10) == 0, bad
+    assert f(C.byref(_rp()), -1, 10) == 0
+    assert f(C.byref(_rp()), 10, pk.PK_REYES_MAX_QUEUE + 1) == 0
+    assert f(None, 10, 10) == 0
+
+
+def test_reyes_split_and_dice_validate_before_launch(L):
+    ok = _rp()
+    bad = _rp(dice_n=0)
+    cnt = FAKE
+    S = L.pk_reyes_split
+    assert S(C.byref(bad), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), None, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, None, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10010, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # ws alignment
+    assert S(C.byref(ok), FAKE + 4, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # patches alignment
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, None, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, None, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, -1, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, -1, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, -1, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    D = L.pk_reyes_dice
+    assert D(C.byref(bad), FAKE, FAKE, 4, FAKE, 4, FAKE, FAKE, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert D(C.byref(ok), FAKE, FAKE, -1, FAKE, 4, FAKE, FAKE, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert D(C.byref(ok), None, FAKE, 4, FAKE, 4, FAKE, FAKE, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert D(C.byref(ok), FAKE, FAKE, 4, FAKE, 4, FAKE, None, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # V = L (n+1)^2 must stay below 2^31 (mesh vertex numbers are int32)
+    assert D(C.byref(_rp(dice_n=16)), FAKE, FAKE, (1 << 31) // 289 + 1, FAKE, 4, FAKE, FAKE,
+             FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # nothing to dice: nothing enqueued, OK
+    assert D(C.byref(ok), None, None, 0, None, 0, None, None, None, None, None) == pk.PK_OK
