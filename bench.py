@@ -503,6 +503,85 @@ def bench_two_level(reps: int = 5) -> dict:
             "frames": out}
 
 
+def bench_reyes(reps: int = 10) -> dict:
+    """The Reyes pipeline (Sec. 7.1) on a 2048-patch bumpy sheet at 1920x1080
+    (dice at 16 px, 8 x 8 grids, one light): Split (every round, one stream),
+    Dice, Sample + Shade of the diced micropolygons under a few rasterizer
+    configurations, and the whole frame including the host's read of the
+    leaf count; medians of HIP-event timings (ms).  Split's rate counts the
+    patches visited over all rounds; the oracle's Split + Dice on the host
+    is timed beside it."""
+    import time
+    import torch
+    import oracle
+    from paper_1404_6293_amd import pk, scenes
+    ps = scenes.patches()
+    r = pk.Reyes(ps)
+    r.split()
+    nl = r.leaves()
+    r.dice(nl)
+    torch.cuda.synchronize()
+    _, largest, visits, _ = r.read_counts()
+    split_ms = _median_ms(torch, r.split, reps)
+    # the same rounds replayed from a HIP graph (launch costs only)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        r.split()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        r.split()
+    g.replay()
+    torch.cuda.synchronize()
+    graph_ok = r.read_counts()[0] == nl
+    split_graph_ms = _median_ms(torch, g.replay, reps)
+    del g
+    dice_ms = _median_ms(torch, lambda: r.dice(nl), reps)
+    tris = int(r.idx.shape[0])
+    raster = {}
+    best, best_ms = None, float("inf")
+    for name, cfg in (("B0", pk.RenderConfig(bin_size=0, want_bary=False)),
+                      ("B8/direct_map", pk.RenderConfig(bin_size=8, want_bary=False)),
+                      ("B16/direct_map", pk.RenderConfig(bin_size=16, want_bary=False)),
+                      ("B32/fragment_bins", pk.RenderConfig(bin_size=32, schedule="fragment_bins",
+                                                            want_bary=False))):
+        r.cfg, r.renderer = cfg, None
+        rr = r.sample_shade()
+        rr.render()
+        torch.cuda.synchronize()
+        raster[name] = round(_median_ms(torch, rr.frame, reps), 4)
+        if raster[name] < best_ms:
+            best, best_ms = cfg, raster[name]
+    r.cfg, r.renderer = best, None
+    r.render()
+    torch.cuda.synchronize()
+
+    def whole():
+        r.frame()
+    frame_ms = _median_ms(torch, whole, reps)
+    t0 = time.perf_counter()
+    lv, src = oracle.reyes_split(ps.patches, ps.mvp, ps.width, ps.height, ps.dice_px,
+                                 ps.max_depth)
+    t1 = time.perf_counter()
+    oracle.reyes_dice(lv, src, ps.patch_color, ps.dice_n)
+    t2 = time.perf_counter()
+    return {"workload": f"{ps.name}: {ps.num_patches} bicubic patches, dice at {ps.dice_px} px "
+                        f"into {ps.dice_n}x{ps.dice_n} grids, forward-lit, 1 light",
+            "leaves": nl, "micropolygons": tris, "largest_queue": largest,
+            "patches_visited": visits, "rounds_enqueued": ps.max_depth + 1,
+            "split_ms": round(split_ms, 4),
+            "split_mpatches_per_s": round(visits / (split_ms * 1e-3) / 1e6, 1),
+            "split_graph_ms": round(split_graph_ms, 4), "split_graph_same_leaves": graph_ok,
+            "dice_ms": round(dice_ms, 4),
+            "dice_mtris_per_s": round(tris / (dice_ms * 1e-3) / 1e6, 1),
+            "sample_shade_ms": raster, "frame_ms": round(frame_ms, 4),
+            "frame_config": {"bin_size": best.bin_size, "schedule": best.schedule},
+            "cpu_oracle": {"split_s": round(t1 - t0, 3), "dice_s": round(t2 - t1, 3),
+                           "split_mpatches_per_s": round(visits / (t1 - t0) / 1e6, 2),
+                           "threads": 1}}
+
+
 def bench_ablation(reps: int = 5) -> dict:
     """The schedule ablation of Sec. 7.2 on grid1080: whole-screen bins (the
     unbinned baseline) and every bin size with each schedule, the resolve in
@@ -673,7 +752,13 @@ def main():
     ap.add_argument("--transparency", type=int, default=-1, metavar="K",
                     help="only time the transparency frame of batch256 with K layers "
                          "(bin size --bin, default 16; 20 frames) and print its JSON")
+    ap.add_argument("--reyes", action="store_true",
+                    help="only run the Reyes pipeline's timings and print their JSON")
     args = ap.parse_args()
+    if args.reyes:
+        print(json.dumps(bench_reyes(reps=max(args.steps, 3) if args.steps < 400 else 10)),
+              flush=True)
+        return
     if args.transparency >= 0:
         print(json.dumps(bench_transparency(reps=20, bins=(16 if args.bin < 0 else args.bin,),
                                             layers=(args.transparency,))), flush=True)
@@ -896,6 +981,8 @@ def main():
         out["lights"] = bench_lights()
         print("bench: two bin levels", file=sys.stderr, flush=True)
         out["two_level"] = bench_two_level()
+        print("bench: reyes", file=sys.stderr, flush=True)
+        out["reyes"] = bench_reyes()
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(sc)

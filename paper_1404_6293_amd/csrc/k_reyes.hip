@@ -2,21 +2,24 @@
 // and Dice of bicubic Bezier patches.
 //
 // Split is the self-loop stage of the Reyes pipeline (Sec. 7.1), run as in
-// Sec. 5.1 by launching it once per round; every round is two kernels over
-// the round's queue, whose length they read from device memory:
-//   k_split_decide  one thread per patch: the split test (drop, dice, split
-//                   in u or v), a decision byte, and per-workgroup counts of
-//                   children and leaves over a contiguous chunk;
-//   k_split_write   every workgroup sums the counts of the chunks before its
-//                   own (prefix sums instead of atomically appended queues,
-//                   as the bins of Sec. 6), scans its chunk tile by tile and
-//                   writes the halves of split patches to the next round's
-//                   queue and the leaves to the leaf list, both in queue
-//                   order; workgroup 0 also publishes the next round's queue
-//                   length and the running leaf count.
-// The queue order therefore equals a breadth-first traversal with halves in
-// parameter order, independent of timing, and all rounds are enqueued at
-// once (a round whose queue is empty exits at once).
+// Sec. 5.1 by launching it once per round.  A round's queue is cut into
+// fixed chunks; one workgroup per chunk.  The decision of every queued patch
+// (drop, dice, split in u or v) and the per-chunk counts of children and
+// leaves are known before the round's kernel starts: the kernel that wrote a
+// patch into the queue also decided it.  k_split_round then
+//   - sums the counts of the chunks before its own (prefix sums instead of
+//     atomically appended queues, as the bins of Sec. 6),
+//   - scans its chunk tile by tile and writes the two halves of each split
+//     patch to the next queue and each diced patch to the leaf list, both
+//     in queue order,
+//   - decides the halves it wrote (for the next round) and adds their
+//     counts to the next round's per-chunk counts,
+//   - (workgroup 0) publishes the next queue length and the leaf count.
+// k_split_first decides the input patches.  The queue order is therefore a
+// breadth-first traversal with halves in parameter order, independent of
+// timing; every round is one kernel, all enqueued at once, reading the
+// round's length from device memory (a round whose queue is empty exits at
+// once).
 //
 // Dice (Sec. 7.1) evaluates an (n+1) x (n+1) grid per leaf in LDS (one
 // workgroup of one wave per leaf) and writes SoA vertex planes, normals from
@@ -31,7 +34,7 @@ namespace pk {
 namespace {
 
 constexpr int kRT = 256;           // threads of a Split workgroup
-constexpr int kRGroups = 1024;     // Split workgroups (contiguous chunks) per round
+constexpr int kMaxChunks = 1024;   // chunks (workgroups) of one round at most
 constexpr int kPatch = 48;         // floats per patch: 16 points x 3
 constexpr int kMaxDepth = 30;
 constexpr int kDiceMaxN = 16;
@@ -45,8 +48,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct SplitWs {
     int64_t *ctl;
-    int32_t *agg;                  // [kRGroups][2]: children, leaves of each chunk
-    uint8_t *dec;                  // decision of each patch of the round
+    int32_t *agg[3];               // [kMaxChunks][2]: children, leaves decided per chunk
+    uint8_t *dec[2];               // decision of each patch of a round
     float *q[2];                   // queues [cap][48]
     int32_t *qsrc[2];              // their source patch numbers
 };
@@ -55,23 +58,31 @@ struct SplitWs {
 size_t split_layout(int64_t np, int64_t cap, char *base, SplitWs *w) {
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off += align_up(bytes); return base ? base + o : nullptr; };
+    const size_t nd = (size_t)std::max(np, cap);
     char *ctl = take(sizeof(int64_t) * kCtlWords);
-    char *agg = take(sizeof(int32_t) * 2 * kRGroups);
-    char *dec = take((size_t)std::max(np, cap));
-    char *q0 = take(sizeof(float) * kPatch * (size_t)cap);
-    char *q1 = take(sizeof(float) * kPatch * (size_t)cap);
-    char *s0 = take(sizeof(int32_t) * (size_t)cap);
-    char *s1 = take(sizeof(int32_t) * (size_t)cap);
+    char *agg[3], *dec[2], *q[2], *qs[2];
+    for (auto &x : agg) x = take(sizeof(int32_t) * 2 * kMaxChunks);
+    for (auto &x : dec) x = take(nd);
+    for (auto &x : q) x = take(sizeof(float) * kPatch * (size_t)cap);
+    for (auto &x : qs) x = take(sizeof(int32_t) * (size_t)cap);
     if (w) {
         w->ctl = (int64_t *)ctl;
-        w->agg = (int32_t *)agg;
-        w->dec = (uint8_t *)dec;
-        w->q[0] = (float *)q0;
-        w->q[1] = (float *)q1;
-        w->qsrc[0] = (int32_t *)s0;
-        w->qsrc[1] = (int32_t *)s1;
+        for (int k = 0; k < 3; ++k) w->agg[k] = (int32_t *)agg[k];
+        for (int k = 0; k < 2; ++k) {
+            w->dec[k] = (uint8_t *)dec[k];
+            w->q[k] = (float *)q[k];
+            w->qsrc[k] = (int32_t *)qs[k];
+        }
     }
     return off;
+}
+
+// Patches per chunk: a whole number of 64-patch tiles, and few enough
+// chunks for the largest round (the input or a full queue).
+int64_t chunk_size(int64_t np, int64_t cap) {
+    const int64_t n = std::max<int64_t>(std::max(np, cap), 1);
+    const int64_t c = (n + kMaxChunks - 1) / kMaxChunks;
+    return std::max<int64_t>(64, (c + 63) / 64 * 64);
 }
 
 struct SplitArgs {
@@ -80,6 +91,7 @@ struct SplitArgs {
     float W, H, hw, hh, dice;
     int max_depth;
     int64_t cap;
+    int64_t chunk;
     float *leaves;
     int32_t *leaf_src;
     int64_t leaf_cap;
@@ -119,63 +131,13 @@ __device__ inline bool ctrl_screen(const float (&m)[16], bool has_m, float hw, f
     return isfinite(xs) && isfinite(ys);
 }
 
-// 0 drop, 1 dice, 2 split in u, 3 split in v (include/pk_reyes.h).
-__device__ inline int split_decide(const float (&cp)[kPatch], const float (&m)[16], bool has_m,
-                                   const SplitArgs &a, bool last) {
-    float xs[16], ys[16];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 16; ++k)
-        ok = ctrl_screen(m, has_m, a.hw, a.hh, cp[3 * k], cp[3 * k + 1], cp[3 * k + 2], xs[k], ys[k]) && ok;
-    if (!ok) return 0;
-    float x0 = xs[0], x1 = xs[0], y0 = ys[0], y1 = ys[0];
-#pragma unroll
-    for (int k = 1; k < 16; ++k) {
-        x0 = fminf(x0, xs[k]); x1 = fmaxf(x1, xs[k]);
-        y0 = fminf(y0, ys[k]); y1 = fmaxf(y1, ys[k]);
-    }
-    if (x1 < 0.0f || x0 > a.W || y1 < 0.0f || y0 > a.H) return 0;
-    if ((x1 - x0 <= a.dice && y1 - y0 <= a.dice) || last) return 1;
-    float du = 0.0f, dv = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float ux = xs[4 * r + 3] - xs[4 * r], uy = ys[4 * r + 3] - ys[4 * r];
-        const float vx = xs[12 + r] - xs[r], vy = ys[12 + r] - ys[r];
-        du = fmaxf(du, ux * ux + uy * uy);
-        dv = fmaxf(dv, vx * vx + vy * vy);
-    }
-    return du >= dv ? 2 : 3;
-}
-
 __device__ inline float lerp_rn(float x, float y, float t) { return x + t * (y - x); }
 
-// de Casteljau of one cubic at t: the point, and optionally both halves.
+// de Casteljau of one cubic at t.
 __device__ inline float cubic_at(float a, float b, float c, float d, float t) {
     const float ab = lerp_rn(a, b, t), bc = lerp_rn(b, c, t), cd = lerp_rn(c, d, t);
     const float abc = lerp_rn(ab, bc, t), bcd = lerp_rn(bc, cd, t);
     return lerp_rn(abc, bcd, t);
-}
-
-// Halves of a patch at u = 1/2 (DIR 0: every row is a cubic in u) or
-// v = 1/2 (DIR 1: every column is a cubic in v).
-template <int DIR>
-__device__ inline void halve(const float (&cp)[kPatch], float (&lo)[kPatch], float (&hi)[kPatch]) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int p0 = DIR == 0 ? 4 * r : r, st = DIR == 0 ? 1 : 4;
-            const float a = cp[3 * p0 + c], b = cp[3 * (p0 + st) + c];
-            const float cc = cp[3 * (p0 + 2 * st) + c], d = cp[3 * (p0 + 3 * st) + c];
-            const float ab = lerp_rn(a, b, 0.5f), bc = lerp_rn(b, cc, 0.5f), cd = lerp_rn(cc, d, 0.5f);
-            const float abc = lerp_rn(ab, bc, 0.5f), bcd = lerp_rn(bc, cd, 0.5f);
-            const float p = lerp_rn(abc, bcd, 0.5f);
-            lo[3 * p0 + c] = a;                lo[3 * (p0 + st) + c] = ab;
-            lo[3 * (p0 + 2 * st) + c] = abc;   lo[3 * (p0 + 3 * st) + c] = p;
-            hi[3 * p0 + c] = p;                hi[3 * (p0 + st) + c] = bcd;
-            hi[3 * (p0 + 2 * st) + c] = cd;    hi[3 * (p0 + 3 * st) + c] = d;
-        }
-    }
 }
 
 __device__ inline void load_matrix(const float *mvp, float (&m)[16]) {
@@ -183,22 +145,14 @@ __device__ inline void load_matrix(const float *mvp, float (&m)[16]) {
     for (int k = 0; k < 16; ++k) m[k] = mvp ? mvp[k] : 0.0f;
 }
 
-// Patches of round r and the chunk [begin, end) of this workgroup.
+// Patches of round r (rounds after the first never exceed the queue).
 __device__ inline int64_t round_size(const SplitArgs &a, int r) {
     const int64_t n = a.w.ctl[kCtlN + r];
     return r == 0 ? n : (n < a.cap ? n : a.cap);
 }
 
-__device__ inline void chunk_of(int64_t n, int64_t &begin, int64_t &end) {
-    int64_t chunk = (n + kRGroups - 1) / kRGroups;
-    chunk = (chunk + kRT - 1) / kRT * kRT;
-    begin = (int64_t)blockIdx.x * chunk;
-    end = begin + chunk < n ? begin + chunk : n;
-    if (begin > n) begin = n;
-}
-
-__global__ void k_split_init(SplitArgs a, int64_t np) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ __launch_bounds__(kRT) void k_split_init(SplitArgs a, int64_t np) {
+    if (threadIdx.x == 0) {
         a.w.ctl[kCtlN] = np;
         a.w.ctl[kCtlLeaf] = 0;
         a.counts[0] = 0;
@@ -206,49 +160,127 @@ __global__ void k_split_init(SplitArgs a, int64_t np) {
         a.counts[2] = 0;
         a.counts[3] = 0;
     }
+    // round 0 adds the counts of the halves it decides into agg[1]
+    for (int k = threadIdx.x; k < 2 * kMaxChunks; k += kRT) a.w.agg[1][k] = 0;
 }
 
-__global__ __launch_bounds__(kRT) void k_split_decide(SplitArgs a, int r, const float *in) {
+// ---- quads: four lanes per patch, lane a holding row a -------------------
+constexpr int kTile = 64;          // patches per tile of a Split workgroup (kRT / 4)
+
+__device__ inline float quad_min(float v) {
+    v = fminf(v, __shfl_xor(v, 1));
+    return fminf(v, __shfl_xor(v, 2));
+}
+
+__device__ inline float quad_max(float v) {
+    v = fmaxf(v, __shfl_xor(v, 1));
+    return fmaxf(v, __shfl_xor(v, 2));
+}
+
+// What Split does with the patch at s (48 floats in LDS): 0 drop, 1 dice,
+// 2 split in u, 3 split in v (include/pk_reyes.h).  Computed by the four
+// lanes of a quad: lane a transforms row a and the two end points of column
+// a; the box and the row and column spans are reduced over the quad.  Every
+// lane of the quad returns the same decision; the four lanes must be active
+// together.
+__device__ inline int quad_decide(const float *s, int a, const float (&m)[16], bool has_m,
+                                  const SplitArgs &A, bool last) {
+    float xs[4], ys[4], cx0, cy0, cx3, cy3;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float *q = s + 3 * (4 * a + k);
+        ok = ctrl_screen(m, has_m, A.hw, A.hh, q[0], q[1], q[2], xs[k], ys[k]) && ok;
+    }
+    ok = ctrl_screen(m, has_m, A.hw, A.hh, s[3 * a], s[3 * a + 1], s[3 * a + 2], cx0, cy0) && ok;
+    ok = ctrl_screen(m, has_m, A.hw, A.hh, s[3 * (12 + a)], s[3 * (12 + a) + 1],
+                     s[3 * (12 + a) + 2], cx3, cy3) && ok;
+    int okq = ok ? 1 : 0;
+    okq &= __shfl_xor(okq, 1);
+    okq &= __shfl_xor(okq, 2);
+    if (!okq) return 0;
+    float x0 = fminf(fminf(xs[0], xs[1]), fminf(xs[2], xs[3]));
+    float x1 = fmaxf(fmaxf(xs[0], xs[1]), fmaxf(xs[2], xs[3]));
+    float y0 = fminf(fminf(ys[0], ys[1]), fminf(ys[2], ys[3]));
+    float y1 = fmaxf(fmaxf(ys[0], ys[1]), fmaxf(ys[2], ys[3]));
+    x0 = quad_min(x0); y0 = quad_min(y0);
+    x1 = quad_max(x1); y1 = quad_max(y1);
+    if (x1 < 0.0f || x0 > A.W || y1 < 0.0f || y0 > A.H) return 0;
+    if ((x1 - x0 <= A.dice && y1 - y0 <= A.dice) || last) return 1;
+    const float ux = xs[3] - xs[0], uy = ys[3] - ys[0];
+    const float vx = cx3 - cx0, vy = cy3 - cy0;
+    const float du = quad_max(ux * ux + uy * uy), dv = quad_max(vx * vx + vy * vy);
+    return du >= dv ? 2 : 3;
+}
+
+// Copy `cnt` consecutive patches starting at `first` into LDS, coalesced.
+__device__ inline void stage_tile(float4 *dst, const float *src, int64_t first, int cnt) {
+    const float4 *s4 = reinterpret_cast<const float4 *>(src) + first * (kPatch / 4);
+    for (int f = threadIdx.x; f < cnt * (kPatch / 4); f += kRT) dst[f] = s4[f];
+}
+
+// Decisions and per-chunk counts of the input patches (round 0).
+__global__ __launch_bounds__(kRT) void k_split_first(SplitArgs a, const float *in, int64_t np) {
     __shared__ int s_wave[kRT / kWave];
-    const int64_t n = round_size(a, r);
-    int64_t begin, end;
-    chunk_of(n, begin, end);
+    __shared__ float4 s_in4[kTile * kPatch / 4];
+    const float *s_in = reinterpret_cast<const float *>(s_in4);
+    const int64_t begin = (int64_t)blockIdx.x * a.chunk;
+    const int64_t end = begin + a.chunk < np ? begin + a.chunk : np;
     float m[16];
     load_matrix(a.mvp, m);
-    const bool has_m = a.mvp != nullptr, last = r == a.max_depth;
+    const bool has_m = a.mvp != nullptr, last = a.max_depth == 0;
+    const int p = threadIdx.x >> 2, row = threadIdx.x & 3;
     int kids = 0, lv = 0;
-    for (int64_t b = begin; b < end; b += kRT) {
-        const int64_t i = b + threadIdx.x;
-        if (i < end) {
-            float cp[kPatch];
-            load_patch(in + kPatch * i, cp);
-            const int d = split_decide(cp, m, has_m, a, last);
-            a.w.dec[i] = (uint8_t)d;
-            kids += d >= 2 ? 2 : 0;
-            lv += d == 1 ? 1 : 0;
+    for (int64_t b = begin; b < end; b += kTile) {
+        const int cnt = (int)(end - b < kTile ? end - b : kTile);
+        stage_tile(s_in4, in, b, cnt);
+        __syncthreads();
+        if (p < cnt) {
+            const int d = quad_decide(s_in + kPatch * p, row, m, has_m, a, last);
+            if (row == 0) {
+                a.w.dec[0][b + p] = (uint8_t)d;
+                kids += d >= 2 ? 2 : 0;
+                lv += d == 1 ? 1 : 0;
+            }
         }
+        __syncthreads();
     }
     int tk, tl;
     block_exclusive_scan<kRT>(kids, s_wave, tk);
     block_exclusive_scan<kRT>(lv, s_wave, tl);
     if (threadIdx.x == 0) {
-        a.w.agg[2 * blockIdx.x] = tk;
-        a.w.agg[2 * blockIdx.x + 1] = tl;
+        a.w.agg[0][2 * blockIdx.x] = tk;
+        a.w.agg[0][2 * blockIdx.x + 1] = tl;
     }
 }
 
-__global__ __launch_bounds__(kRT) void k_split_write(SplitArgs a, int r, const float *in,
-                                                      const int32_t *in_src, float *out,
-                                                      int32_t *out_src) {
+// One round: leaves and halves of the round's patches written in queue
+// order (staged in LDS, stored coalesced), the halves decided for the next
+// round.  Tiles of 64 patches, four lanes per patch.
+__global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const float *in,
+                                                      const int32_t *in_src, const uint8_t *dec_in,
+                                                      const int32_t *agg_in, float *out,
+                                                      int32_t *out_src, uint8_t *dec_out,
+                                                      int32_t *agg_out, int32_t *agg_clear) {
     __shared__ int s_wave[kRT / kWave];
+    __shared__ int s_next[4][2];   // counts of the next round's chunks this tile touches
+    __shared__ float4 s_in4[kTile * kPatch / 4];
+    __shared__ float4 s_out4[2 * kTile * kPatch / 4];
+    __shared__ int s_leaf[kTile];  // tile patch of each leaf of the tile
+    __shared__ int32_t s_ksrc[2 * kTile];
+    float *s_in = reinterpret_cast<float *>(s_in4);
+    float *s_out = reinterpret_cast<float *>(s_out4);
+    // the next round but one accumulates into agg_clear
+    if (threadIdx.x < 2) agg_clear[2 * blockIdx.x + threadIdx.x] = 0;
     const int64_t n = round_size(a, r);
-    int64_t begin, end;
-    chunk_of(n, begin, end);
+    const int64_t CH = a.chunk;
+    const int64_t begin = (int64_t)blockIdx.x * CH;
+    const int64_t end = begin + CH < n ? begin + CH : n;
     if (begin >= end && blockIdx.x != 0) return;          // uniform per workgroup
     // children and leaves of the chunks before this one (and of all chunks)
     int kb = 0, lb = 0, kt = 0, lt = 0;
-    for (int g = threadIdx.x; g < kRGroups; g += kRT) {
-        const int c = a.w.agg[2 * g], l = a.w.agg[2 * g + 1];
+    for (int g = threadIdx.x; g < (int)gridDim.x; g += kRT) {
+        const int c = agg_in[2 * g], l = agg_in[2 * g + 1];
         if (g < (int)blockIdx.x) { kb += c; lb += l; }
         kt += c;
         lt += l;
@@ -258,34 +290,92 @@ __global__ __launch_bounds__(kRT) void k_split_write(SplitArgs a, int r, const f
     block_exclusive_scan<kRT>(lb, s_wave, t); lb = t;
     block_exclusive_scan<kRT>(kt, s_wave, t); kt = t;
     block_exclusive_scan<kRT>(lt, s_wave, t); lt = t;
+    float m[16];
+    load_matrix(a.mvp, m);
+    const bool has_m = a.mvp != nullptr, last_next = r + 1 == a.max_depth;
     const int64_t leaf0 = a.w.ctl[kCtlLeaf + r];
     int64_t kid_run = kb, leaf_run = leaf0 + lb;
-    for (int64_t b = begin; b < end; b += kRT) {
-        const int64_t i = b + threadIdx.x;
-        const int d = i < end ? (int)a.w.dec[i] : 0;
+    const int p = threadIdx.x >> 2, row = threadIdx.x & 3;
+    const int lane = threadIdx.x & (kWave - 1), lead_lane = lane & ~3;
+    float4 *out4 = reinterpret_cast<float4 *>(out);
+    float4 *leaves4 = reinterpret_cast<float4 *>(a.leaves);
+    for (int64_t b = begin; b < end; b += kTile) {
+        const int cnt = (int)(end - b < kTile ? end - b : kTile);
+        stage_tile(s_in4, in, b, cnt);
+        const int d = p < cnt ? (int)dec_in[b + p] : 0;
+        const bool lead = row == 0;
         int tk, tl;
-        const int ek = block_exclusive_scan<kRT>(d >= 2 ? 2 : 0, s_wave, tk);
-        const int el = block_exclusive_scan<kRT>(d == 1 ? 1 : 0, s_wave, tl);
-        if (d != 0) {
-            float cp[kPatch];
-            load_patch(in + kPatch * i, cp);
-            const int32_t src = in_src ? in_src[i] : (int32_t)i;
+        int ek = block_exclusive_scan<kRT>(lead && d >= 2 ? 2 : 0, s_wave, tk);
+        int el = block_exclusive_scan<kRT>(lead && d == 1 ? 1 : 0, s_wave, tl);
+        ek = __shfl(ek, lead_lane);
+        el = __shfl(el, lead_lane);
+        if (lead && d != 0) {
+            const int32_t src = in_src ? in_src[b + p] : (int32_t)(b + p);
             if (d == 1) {
-                const int64_t slot = leaf_run + el;
-                if (slot < a.leaf_cap) {
-                    store_patch(a.leaves + kPatch * slot, cp);
-                    a.leaf_src[slot] = src;
-                }
+                s_leaf[el] = p;
+                if (leaf_run + el < a.leaf_cap) a.leaf_src[leaf_run + el] = src;
             } else {
-                float lo[kPatch], hi[kPatch];
-                if (d == 2) halve<0>(cp, lo, hi); else halve<1>(cp, lo, hi);
-                const int64_t slot = kid_run + ek;
-                if (slot < a.cap) { store_patch(out + kPatch * slot, lo); out_src[slot] = src; }
-                if (slot + 1 < a.cap) { store_patch(out + kPatch * (slot + 1), hi); out_src[slot + 1] = src; }
+                s_ksrc[ek] = src;
+                s_ksrc[ek + 1] = src;
             }
+        }
+        if (threadIdx.x < 8) (&s_next[0][0])[threadIdx.x] = 0;
+        __syncthreads();                                   // tile, maps in LDS
+        if (d >= 2) {
+            // lane `row` halves line `row`: a row (split in u) or a column (in v)
+            const float *cp = s_in + kPatch * p;
+            float *lo = s_out + kPatch * ek, *hi = s_out + kPatch * (ek + 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int pt[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pt[k] = d == 2 ? 4 * row + k : 4 * k + row;
+                const float x0 = cp[3 * pt[0] + c], x1 = cp[3 * pt[1] + c];
+                const float x2 = cp[3 * pt[2] + c], x3 = cp[3 * pt[3] + c];
+                const float ab = lerp_rn(x0, x1, 0.5f), bc = lerp_rn(x1, x2, 0.5f);
+                const float cd = lerp_rn(x2, x3, 0.5f);
+                const float abc = lerp_rn(ab, bc, 0.5f), bcd = lerp_rn(bc, cd, 0.5f);
+                const float mid = lerp_rn(abc, bcd, 0.5f);
+                lo[3 * pt[0] + c] = x0;   lo[3 * pt[1] + c] = ab;
+                lo[3 * pt[2] + c] = abc;  lo[3 * pt[3] + c] = mid;
+                hi[3 * pt[0] + c] = mid;  hi[3 * pt[1] + c] = bcd;
+                hi[3 * pt[2] + c] = cd;   hi[3 * pt[3] + c] = x3;
+            }
+        }
+        __syncthreads();                                   // halves in LDS
+        for (int f = threadIdx.x; f < tl * (kPatch / 4); f += kRT) {
+            const int j = f / (kPatch / 4), k = f - j * (kPatch / 4);
+            const int64_t slot = leaf_run + j;
+            if (slot < a.leaf_cap) leaves4[slot * (kPatch / 4) + k] = s_in4[s_leaf[j] * (kPatch / 4) + k];
+        }
+        for (int f = threadIdx.x; f < tk * (kPatch / 4); f += kRT) {
+            const int64_t slot = kid_run + f / (kPatch / 4);
+            if (slot < a.cap) out4[kid_run * (kPatch / 4) + f] = s_out4[f];
+        }
+        for (int j = threadIdx.x; j < tk; j += kRT)
+            if (kid_run + j < a.cap) out_src[kid_run + j] = s_ksrc[j];
+        // decide the halves for the next round: quad p takes halves p, p + 64
+        const int64_t c0 = kid_run / CH;
+        for (int j = p; j < tk; j += kTile) {
+            const int64_t slot = kid_run + j;
+            if (slot < a.cap) {
+                const int dh = quad_decide(s_out + kPatch * j, row, m, has_m, a, last_next);
+                if (row == 0) {
+                    dec_out[slot] = (uint8_t)dh;
+                    const int c = (int)(slot / CH - c0);
+                    if (dh >= 2) atomicAdd(&s_next[c][0], 2);
+                    if (dh == 1) atomicAdd(&s_next[c][1], 1);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            const int c = threadIdx.x >> 1, v = (&s_next[0][0])[threadIdx.x];
+            if (v) atomicAdd(&agg_out[2 * (c0 + c) + (threadIdx.x & 1)], v);
         }
         kid_run += tk;
         leaf_run += tl;
+        __syncthreads();                                   // LDS reused by the next tile
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.w.ctl[kCtlN + r + 1] = kt;
@@ -408,13 +498,17 @@ extern "C" pk_status pk_reyes_split(const pk_reyes_params *p, const float *patch
     a.leaf_cap = leaf_capacity;
     a.counts = counts;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_split_init, dim3(1), dim3(64), 0, st, a, num_patches);
+    const int64_t n_max = std::max<int64_t>(std::max(num_patches, queue_capacity), 1);
+    a.chunk = chunk_size(num_patches, queue_capacity);
+    const unsigned groups = (unsigned)((n_max + a.chunk - 1) / a.chunk);
+    hipLaunchKernelGGL(k_split_init, dim3(1), dim3(kRT), 0, st, a, num_patches);
+    hipLaunchKernelGGL(k_split_first, dim3(groups), dim3(kRT), 0, st, a, patches, num_patches);
     for (int r = 0; r <= p->max_depth; ++r) {
         const float *in = r == 0 ? patches : a.w.q[(r - 1) & 1];
         const int32_t *in_src = r == 0 ? nullptr : a.w.qsrc[(r - 1) & 1];
-        hipLaunchKernelGGL(k_split_decide, dim3(kRGroups), dim3(kRT), 0, st, a, r, in);
-        hipLaunchKernelGGL(k_split_write, dim3(kRGroups), dim3(kRT), 0, st, a, r, in, in_src,
-                           a.w.q[r & 1], a.w.qsrc[r & 1]);
+        hipLaunchKernelGGL(k_split_round, dim3(groups), dim3(kRT), 0, st, a, r, in, in_src,
+                           a.w.dec[r & 1], a.w.agg[r % 3], a.w.q[r & 1], a.w.qsrc[r & 1],
+                           a.w.dec[(r + 1) & 1], a.w.agg[(r + 1) % 3], a.w.agg[(r + 2) % 3]);
     }
     return hipGetLastError() == hipSuccess ? PK_OK : PK_ERR_HIP;
 }
