@@ -272,19 +272,23 @@ __global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const f
     float *s_out = reinterpret_cast<float *>(s_out4);
     // the next round but one accumulates into agg_clear
     if (threadIdx.x < 2) agg_clear[2 * blockIdx.x + threadIdx.x] = 0;
+    // Every load that does not depend on another is issued before the first
+    // wait: a round is a short chain of dependent memory round trips, and
+    // each one removed shortens it.
+    // children and leaves of the chunks before this one (and of all chunks)
+    int kb = 0, lb = 0, kt = 0, lt = 0;
+    for (int g = threadIdx.x; g < (int)gridDim.x; g += kRT) {
+        const int2 cl = reinterpret_cast<const int2 *>(agg_in)[g];
+        if (g < (int)blockIdx.x) { kb += cl.x; lb += cl.y; }
+        kt += cl.x;
+        lt += cl.y;
+    }
     const int64_t n = round_size(a, r);
+    const int64_t leaf0 = a.w.ctl[kCtlLeaf + r];
     const int64_t CH = a.chunk;
     const int64_t begin = (int64_t)blockIdx.x * CH;
     const int64_t end = begin + CH < n ? begin + CH : n;
     if (begin >= end && blockIdx.x != 0) return;          // uniform per workgroup
-    // children and leaves of the chunks before this one (and of all chunks)
-    int kb = 0, lb = 0, kt = 0, lt = 0;
-    for (int g = threadIdx.x; g < (int)gridDim.x; g += kRT) {
-        const int c = agg_in[2 * g], l = agg_in[2 * g + 1];
-        if (g < (int)blockIdx.x) { kb += c; lb += l; }
-        kt += c;
-        lt += l;
-    }
     int t;
     block_exclusive_scan<kRT>(kb, s_wave, t); kb = t;
     block_exclusive_scan<kRT>(lb, s_wave, t); lb = t;
@@ -293,16 +297,25 @@ __global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const f
     float m[16];
     load_matrix(a.mvp, m);
     const bool has_m = a.mvp != nullptr, last_next = r + 1 == a.max_depth;
-    const int64_t leaf0 = a.w.ctl[kCtlLeaf + r];
     int64_t kid_run = kb, leaf_run = leaf0 + lb;
     const int p = threadIdx.x >> 2, row = threadIdx.x & 3;
     const int lane = threadIdx.x & (kWave - 1), lead_lane = lane & ~3;
     float4 *out4 = reinterpret_cast<float4 *>(out);
     float4 *leaves4 = reinterpret_cast<float4 *>(a.leaves);
+    const float4 *in4 = reinterpret_cast<const float4 *>(in);
     for (int64_t b = begin; b < end; b += kTile) {
         const int cnt = (int)(end - b < kTile ? end - b : kTile);
-        stage_tile(s_in4, in, b, cnt);
+        // the tile (3 float4 per thread), its decisions and sources, all in flight at once
+        float4 v4[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int f = threadIdx.x + k * kRT;
+            v4[k] = f < cnt * (kPatch / 4) ? in4[b * (kPatch / 4) + f] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         const int d = p < cnt ? (int)dec_in[b + p] : 0;
+        const int32_t src_l = (row == 0 && p < cnt) ? (in_src ? in_src[b + p] : (int32_t)(b + p)) : 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_in4[threadIdx.x + k * kRT] = v4[k];
         const bool lead = row == 0;
         int tk, tl;
         int ek = block_exclusive_scan<kRT>(lead && d >= 2 ? 2 : 0, s_wave, tk);
@@ -310,7 +323,7 @@ __global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const f
         ek = __shfl(ek, lead_lane);
         el = __shfl(el, lead_lane);
         if (lead && d != 0) {
-            const int32_t src = in_src ? in_src[b + p] : (int32_t)(b + p);
+            const int32_t src = src_l;
             if (d == 1) {
                 s_leaf[el] = p;
                 if (leaf_run + el < a.leaf_cap) a.leaf_src[leaf_run + el] = src;
