@@ -508,9 +508,11 @@ def bench_reyes(reps: int = 10) -> dict:
     (dice at 16 px, 8 x 8 grids, one light): Split (every round, one stream),
     Dice, Sample + Shade of the diced micropolygons under a few rasterizer
     configurations, and the whole frame including the host's read of the
-    leaf count; medians of HIP-event timings (ms).  Split's rate counts the
-    patches visited over all rounds; the oracle's Split + Dice on the host
-    is timed beside it."""
+    leaf count; medians of HIP-event timings (ms).  A frame's Split enqueues
+    the rounds the previous frame needed (the count of rounds with work)
+    and only then the rest if the queue has not drained; Split's rate counts
+    the patches visited over all rounds; the oracle's Split + Dice on the
+    host is timed beside it."""
     import time
     import torch
     import oracle
@@ -521,8 +523,14 @@ def bench_reyes(reps: int = 10) -> dict:
     nl = r.leaves()
     r.dice(nl)
     torch.cuda.synchronize()
-    _, largest, visits, _ = r.read_counts()
+    _, largest, visits, _, _, worked = r.read_counts()
+    # a frame enqueues the rounds the last one needed (then checks that the
+    # queue drained); all max_depth + 1 rounds for comparison
     split_ms = _median_ms(torch, r.split, reps)
+    split_all_ms = _median_ms(torch, lambda: r.split(ps.max_depth + 1), reps)
+    r.split()
+    torch.cuda.synchronize()
+    assert r.read_counts()[4] == 0
     # the same rounds replayed from a HIP graph (launch costs only)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -569,8 +577,9 @@ def bench_reyes(reps: int = 10) -> dict:
     return {"workload": f"{ps.name}: {ps.num_patches} bicubic patches, dice at {ps.dice_px} px "
                         f"into {ps.dice_n}x{ps.dice_n} grids, forward-lit, 1 light",
             "leaves": nl, "micropolygons": tris, "largest_queue": largest,
-            "patches_visited": visits, "rounds_enqueued": ps.max_depth + 1,
-            "split_ms": round(split_ms, 4),
+            "patches_visited": visits, "rounds_with_work": worked,
+            "max_rounds": ps.max_depth + 1, "split_ms": round(split_ms, 4),
+            "split_all_rounds_ms": round(split_all_ms, 4),
             "split_mpatches_per_s": round(visits / (split_ms * 1e-3) / 1e6, 1),
             "split_graph_ms": round(split_graph_ms, 4), "split_graph_same_leaves": graph_ok,
             "dice_ms": round(dice_ms, 4),

@@ -11,8 +11,8 @@
  * diced mesh with PK_SHADE_LIT; this header adds the two stages in front of
  * it.  A self-loop stage runs by launching it again until its queue is
  * empty (Sec. 5.1, stage ordering with cycles); here each round of Split is
- * two kernels that read the round's queue length from device memory, so all
- * rounds are enqueued at once and no round waits for the host.
+ * one kernel that reads the round's queue length from device memory, so
+ * rounds are enqueued in batches and no round waits for the host.
  *
  * The paper fixes neither the split test nor the dice rate.  This library
  * reads them as follows (every rule is exact and deterministic, so results
@@ -84,25 +84,36 @@ size_t pk_reyes_workspace_bytes(const pk_reyes_params *p, int64_t num_patches,
 /* Split (Sec. 7.1 Reyes; self-loop of Sec. 5.1) of num_patches patches
  * [P][16][3] seen through `mvp` ([16] float32 row-major acting on column
  * vectors, or NULL = identity).  `patches` and `leaves` are 16-byte
- * aligned.  Writes the leaves, in the order above, to
- * leaves [leaf_capacity][16][3] and their input patch numbers to
- * leaf_src [leaf_capacity]; leaves beyond leaf_capacity are counted, not
- * written.  counts (device, int64[4]) receives:
+ * aligned.  Enqueues rounds round_begin .. min(round_end, max_depth + 1) - 1:
+ * a whole Split is rounds 0 .. max_depth, in one call or in several calls on
+ * the same workspace and buffers, each starting where the previous one
+ * stopped (a call with round_begin 0 starts afresh).  The leaves, in the
+ * order above, go to leaves [leaf_capacity][16][3] and their input patch
+ * numbers to leaf_src [leaf_capacity]; leaves beyond leaf_capacity are
+ * counted, not written.  counts (device, int64[6]) receives, over the
+ * rounds run so far:
  *   [0] the number of leaves,
  *   [1] the most patches any round had to queue,
- *   [2] the patches visited over all rounds (Split's work),
- *   [3] 1 when a round's queue outgrew queue_capacity, else 0.
- * When [3] is 1 the rounds after the overflow saw a truncated queue and
- * [0] is not the true count: call again with queue_capacity >= [1] (which
- * may grow again in later rounds).  `ws` (256-byte aligned) holds
- * pk_reyes_workspace_bytes(p, num_patches, queue_capacity) bytes; its
- * contents need no initialisation.  num_patches
+ *   [2] the patches visited (Split's work),
+ *   [3] 1 when a round's queue outgrew queue_capacity, else 0,
+ *   [4] the patches queued for the round after the last one run (0: Split
+ *       has drained, and further rounds would do nothing),
+ *   [5] the number of rounds that had patches to visit.
+ * A caller that knows roughly how deep a scene splits (say [5] of the
+ * previous frame) enqueues that many rounds, reads [4] (the paper's check
+ * that the self-loop has drained) and enqueues the rest only if it is not
+ * 0: empty rounds cost a launch each.  When [3] is 1 the rounds after the
+ * overflow saw a truncated queue and [0] is not the true count: split again
+ * from round 0 with queue_capacity >= [1] (which may grow again in later
+ * rounds).  `ws` (256-byte aligned) holds pk_reyes_workspace_bytes(p,
+ * num_patches, queue_capacity) bytes; it needs no initialisation, and keeps
+ * the state between the calls of one Split.  num_patches
  * 0..PK_REYES_MAX_QUEUE, queue_capacity 0..PK_REYES_MAX_QUEUE,
- * leaf_capacity >= 0. */
+ * leaf_capacity >= 0, 0 <= round_begin <= round_end. */
 pk_status pk_reyes_split(const pk_reyes_params *p, const float *patches, int64_t num_patches,
                          const float *mvp, void *ws, int64_t queue_capacity, float *leaves,
-                         int32_t *leaf_src, int64_t leaf_capacity, int64_t *counts,
-                         void *stream);
+                         int32_t *leaf_src, int64_t leaf_capacity, int32_t round_begin,
+                         int32_t round_end, int64_t *counts, void *stream);
 
 /* Dice (Sec. 7.1 Reyes) of num_leaves leaves [L][16][3] with source patch
  * numbers leaf_src [L] into a one-scene indexed mesh for pk.h: pos, color

@@ -155,10 +155,7 @@ __global__ __launch_bounds__(kRT) void k_split_init(SplitArgs a, int64_t np) {
     if (threadIdx.x == 0) {
         a.w.ctl[kCtlN] = np;
         a.w.ctl[kCtlLeaf] = 0;
-        a.counts[0] = 0;
-        a.counts[1] = 0;
-        a.counts[2] = 0;
-        a.counts[3] = 0;
+        for (int k = 0; k < 6; ++k) a.counts[k] = 0;
     }
     // round 0 adds the counts of the halves it decides into agg[1]
     for (int k = threadIdx.x; k < 2 * kMaxChunks; k += kRT) a.w.agg[1][k] = 0;
@@ -397,6 +394,8 @@ __global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const f
         if (kt > a.counts[1]) a.counts[1] = kt;
         a.counts[2] += n;
         if (kt > a.cap) a.counts[3] = 1;
+        a.counts[4] = kt;
+        if (n > 0) a.counts[5] = r + 1;
     }
 }
 
@@ -488,8 +487,10 @@ extern "C" size_t pk_reyes_workspace_bytes(const pk_reyes_params *p, int64_t num
 extern "C" pk_status pk_reyes_split(const pk_reyes_params *p, const float *patches,
                                     int64_t num_patches, const float *mvp, void *ws,
                                     int64_t queue_capacity, float *leaves, int32_t *leaf_src,
-                                    int64_t leaf_capacity, int64_t *counts, void *stream) {
+                                    int64_t leaf_capacity, int32_t round_begin,
+                                    int32_t round_end, int64_t *counts, void *stream) {
     if (!params_ok(p) || num_patches < 0 || num_patches > PK_REYES_MAX_QUEUE ||
+        round_begin < 0 || round_end < round_begin ||
         queue_capacity < 0 || queue_capacity > PK_REYES_MAX_QUEUE || leaf_capacity < 0 ||
         !ws || !aligned(ws, kAlign) || !counts || (num_patches > 0 && !patches) ||
         !aligned(patches, 16) || (leaf_capacity > 0 && (!leaves || !leaf_src)) ||
@@ -514,9 +515,12 @@ extern "C" pk_status pk_reyes_split(const pk_reyes_params *p, const float *patch
     const int64_t n_max = std::max<int64_t>(std::max(num_patches, queue_capacity), 1);
     a.chunk = chunk_size(num_patches, queue_capacity);
     const unsigned groups = (unsigned)((n_max + a.chunk - 1) / a.chunk);
-    hipLaunchKernelGGL(k_split_init, dim3(1), dim3(kRT), 0, st, a, num_patches);
-    hipLaunchKernelGGL(k_split_first, dim3(groups), dim3(kRT), 0, st, a, patches, num_patches);
-    for (int r = 0; r <= p->max_depth; ++r) {
+    if (round_begin == 0 && round_end > 0) {
+        hipLaunchKernelGGL(k_split_init, dim3(1), dim3(kRT), 0, st, a, num_patches);
+        hipLaunchKernelGGL(k_split_first, dim3(groups), dim3(kRT), 0, st, a, patches, num_patches);
+    }
+    const int r_end = std::min(round_end, p->max_depth + 1);
+    for (int r = round_begin; r < r_end; ++r) {
         const float *in = r == 0 ? patches : a.w.q[(r - 1) & 1];
         const int32_t *in_src = r == 0 ? nullptr : a.w.qsrc[(r - 1) & 1];
         hipLaunchKernelGGL(k_split_round, dim3(groups), dim3(kRT), 0, st, a, r, in, in_src,

@@ -116,7 +116,8 @@ def lib():
         L.pk_reyes_workspace_bytes.restype = C.c_size_t
         L.pk_reyes_workspace_bytes.argtypes = [P, C.c_int64, C.c_int64]
         L.pk_reyes_split.restype = C.c_int
-        L.pk_reyes_split.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P, P, C.c_int64, P, P]
+        L.pk_reyes_split.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P, P, C.c_int64,
+                                     C.c_int32, C.c_int32, P, P]
         L.pk_reyes_dice.restype = C.c_int
         L.pk_reyes_dice.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, P, P, P, P]
         L.pk_status_string.restype = C.c_char_p
@@ -191,10 +192,12 @@ def pk_reyes_workspace_bytes(params: ReyesParams, num_patches: int, queue_capaci
 
 def pk_reyes_split(params: ReyesParams, patches: int, num_patches: int, mvp: Optional[int],
                    ws: int, queue_capacity: int, leaves: Optional[int], leaf_src: Optional[int],
-                   leaf_capacity: int, counts: int, stream: int = 0):
+                   leaf_capacity: int, round_begin: int, round_end: int, counts: int,
+                   stream: int = 0):
     _check("pk_reyes_split", lib().pk_reyes_split(_ref(params), patches, int(num_patches), mvp, ws,
                                                   int(queue_capacity), leaves, leaf_src,
-                                                  int(leaf_capacity), counts, stream))
+                                                  int(leaf_capacity), int(round_begin),
+                                                  int(round_end), counts, stream))
 
 
 def pk_reyes_dice(params: ReyesParams, leaves: int, leaf_src: int, num_leaves: int,
@@ -498,7 +501,9 @@ class Reyes:
         self.lights = np.asarray(lights, np.float64).astype(np.float32).reshape(-1, 3)
         self.params = ReyesParams(self.W, self.H, float(ps.dice_px), int(ps.max_depth),
                                   int(ps.dice_n))
-        self.counts = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.counts = torch.zeros(6, dtype=torch.int64, device=dev)
+        self._rounds_hint = int(ps.max_depth) + 1
+        self._enqueued = 0
         P = max(self.num_patches, 1)
         self._alloc_queue(queue_capacity if queue_capacity is not None else 8 * P + 1024)
         self._alloc_leaves(leaf_capacity if leaf_capacity is not None else 8 * P + 1024)
@@ -521,31 +526,49 @@ class Reyes:
                                         device=self.device)
         self.leaf_src = self.torch.empty(max(cap, 1), dtype=self.torch.int32, device=self.device)
 
-    def split(self):
-        """Enqueue every Split round; no synchronization."""
+    def split(self, rounds: Optional[int] = None):
+        """Enqueue the first ``rounds`` Split rounds (default: as many as the
+        last split needed, or all of them the first time); no
+        synchronization.  ``leaves()`` enqueues the rest if they were not
+        enough."""
+        total = int(self.params.max_depth) + 1
+        k = self._rounds_hint if rounds is None else int(rounds)
+        k = min(max(k, 1), total)
+        self._enqueued = k
+        self._split_rounds(0, k)
+
+    def _split_rounds(self, r0: int, r1: int):
         pk_reyes_split(self.params, self.patches.data_ptr(), self.num_patches, _ptr(self.mvp),
                        self.ws.data_ptr(), self.queue_capacity, self.leaf_cp.data_ptr(),
-                       self.leaf_src.data_ptr(), self.leaf_capacity, self.counts.data_ptr(),
-                       _stream())
+                       self.leaf_src.data_ptr(), self.leaf_capacity, r0, r1,
+                       self.counts.data_ptr(), _stream())
 
     def read_counts(self):
-        """(leaves, largest queue, patches visited, overflow) of the last split."""
+        """(leaves, largest queue, patches visited, overflow, patches queued
+        for the next round, rounds with work) of the rounds run so far."""
         return tuple(int(x) for x in self.counts.cpu().tolist())
 
     def leaves(self) -> int:
-        """Number of leaves of the last split(), after growing the buffers and
-        splitting again until both the queue and the leaf list were large
-        enough."""
+        """Number of leaves of the last split(), after enqueueing the rounds
+        it still needed, and after growing the buffers and splitting again
+        when the queue or the leaf list were too small."""
+        total = int(self.params.max_depth) + 1
         for _ in range(64):
-            nl, need, _, overflow = self.read_counts()
+            nl, need, _, overflow, pending, worked = self.read_counts()
             if overflow:
                 self._alloc_queue(max(int(need * 1.25) + 1024, 2 * self.queue_capacity))
+                self._split_rounds(0, self._enqueued)
             elif nl > self.leaf_capacity:
                 self._alloc_leaves(int(nl * 1.25) + 1024)
+                self._split_rounds(0, self._enqueued)
+            elif pending and self._enqueued < total:
+                # the self-loop has not drained: run the remaining rounds
+                self._split_rounds(self._enqueued, total)
+                self._enqueued = total
             else:
                 self.num_leaves = nl
+                self._rounds_hint = max(worked, 1)
                 return nl
-            self.split()
         raise PkError("pk_reyes_split", PK_ERR_CAPACITY, "queue kept overflowing")
 
     def _alloc_mesh(self, nl: int):

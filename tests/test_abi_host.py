@@ -322,16 +322,19 @@ def test_reyes_split_and_dice_validate_before_launch(L):
     bad = _rp(dice_n=0)
     cnt = FAKE
     S = L.pk_reyes_split
-    assert S(C.byref(bad), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), None, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, 4, None, None, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, 4, None, 0x10010, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # ws alignment
-    assert S(C.byref(ok), FAKE + 4, 4, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # patches alignment
-    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, None, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, None, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, -1, None, 0x10000, 64, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, 4, None, 0x10000, -1, FAKE, FAKE, 64, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
-    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, -1, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(bad), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), None, 4, None, 0x10000, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, None, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10010, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # ws alignment
+    assert S(C.byref(ok), FAKE + 4, 4, None, 0x10000, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT  # patches alignment
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, None, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, 0, 21, None, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, -1, None, 0x10000, 64, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, -1, FAKE, FAKE, 64, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, -1, 0, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    # rounds: 0 <= round_begin <= round_end
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, -1, 21, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
+    assert S(C.byref(ok), FAKE, 4, None, 0x10000, 64, FAKE, FAKE, 64, 5, 4, cnt, None) == pk.PK_ERR_INVALID_ARGUMENT
     D = L.pk_reyes_dice
     assert D(C.byref(bad), FAKE, FAKE, 4, FAKE, 4, FAKE, FAKE, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT
     assert D(C.byref(ok), FAKE, FAKE, -1, FAKE, 4, FAKE, FAKE, FAKE, FAKE, None) == pk.PK_ERR_INVALID_ARGUMENT

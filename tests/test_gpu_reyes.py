@@ -135,11 +135,11 @@ def test_empty_input_and_all_culled():
                          patch_color=np.zeros((0, 3), np.float32), mvp=None, dice_px=8.0,
                          max_depth=5, dice_n=4, lights=None)
     r, lv, src = gpu_split(ps)
-    assert len(lv) == 0 and r.read_counts() == (0, 0, 0, 0)
+    assert len(lv) == 0 and r.read_counts() == (0, 0, 0, 0, 0, 0)
     ps.patches = np.stack([reyes_pins.square(2.0, 2.0, 0.5)] * 3)
     ps.patch_color = np.ones((3, 3), np.float32)
     r, lv, src = gpu_split(ps)
-    assert len(lv) == 0 and r.read_counts() == (0, 0, 3, 0)
+    assert len(lv) == 0 and r.read_counts() == (0, 0, 3, 0, 0, 1)
     r.dice(0)
     torch.cuda.synchronize()
 
@@ -150,12 +150,12 @@ def test_queue_and_leaf_overflow_then_retry():
     ps = small(seed=4)
     r = pk.Reyes(ps, queue_capacity=16, leaf_capacity=8)
     r.split()
-    nl, need, visits, overflow = r.read_counts()
+    nl, need, visits, overflow = r.read_counts()[:4]
     assert overflow == 1 and need > 16
     check_split(ps, queue_capacity=16, leaf_capacity=8)
     r2 = pk.Reyes(ps, queue_capacity=1 << 16, leaf_capacity=8)
     r2.split()
-    nl, need, visits, overflow = r2.read_counts()
+    nl, need, visits, overflow = r2.read_counts()[:4]
     olv, _ = oracle.reyes_split(ps.patches, ps.mvp, ps.width, ps.height, ps.dice_px,
                                 ps.max_depth)
     assert overflow == 0 and nl == len(olv) > 8          # counted beyond the leaf list
@@ -163,14 +163,16 @@ def test_queue_and_leaf_overflow_then_retry():
 
 
 def test_counts_visits_and_largest_queue():
-    """[1] and [2] of the counts: the largest queue of rounds >= 1 and the
-    patches visited, from a breadth-first walk of the oracle's decisions."""
+    """The counts: the largest queue of rounds >= 1, the patches visited and
+    the rounds with work, from a breadth-first walk of the oracle's
+    decisions; nothing left queued at the end."""
     ps = small(seed=2)
     r, _, _ = gpu_split(ps)
     q = [p for p in ps.patches]
-    visits, largest = 0, 0
+    visits, largest, worked = 0, 0, 0
     for depth in range(ps.max_depth + 1):
         visits += len(q)
+        worked += 1 if q else 0
         nxt = []
         for cp in q:
             d = oracle.reyes_decide(cp, ps.mvp, ps.width, ps.height, ps.dice_px,
@@ -179,8 +181,31 @@ def test_counts_visits_and_largest_queue():
                 nxt.extend(oracle.reyes_halve(cp, d - 2))
         q = nxt
         largest = max(largest, len(q))
-    _, need, got_visits, overflow = r.read_counts()
-    assert (need, got_visits, overflow) == (largest, visits, 0)
+    _, need, got_visits, overflow, pending, got_worked = r.read_counts()
+    assert (need, got_visits, overflow, pending, got_worked) == (largest, visits, 0, 0, worked)
+    assert r._rounds_hint == worked
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 5])
+def test_split_in_batches_of_rounds(rounds):
+    """Enqueueing the first rounds only, then the rest when the counts say
+    the queue has not drained, gives the same leaves as one call; so does a
+    later frame that enqueues just the rounds the last one needed."""
+    ps = small(seed=6)
+    _note(f"reyes rounds in batches: first {rounds}")
+    olv, osrc = oracle.reyes_split(ps.patches, ps.mvp, ps.width, ps.height, ps.dice_px,
+                                   ps.max_depth)
+    r = pk.Reyes(ps, queue_capacity=1 << 16)
+    for it in range(2):
+        r.split(rounds)
+        # the first rounds alone do not drain the sheet; the hint does
+        assert (r.read_counts()[4] > 0) == (it == 0)
+        nl = r.leaves()
+        assert nl == len(olv)
+        np.testing.assert_array_equal(r.leaf_src[:nl].cpu().numpy(), osrc)
+        assert (r.leaf_cp[:nl].cpu().numpy().view(np.uint32) == olv.view(np.uint32)).all()
+        rounds = None                           # next: the hint from the counts
+    assert r.read_counts()[4] == 0
 
 
 @pytest.mark.parametrize("cfg", [dict(bin_size=16), dict(bin_size=32, fuse_resolve=True),
