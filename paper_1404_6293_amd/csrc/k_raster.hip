@@ -517,19 +517,6 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 atomicMin(&s_key[sl], key);
             }
         };
-        if (a.init_keys) {
-            // the coarse level starts from the fine level's keys
-            const int64_t sb = (int64_t)s * G.W * G.H;
-            for (int i = tid; i < NPIX; i += TPB) {
-                const int lx = i % B, ly = i / B;
-                s_key[i] = (lx < pw && ly < ph) ? a.w.keys[sb + (int64_t)(py0 + ly) * G.W + px0 + lx]
-                                                : kEmptyKey;
-            }
-        } else {
-            for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
-        }
-        if (KBUF)
-            for (int i = tid; i < (a.sh.layers - 1) * NPIX; i += TPB) s_kbuf[i] = kEmptyKey;
         int32_t lbeg = 0, lend = 0;
         bool shared = false;   // PK_SCHED_SPLIT: the bin has several pieces
         if (!overflow && !piped) {
@@ -542,6 +529,37 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 lend = min(lend, lbeg + a.w.split);
             }
         }
+        // a coarse bin without triangles leaves the fine level's keys, which
+        // are already in the workspace, as they are
+        if (a.init_keys && lbeg >= lend) continue;
+        if (a.init_keys) {
+            // the coarse level starts from the fine level's keys: split into
+            // the depth and primitive-ID targets when the caller gave both
+            // (the two halves of a key; primitive ID -1 marks an empty
+            // pixel), else in the workspace
+            const int64_t sb = (int64_t)s * G.W * G.H;
+            const bool halves = a.sh.out_depth && a.sh.out_primid;
+            for (int i = tid; i < NPIX; i += TPB) {
+                const int lx = i % B, ly = i / B;
+                unsigned long long k = kEmptyKey;
+                if (lx < pw && ly < ph) {
+                    const int64_t p = sb + (int64_t)(py0 + ly) * G.W + px0 + lx;
+                    if (halves) {
+                        const int32_t pid = a.sh.out_primid[p];
+                        if (pid != -1)
+                            k = ((unsigned long long)__float_as_uint(a.sh.out_depth[p]) << 32) |
+                                (uint32_t)pid;
+                    } else {
+                        k = a.w.keys[p];
+                    }
+                }
+                s_key[i] = k;
+            }
+        } else {
+            for (int i = tid; i < NPIX; i += TPB) s_key[i] = kEmptyKey;
+        }
+        if (KBUF)
+            for (int i = tid; i < (a.sh.layers - 1) * NPIX; i += TPB) s_kbuf[i] = kEmptyKey;
         __syncthreads();
 
         // Process: every wave takes chunks of 64 triangles of the bin list
@@ -761,8 +779,7 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
             // as the final depth and primitive-ID targets when the caller
             // has both (the two halves of the key), else as keys
             const int64_t sb = (int64_t)s * G.W * G.H;
-            const bool split = !OIT && !KBUF && !a.w.split && !a.w.two_level && a.sh.out_depth &&
-                               a.sh.out_primid;
+            const bool split = !OIT && !KBUF && !a.w.split && a.sh.out_depth && a.sh.out_primid;
             // layer l's keys follow the whole key buffer of layers 0..l-1
             const int64_t lofs = OIT ? (int64_t)layer * G.S * G.W * G.H : 0;
 #pragma unroll 1
@@ -1048,7 +1065,7 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
     // keys in the workspace: whole-screen bins and split bins always, other
     // bins when a depth or primitive-ID target is missing
-    const bool split = G.B != 0 && !a.w.split && !a.w.two_level && a.sh.out_depth && a.sh.out_primid;
+    const bool split = G.B != 0 && !a.w.split && a.sh.out_depth && a.sh.out_primid;
     Resolve r[kResPPT];
     bool on[kResPPT];
 #pragma unroll
@@ -1268,10 +1285,12 @@ hipError_t launch_raster(const Geom &G, const Ws &w, const Shade &sh, int schedu
         for (int level = 0; level < 2 && e == hipSuccess; ++level) {
             const Geom &Gl = level ? Gc : Gf;
             const int tl = level ? 256 : tpb;
-            RasterArgs al{Gl, w, sh, schedule, G.nbins_scene, level ? G.nbins_f : 0, level};
-            const int gl = level ? 256 * 16 * kWave / 256 : groups;
-            const int64_t nb = schedule == PK_SCHED_LOAD_BALANCE ? Gl.nbins_total
-                               : (gl < Gl.nbins_total ? gl : Gl.nbins_total);
+            // the coarse level: one workgroup per coarse bin (LOAD_BALANCE),
+            // so that a bin without triangles costs nothing but its launch
+            const int sl = level ? PK_SCHED_LOAD_BALANCE : schedule;
+            RasterArgs al{Gl, w, sh, sl, G.nbins_scene, level ? G.nbins_f : 0, level};
+            const int64_t nb = sl == PK_SCHED_LOAD_BALANCE ? Gl.nbins_total
+                               : (groups < Gl.nbins_total ? groups : Gl.nbins_total);
             e = launch_shade<kKeysOnly>(al, tl, dim3((unsigned)nb), st);
         }
         if (e != hipSuccess) return e;

@@ -31,11 +31,12 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 }
 
 // A setup/scatter workgroup covers kGroupItems consecutive triangles.  When
-// the scenes those triangles belong to have at most kHist bins in total, the
-// per-bin counts are first accumulated in LDS and flushed with one global
-// atomic per touched bin (and the scatter reserves one contiguous slot range
-// per touched bin); otherwise lanes fall back to wave-aggregated global
-// atomics.  Device-scope atomics are slow on this part, LDS atomics are not.
+// the bins those triangles touch span at most kHist consecutive bin numbers
+// (counted over the scenes they belong to), the per-bin counts are first
+// accumulated in LDS over that span and flushed with one global atomic per
+// touched bin (and the scatter reserves one contiguous slot range per
+// touched bin); otherwise lanes fall back to wave-aggregated global atomics.
+// Device-scope atomics are slow on this part, LDS atomics are not.
 constexpr int kGroupThreads = 256;
 constexpr int kItemsPerThread = 4;
 constexpr int kGroupItems = kGroupThreads * kItemsPerThread;
@@ -51,13 +52,10 @@ __device__ inline int32_t scene_of(const Geom &G, int64_t item) {
     return item_ref(G, item).s;
 }
 
-// Scene window [s_lo, ...] of this workgroup's items; nwin = bins in it.
-__device__ inline bool group_window(const Geom &G, int64_t first, int32_t &s_lo, int64_t &nwin) {
-    const int64_t last = min(first + kGroupItems, G.items) - 1;
-    s_lo = scene_of(G, first);
-    const int32_t s_hi = scene_of(G, last);
-    nwin = (int64_t)(s_hi - s_lo + 1) * G.nbins_scene;
-    return nwin <= kHist;
+// First scene of this workgroup's items: bin numbers inside the workgroup
+// count from that scene's first bin.
+__device__ inline int32_t group_scene(const Geom &G, int64_t first) {
+    return scene_of(G, first);
 }
 
 // Vertex Shader stage for indexed meshes: each vertex (of each view when
@@ -245,9 +243,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
     __shared__ int s_red[2 * kGroupThreads / kWave];
     const int tid = threadIdx.x;
     const int64_t first = blockIdx.x * (int64_t)kGroupItems;
-    int32_t s_lo;
-    int64_t nwin;
-    const bool lds = group_window(G, first, s_lo, nwin);
+    const int32_t s_lo = group_scene(G, first);
     TriIn tin[kItemsPerThread];
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k)
@@ -275,10 +271,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
     }
     // AssignBin counts of the screen-space stage.  In LDS, only over the
     // span of bins this workgroup touches (a row strip for coherent meshes)
-    int glo = 0, ghi = -1;
+    int glo, ghi;
+    group_span(lo, hi, s_red, glo, ghi);
+    // (a workgroup touching no bin has glo > ghi and takes the other path,
+    // which then does nothing)
+    const bool lds = glo <= ghi && (int64_t)ghi - glo + 1 <= kHist;
     if (lds) {
-        group_span(lo, hi, s_red, glo, ghi);
-        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i] = 0;
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i - glo] = 0;
         __syncthreads();
     }
 #pragma unroll
@@ -286,10 +285,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
         const int32_t s = tin[k].s;
         if (lds) {
             // LDS atomics are cheap enough per lane
-            uint32_t *h = s_hist + (s - s_lo) * G.nbins_scene;
+            const int hb = (s - s_lo) * G.nbins_scene - glo;   // histogram index of bin 0
             int cx = br[k].bx0, cy = br[k].by0;
             for (int r = 0; r < br[k].nb; ++r) {
-                atomicAdd(h + bin_of(br[k], cx, cy), 1u);
+                atomicAdd(s_hist + (hb + bin_of(br[k], cx, cy)), 1u);
                 if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
         } else {
@@ -307,7 +306,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
         __syncthreads();
         uint32_t *dst = w.bin_count + (int64_t)s_lo * G.nbins_scene;
         for (int i = glo + tid; i <= ghi; i += kGroupThreads) {
-            const uint32_t c = s_hist[i];
+            const uint32_t c = s_hist[i - glo];
             if (c) atomicAdd(dst + i, c);
         }
     }
@@ -460,9 +459,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
     if (w.misc[1]) return;   // pair capacity exceeded: lists stay unwritten
     const int tid = threadIdx.x;
     const int64_t first = blockIdx.x * (int64_t)kGroupItems;
-    int32_t s_lo;
-    int64_t nwin;
-    const bool lds = group_window(G, first, s_lo, nwin);
+    const int32_t s_lo = group_scene(G, first);
     uint64_t bb[kItemsPerThread];
     int32_t sc[kItemsPerThread];
 #pragma unroll
@@ -471,28 +468,31 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         bb[k] = item < G.items ? w.bbox[item] : kEmptyKey;
         sc[k] = bb[k] != kEmptyKey ? scene_of(G, item) : 0;
     }
-    if (lds) {
-        // only the span of bins this workgroup touches
-        int lo = INT_MAX, hi = INT_MIN;
+    // the span of bins this workgroup touches
+    int lo = INT_MAX, hi = INT_MIN;
 #pragma unroll
-        for (int k = 0; k < kItemsPerThread; ++k) {
-            int l, h;
-            window_span(G, bin_rect(G, bb[k]), sc[k], s_lo, l, h);
-            lo = min(lo, l);
-            hi = max(hi, h);
-        }
-        int glo, ghi;
-        group_span(lo, hi, s_red, glo, ghi);
-        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i] = 0;
+    for (int k = 0; k < kItemsPerThread; ++k) {
+        int l, h;
+        window_span(G, bin_rect(G, bb[k]), sc[k], s_lo, l, h);
+        lo = min(lo, l);
+        hi = max(hi, h);
+    }
+    int glo, ghi;
+    group_span(lo, hi, s_red, glo, ghi);
+    // (a workgroup touching no bin has glo > ghi and takes the other path,
+    // which then does nothing)
+    const bool lds = glo <= ghi && (int64_t)ghi - glo + 1 <= kHist;
+    if (lds) {
+        for (int i = glo + tid; i <= ghi; i += kGroupThreads) s_hist[i - glo] = 0;
         __syncthreads();
         // count this workgroup's pairs per bin
 #pragma unroll
         for (int k = 0; k < kItemsPerThread; ++k) {
             const BinRect br = bin_rect(G, bb[k]);
-            uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
+            const int hb = (sc[k] - s_lo) * G.nbins_scene - glo;
             int cx = br.bx0, cy = br.by0;
             for (int r = 0; r < br.nb; ++r) {
-                atomicAdd(h + bin_of(br, cx, cy), 1u);
+                atomicAdd(s_hist + (hb + bin_of(br, cx, cy)), 1u);
                 if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }
         }
@@ -500,8 +500,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         // reserve one contiguous range per touched bin
         int32_t *cur = w.cursor + (int64_t)s_lo * G.nbins_scene;
         for (int i = glo + tid; i <= ghi; i += kGroupThreads) {
-            const uint32_t c = s_hist[i];
-            if (c) s_hist[i] = (uint32_t)atomicAdd(cur + i, (int32_t)c);
+            const uint32_t c = s_hist[i - glo];
+            if (c) s_hist[i - glo] = (uint32_t)atomicAdd(cur + i, (int32_t)c);
         }
         __syncthreads();
         // hand out the slots
@@ -509,10 +509,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
         for (int k = 0; k < kItemsPerThread; ++k) {
             const int64_t item = first + k * kGroupThreads + tid;
             const BinRect br = bin_rect(G, bb[k]);
-            uint32_t *h = s_hist + (sc[k] - s_lo) * G.nbins_scene;
+            const int hb = (sc[k] - s_lo) * G.nbins_scene - glo;
             int cx = br.bx0, cy = br.by0;
             for (int r = 0; r < br.nb; ++r) {
-                const uint32_t slot = atomicAdd(h + bin_of(br, cx, cy), 1u);
+                const uint32_t slot = atomicAdd(s_hist + (hb + bin_of(br, cx, cy)), 1u);
                 w.pairs[slot] = (int32_t)item;
                 if (++cx >= br.bx0 + br.nbx_t) { cx = br.bx0; ++cy; }
             }

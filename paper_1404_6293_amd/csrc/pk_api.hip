@@ -191,7 +191,6 @@ Ws carve(void *ws, const Frame &f, int64_t pair_capacity) {
     w.fb_mat = reinterpret_cast<uint32_t *>(b + L.fb_mat);
     w.fb_groups = f.fragbins ? f.fb_groups : 0;
     w.fb_rounds = f.fb_rounds;
-    w.two_level = f.two_level ? 1 : 0;
     return w;
 }
 

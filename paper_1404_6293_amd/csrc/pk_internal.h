@@ -208,7 +208,6 @@ struct Ws {
     int32_t *pairs;            // [pair_capacity]
     int64_t pair_capacity;
     int32_t split;             // PK_SCHED_SPLIT: pairs per work item; 0 otherwise
-    int32_t two_level;         // PK_FLAG_TWO_LEVEL_BINS: keys always in `keys`
     // PK_SCHED_FRAGMENT_BINS: `pairs` holds the fragments instead, as
     // kFbPlanes planes of pair_capacity 16-byte entries; fb_mat [fb_groups]
     // [nbins] the per-workgroup fragment counts of each bin
