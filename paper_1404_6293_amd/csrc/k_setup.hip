@@ -207,6 +207,67 @@ __device__ inline BinRect bin_rect(const Geom &G, uint64_t bb) {
 
 __device__ inline int bin_of(const BinRect &br, int cx, int cy) { return br.base + cy * br.stride + cx; }
 
+// The device-atomic path for a wave whose items have bin rectangles of very
+// different sizes (a large triangle among small ones): instead of one round
+// per bin of the largest rectangle, with the other lanes idle, the wave's
+// (item, bin) pairs are laid end to end in lane order and dealt 64 at a time,
+// one per lane.  Pair j belongs to the last lane whose first pair is at or
+// before j (a binary search over the lanes' exclusive prefix of counts); its
+// rectangle, scene and item come from that lane by shuffles.  fn(key, item)
+// runs on every lane once per round, key = scene * bins per scene + bin, or
+// -1 for no pair.  Call from uniform control flow.
+template <class F>
+__device__ inline void spread_pairs(const Geom &G, const BinRect &br, int32_t s, int64_t item, F fn) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int incl = br.nb;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    const int total = __shfl(incl, kWave - 1, kWave);
+    const int start = incl - br.nb;
+    const int ilo = (int)(uint32_t)item, ihi = (int)(item >> 32);
+    for (int b = 0; b < total; b += kWave) {
+        const int j = b + lane;
+        // the largest lane whose first pair is at or before j (starts never
+        // decrease over the lanes, and the owner found has pairs: a lane with
+        // none starts where the next one does)
+        int o = 0;
+#pragma unroll
+        for (int step = kWave / 2; step >= 1; step >>= 1) {
+            const int c = o + step;
+            const int sc = __shfl(start, c, kWave);
+            if (sc <= j) o = c;
+        }
+        const int o_start = __shfl(start, o, kWave);
+        const int bx0 = __shfl(br.bx0, o, kWave), by0 = __shfl(br.by0, o, kWave);
+        const int nbx = __shfl(br.nbx_t, o, kWave);
+        const int base = __shfl(br.base, o, kWave), stride = __shfl(br.stride, o, kWave);
+        const int so = __shfl(s, o, kWave);
+        const int64_t it = ((int64_t)__shfl(ihi, o, kWave) << 32) |
+                           (uint32_t)__shfl(ilo, o, kWave);
+        int key = -1;
+        if (j < total) {
+            const int local = j - o_start;
+            const int ry = (int)((uint32_t)local / (uint32_t)nbx), rx = local - ry * nbx;
+            key = so * G.nbins_scene + base + (by0 + ry) * stride + bx0 + rx;
+        }
+        fn(key, it);
+    }
+}
+
+// Whether spreading the wave's pairs over the lanes saves rounds: the
+// largest rectangle needs wave_max(nb) rounds one bin at a time, the spread
+// needs ceil(total / 64) plus the cost of its searches.
+__device__ inline bool spread_pays(int nb) {
+    const int mx = wave_max(nb);
+    int total = nb;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) total += __shfl_xor(total, d, kWave);
+    return mx > (total + kWave - 1) / kWave + 4;
+}
+
 // Range [lo, hi] of LDS window indices ((scene - s_lo) * bins per scene +
 // bin) that a triangle's bin rectangle touches; lo > hi when it touches none.
 __device__ inline void window_span(const Geom &G, const BinRect &br, int32_t s, int32_t s_lo,
@@ -291,6 +352,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
                 atomicAdd(s_hist + (hb + bin_of(br[k], cx, cy)), 1u);
                 if (++cx >= br[k].bx0 + br[k].nbx_t) { cx = br[k].bx0; ++cy; }
             }
+        } else if (spread_pays(br[k].nb)) {
+            spread_pairs(G, br[k], s, 0, [&](int key, int64_t) { agg_count(w.bin_count, key); });
         } else {
             // one round per bin of the largest bin rectangle in the wave
             const int rounds = wave_max(br[k].nb);
@@ -523,6 +586,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
     for (int k = 0; k < kItemsPerThread; ++k) {
         const int64_t item = first + k * kGroupThreads + tid;
         const BinRect br = bin_rect(G, bb[k]);
+        if (spread_pays(br.nb)) {
+            spread_pairs(G, br, sc[k], item, [&](int key, int64_t it) {
+                const int32_t slot = agg_slot(w.cursor, key);
+                if (key >= 0) w.pairs[slot] = (int32_t)it;
+            });
+            continue;
+        }
         const int rounds = wave_max(br.nb);
         const int base = sc[k] * G.nbins_scene;
         int cx = br.bx0, cy = br.by0;

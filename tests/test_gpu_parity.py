@@ -140,6 +140,25 @@ def test_bin_lists_random_micropolygons(B):
     compare(sc, g, oracle.render(sc), check_bary=False)
 
 
+@pytest.mark.parametrize("B,two_level", [(8, False), (8, True), (16, False)])
+def test_bin_lists_wide_screen_mixed_sizes(B, two_level):
+    """1920x1080 with 8-px bins (32,400 bins): a setup workgroup's randomly
+    placed triangles span more bin numbers than its LDS histogram holds, so
+    AssignBin counts and scatters with device atomics, spreading a large
+    triangle's bins over the wave's lanes.  Lists and image must match the
+    oracle."""
+    _note(f"wide-screen mixed sizes B={B} two_level={two_level}")
+    sc = scenes.mixed(seed=31, num_small=30000, num_large=48)
+    g = gpu_render(sc, bin_size=B, want_bary=False, two_level=two_level)
+    if not two_level:
+        off, pairs = g["renderer"].bin_lists()
+        ooff, otris = oracle.assign_bin(sc, B)
+        np.testing.assert_array_equal(off, ooff)
+        for b in range(len(ooff) - 1):
+            assert sorted(pairs[off[b]:off[b + 1]]) == list(otris[ooff[b]:ooff[b + 1]])
+    compare(sc, g, oracle.render(sc), check_bary=False)
+
+
 def test_repeat_runs_bit_identical():
     import torch
     sc = scenes.tiny(seed=3, width=96, height=96, num_tris=800)
