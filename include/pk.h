@@ -251,8 +251,13 @@ size_t pk_workspace_bytes(const pk_params *p, const pk_mesh *m, int64_t pair_cap
  * plus the per-bin triangle counts of AssignToBoundingBox.  Indexed meshes
  * first run the Vertex Shader once per vertex (per view), then setup gathers
  * the snapped vertices; unindexed ones transform in setup.  Writes the
- * workspace only.  Sec. 7.1 stage list (Vertex Shader, Rasterizer setup);
- * Sec. 5.2 opening text, basic kernel mapping. */
+ * workspace only.  With bin_size 0 there is nothing to count, and triangle
+ * setup runs inside pk_raster_shade's per-triangle kernel instead (no setup
+ * result goes through memory): this call then only runs the Vertex Shader
+ * of indexed meshes and clears counters.  Sec. 7.1 stage list (Vertex
+ * Shader, Rasterizer setup); Sec. 5.2 opening text, basic kernel mapping,
+ * with setup fused into the next stage's kernel for whole-screen bins
+ * (Sec. 5.2.1). */
 pk_status pk_setup(const pk_params *p, const pk_mesh *m, void *ws, void *stream);
 
 /* AssignToBoundingBox (Sec. 4.3): exclusive prefix sum of the per-bin counts
@@ -275,8 +280,9 @@ pk_status pk_assign_bin(const pk_params *p, const pk_mesh *m, void *ws, int64_t 
  * Sec. 5.2.1 fusion of Rasterizer, Fragment Shader, Depth Test, Composite).
  * With PK_SHADE_DEFERRED the colour comes from a second pass over the
  * G-buffer.  Requires pk_setup and pk_assign_bin on the same workspace.
- * With bin_size 0 (whole-screen bins) one thread per triangle covers its
- * bounding box on the screen and the depth test is a device-scope 64-bit
+ * With bin_size 0 (whole-screen bins) one thread per triangle sets the
+ * triangle up, covers its bounding box on the screen, and the depth test is
+ * a device-scope 64-bit
  * atomic min into the workspace's key buffer (the paper's baseline with
  * full-screen bins, Sec. 7); the per-pixel resolve then always runs as its
  * own pass (also under PK_FLAG_FUSE_RESOLVE, since there is no per-bin EndBin),

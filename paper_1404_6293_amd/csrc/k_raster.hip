@@ -905,15 +905,22 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     EdgeTri t;
     t.cnt = 0;
     int64_t kbase = 0;   // first key of the triangle's scene
-    // the record load does not wait for the box (a culled triangle's record
-    // is simply not used)
-    const bool inb = item < G.items;
-    RawTri raw;
-    fetch_tri(a.w, inb ? (int32_t)item : 0, raw);
-    if (inb && a.w.bbox[item] != kEmptyKey) {
-        const ItemRef r = item_ref(G, item);
-        decode_tri(raw, item, item - r.t, 0, 0, G.W, G.H, G.W, G.H, t);
-        kbase = (int64_t)r.s * G.W * G.H;
+    // Triangle setup happens here, not in pk_setup: the kernel reads the
+    // triangle's vertices (the Vertex Shader's records, or raw positions),
+    // snaps and culls it and keeps the result in registers; only an
+    // unindexed mesh's record is stored, for the per-pixel resolve.
+    TriIn tin;
+    setup_indices(G, item, tin);
+    setup_fetch(G, a.w, tin);
+    if (item < G.items) {
+        int32_t X[3], Y[3];
+        float z[3], iw[3];
+        if (setup_snap(G, tin, X, Y, z, iw) != kEmptyKey) {
+            if (!G.idx) store_record(G, a.w, item, X, Y, z, iw);
+            const ItemRef r = item_ref(G, item);
+            edge_setup(X, Y, z[0], z[1], z[2], (int32_t)r.t, 0, 0, G.W, G.H, G.W, G.H, t);
+            kbase = (int64_t)r.s * G.W * G.H;
+        }
     }
     uint32_t frags = 0;
     unsigned long long *keys = a.w.keys;

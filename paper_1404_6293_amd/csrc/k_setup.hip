@@ -88,88 +88,14 @@ __global__ __launch_bounds__(256) void k_vertex(Geom G, Ws w, uint32_t *zero, in
     reinterpret_cast<int4 *>(w.vtx)[i] = make_int4(r.X, r.Y, __float_as_int(r.z), __float_as_int(r.iw));
 }
 
-// Setup of one triangle in three steps, so that a thread can issue the loads
-// of all its triangles before it waits for any: (1) the vertex numbers (the
-// index buffer), (2) the vertices (snapped records of k_vertex, or raw
-// positions), (3) transform if needed, snap, cull and write the record.
-struct TriIn {
-    int64_t v[3];          // vertex numbers
-    int4 q[3];             // indexed: snapped X, Y, z, 1/w; else raw x, y, z
-    int32_t s;             // scene
-    bool ok;
-};
-
-__device__ inline void setup_indices(const Geom &G, int64_t item, TriIn &t) {
-    t.s = 0;
-    t.ok = item < G.items;
-    if (!t.ok) return;
-    const ItemRef r = item_ref(G, item);
-    t.s = r.s;
-    // a triangle may only use the vertices of its own scene
-    const int64_t vlo = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s] : 0;
-    const int64_t vhi = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s + 1] : G.V;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        t.v[k] = vertex_of(G, r, k);
-        if (t.v[k] < vlo || t.v[k] >= vhi || t.v[k] >= G.V) t.ok = false;
-    }
-}
-
-__device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
-    if (!t.ok) return;
-    if (G.idx) {
-        const int64_t vb = G.instanced ? (int64_t)t.s * G.V : 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) t.q[k] = reinterpret_cast<const int4 *>(w.vtx)[vb + t.v[k]];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            t.q[k] = make_int4(__float_as_int(G.pos[t.v[k]]), __float_as_int(G.pos[G.V + t.v[k]]),
-                               __float_as_int(G.pos[2 * G.V + t.v[k]]), 0);
-    }
-}
-
 // Returns the packed pixel bbox (kEmptyKey when culled).
 __device__ inline uint64_t setup_finish(const Geom &G, const Ws &w, int64_t item,
                                         const TriIn &t) {
     if (item >= G.items) return kEmptyKey;
-    int32_t X[3] = {0, 0, 0}, Y[3] = {0, 0, 0};
-    float z[3] = {0, 0, 0}, iw[3] = {0, 0, 0};
-    bool ok = t.ok;
-    if (ok) {
-        if (G.idx) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                ok = ok && t.q[k].x != kBadVertex;
-                X[k] = t.q[k].x; Y[k] = t.q[k].y;
-                z[k] = __int_as_float(t.q[k].z); iw[k] = __int_as_float(t.q[k].w);
-            }
-        } else {
-            const float *m = G.mvp ? G.mvp + 16 * (int64_t)t.s : nullptr;
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-                ok = vertex_stage_xyz(G, __int_as_float(t.q[k].x), __int_as_float(t.q[k].y),
-                                      __int_as_float(t.q[k].z), m, X[k], Y[k], z[k], iw[k]) && ok;
-        }
-    }
-    uint64_t bb = kEmptyKey;
-    if (ok) {
-        const int64_t A2 = area2(X, Y);
-        int32_t x0, x1, y0, y1;
-        sample_bbox(X, Y, G.W, G.H, x0, x1, y0, y1);
-        if (A2 != 0 && x0 <= x1 && y0 <= y1) {
-            bb = (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) |
-                 ((uint64_t)y1 << 48);
-            uint32_t xy[5];
-            pack_xy(X, Y, xy);
-            uint4 *dst = reinterpret_cast<uint4 *>(w.rec + item);
-            dst[0] = make_uint4(xy[0], xy[1], xy[2], xy[3]);
-            dst[1] = make_uint4(xy[4], __float_as_uint(z[0]), __float_as_uint(z[1]),
-                                __float_as_uint(z[2]));
-            // (without a matrix 1/w is exactly 1 and the entry is not needed)
-            if (!G.idx && G.mvp) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
-        }
-    }
+    int32_t X[3], Y[3];
+    float z[3], iw[3];
+    const uint64_t bb = setup_snap(G, t, X, Y, z, iw);
+    if (bb != kEmptyKey) store_record(G, w, item, X, Y, z, iw);
     w.bbox[item] = bb;
     return bb;
 }
@@ -392,6 +318,9 @@ hipError_t launch_setup(const Geom &G, const Ws &w, hipStream_t st) {
     }
     if (e != hipSuccess || G.items == 0) return e;
     if (w.fb_groups) return launch_fb_count(G, w, st);
+    // whole-screen bins: the triangle setup runs inside the depth-test
+    // kernel (k_direct), which needs no record or box from here
+    if (G.B == 0) return hipSuccess;
     const int64_t blocks = (G.items + kGroupItems - 1) / kGroupItems;
     const size_t hist = G.B ? kHist * sizeof(uint32_t) : 0;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(kGroupThreads), hist, st, G, w);

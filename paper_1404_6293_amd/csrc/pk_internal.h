@@ -403,6 +403,92 @@ __device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, in
     return vertex_stage_xyz(G, G.pos[v], G.pos[G.V + v], G.pos[2 * G.V + v], m, X, Y, z, iw);
 }
 
+// Setup of one triangle in three steps, so that a thread can issue the loads
+// of all its triangles before it waits for any: (1) the vertex numbers (the
+// index buffer), (2) the vertices (snapped records of k_vertex, or raw
+// positions), (3) transform if needed, snap, cull and write the record.
+struct TriIn {
+    int64_t v[3];          // vertex numbers
+    int4 q[3];             // indexed: snapped X, Y, z, 1/w; else raw x, y, z
+    int32_t s;             // scene
+    bool ok;
+};
+
+__device__ inline void setup_indices(const Geom &G, int64_t item, TriIn &t) {
+    t.s = 0;
+    t.ok = item < G.items;
+    if (!t.ok) return;
+    const ItemRef r = item_ref(G, item);
+    t.s = r.s;
+    // a triangle may only use the vertices of its own scene
+    const int64_t vlo = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s] : 0;
+    const int64_t vhi = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s + 1] : G.V;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t.v[k] = vertex_of(G, r, k);
+        if (t.v[k] < vlo || t.v[k] >= vhi || t.v[k] >= G.V) t.ok = false;
+    }
+}
+
+__device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
+    if (!t.ok) return;
+    if (G.idx) {
+        const int64_t vb = G.instanced ? (int64_t)t.s * G.V : 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t.q[k] = reinterpret_cast<const int4 *>(w.vtx)[vb + t.v[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            t.q[k] = make_int4(__float_as_int(G.pos[t.v[k]]), __float_as_int(G.pos[G.V + t.v[k]]),
+                               __float_as_int(G.pos[2 * G.V + t.v[k]]), 0);
+    }
+}
+
+// Snapped vertices, depth and 1/w of a triangle from its fetched inputs
+// (indexed: the Vertex Shader's records; else the vertex transform here);
+// returns the packed pixel bbox, or kEmptyKey when the triangle is culled
+// (a dropped vertex, zero area, or no sample centre in its box).
+__device__ inline uint64_t setup_snap(const Geom &G, const TriIn &t, int32_t X[3], int32_t Y[3],
+                                      float z[3], float iw[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { X[k] = 0; Y[k] = 0; z[k] = 0.0f; iw[k] = 0.0f; }
+    bool ok = t.ok;
+    if (ok) {
+        if (G.idx) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ok = ok && t.q[k].x != kBadVertex;
+                X[k] = t.q[k].x; Y[k] = t.q[k].y;
+                z[k] = __int_as_float(t.q[k].z); iw[k] = __int_as_float(t.q[k].w);
+            }
+        } else {
+            const float *m = G.mvp ? G.mvp + 16 * (int64_t)t.s : nullptr;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                ok = vertex_stage_xyz(G, __int_as_float(t.q[k].x), __int_as_float(t.q[k].y),
+                                      __int_as_float(t.q[k].z), m, X[k], Y[k], z[k], iw[k]) && ok;
+        }
+    }
+    if (!ok) return kEmptyKey;
+    const int64_t A2 = area2(X, Y);
+    int32_t x0, x1, y0, y1;
+    sample_bbox(X, Y, G.W, G.H, x0, x1, y0, y1);
+    if (A2 == 0 || x0 > x1 || y0 > y1) return kEmptyKey;
+    return (uint64_t)x0 | ((uint64_t)x1 << 16) | ((uint64_t)y0 << 32) | ((uint64_t)y1 << 48);
+}
+
+// The 32-byte setup record of a live triangle (and its 1/w entry when an
+// unindexed mesh has a matrix: without one 1/w is exactly 1).
+__device__ inline void store_record(const Geom &G, const Ws &w, int64_t item, const int32_t X[3],
+                                    const int32_t Y[3], const float z[3], const float iw[3]) {
+    uint32_t xy[5];
+    pack_xy(X, Y, xy);
+    uint4 *dst = reinterpret_cast<uint4 *>(w.rec + item);
+    dst[0] = make_uint4(xy[0], xy[1], xy[2], xy[3]);
+    dst[1] = make_uint4(xy[4], __float_as_uint(z[0]), __float_as_uint(z[1]), __float_as_uint(z[2]));
+    if (!G.idx && G.mvp) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
+}
+
 __device__ inline uint32_t bb_x0(uint64_t b) { return (uint32_t)(b & 0xffff); }
 __device__ inline uint32_t bb_x1(uint64_t b) { return (uint32_t)((b >> 16) & 0xffff); }
 __device__ inline uint32_t bb_y0(uint64_t b) { return (uint32_t)((b >> 32) & 0xffff); }
