@@ -72,8 +72,10 @@ def algorithmic_bytes(sc, npairs: int, covered: int, want_bary: bool, B: int) ->
     pairs and the CSR offsets; `raster` reads the pairs and offsets and
     writes every pixel's depth and primitive ID; `shade` gathers the
     attributes and writes colour (bary; G-buffer, then reads it back and
-    writes colour for deferred shading).  Returns {stage: bytes, "frame":
-    total}."""
+    writes colour for deferred shading).  With whole-screen bins the
+    triangle setup runs in the raster stage's kernel: the raster stage then
+    reads the indices (indexed meshes, whose vertices the setup stage still
+    transforms) or the positions.  Returns {stage: bytes, "frame": total}."""
     S = int(getattr(sc, "num_scenes", 1) or 1)
     views = S if getattr(sc, "instanced", False) else 1
     V = int(sc.pos.shape[1]) * views
@@ -88,6 +90,11 @@ def algorithmic_bytes(sc, npairs: int, covered: int, want_bary: bool, B: int) ->
     setup = 12 * V + (12 * T if indexed else 0)
     assign = 4 * npairs + 4 * (nbins + 1)
     raster = 4 * npairs + 4 * (nbins + 1) + 8 * npix
+    if not B:
+        # setup fused into the per-triangle depth-test kernel
+        moved = 12 * T if indexed else 12 * V
+        setup -= moved
+        raster += moved
     shade = plane(3)
     if shading == "textured":
         tex = getattr(sc, "texture", None)
@@ -905,7 +912,8 @@ def main():
     # algorithmic bytes per stage; the dominant kernel is the longest stage's
     alg = algorithmic_bytes(sc, npairs, covered, bary, B)
     deferred = getattr(sc, "shading", "gouraud") == "deferred"
-    kernels = {"setup": ("k_vertex + k_setup" if sc.idx is not None else "k_setup"),
+    kernels = {"setup": ("k_vertex + k_setup" if sc.idx is not None else "k_setup") if B
+               else ("k_vertex" if sc.idx is not None else "(none: setup runs in k_direct)"),
                "assign_bin": "k_scan + k_scatter" if B else "(none: whole-screen bins)",
                "raster": "k_direct" if B == 0 else "k_raster",
                "shade": "k_resolve" + (" + k_deferred" if deferred else "")}

@@ -45,8 +45,10 @@ def test_algorithmic_bytes_formulas():
     # than the planes; G-buffer written and read back, colour written
     sd = _scene(100, 70, V=3000, T=1000, idx=False, shading="deferred")
     d = bench.algorithmic_bytes(sd, 0, 300, False, 0)
-    assert d["setup"] == 12 * 3000
-    assert d["assign_bin"] == 4 and d["raster"] == 4 + 8 * 7000
+    # (whole-screen bins: the setup runs in the depth-test kernel, which
+    # reads the positions)
+    assert d["setup"] == 0
+    assert d["assign_bin"] == 4 and d["raster"] == 12 * 3000 + 4 + 8 * 7000
     assert d["shade"] == 2 * 36 * 300 + 24 * 7000 * 2 + 16 * 7000
     # textured instanced views read the mesh once per view
     import numpy as np
@@ -56,6 +58,11 @@ def test_algorithmic_bytes_formulas():
     assert t["setup"] == 4 * (12 * 100 + 12 * 150)
     assert t["shade"] == (4 * 12 * 100 + 4 * 8 * 100 + 4 * 8 * 8 * 3 * 4
                           + (16 + 8) * 4 * 1024)
+    # indexed mesh, whole-screen bins: the Vertex Shader still reads the
+    # positions in the setup stage, the depth-test kernel the indices
+    w = bench.algorithmic_bytes(sc, 0, 300, False, 0)
+    assert w["setup"] == 12 * 50 and w["raster"] == 12 * 80 + 4 + 8 * 7000
+    assert w["frame"] == a["frame"] - 8 * 1000 - 8 * 35
 
 
 def test_grid1080_frame_bytes_match_the_workload_sizes():
