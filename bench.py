@@ -581,6 +581,18 @@ def bench_reyes(reps: int = 10) -> dict:
     t1 = time.perf_counter()
     oracle.reyes_dice(lv, src, ps.patch_color, ps.dice_n)
     t2 = time.perf_counter()
+    # algorithmic bytes: Split reads every visited patch (192 B) and its
+    # decision, and writes each half it queues and each leaf once (192 B +
+    # a 4-B source); Dice reads each leaf and its source and writes 36 B per
+    # vertex (position, colour, normal) and 12 B per triangle
+    n = ps.dice_n
+    split_bytes = 193 * visits + 196 * (visits - ps.num_patches) + 196 * nl
+    dice_bytes = 196 * nl + 36 * nl * (n + 1) ** 2 + 12 * tris
+
+    def roof(nbytes, ms):
+        a_ = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "alg_bytes": int(nbytes), "achieved": round(a_, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a_ / HBM_PEAK_GBS, 4)}
     return {"workload": f"{ps.name}: {ps.num_patches} bicubic patches, dice at {ps.dice_px} px "
                         f"into {ps.dice_n}x{ps.dice_n} grids, forward-lit, 1 light",
             "leaves": nl, "micropolygons": tris, "largest_queue": largest,
@@ -589,8 +601,10 @@ def bench_reyes(reps: int = 10) -> dict:
             "split_all_rounds_ms": round(split_all_ms, 4),
             "split_mpatches_per_s": round(visits / (split_ms * 1e-3) / 1e6, 1),
             "split_graph_ms": round(split_graph_ms, 4), "split_graph_same_leaves": graph_ok,
+            "split_roofline": roof(split_bytes, split_ms),
             "dice_ms": round(dice_ms, 4),
             "dice_mtris_per_s": round(tris / (dice_ms * 1e-3) / 1e6, 1),
+            "dice_roofline": roof(dice_bytes, dice_ms),
             "sample_shade_ms": raster, "frame_ms": round(frame_ms, 4),
             "frame_config": {"bin_size": best.bin_size, "schedule": best.schedule},
             "cpu_oracle": {"split_s": round(t1 - t0, 3), "dice_s": round(t2 - t1, 3),

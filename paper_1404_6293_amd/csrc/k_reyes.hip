@@ -22,8 +22,10 @@
 // once).
 //
 // Dice (Sec. 7.1) evaluates an (n+1) x (n+1) grid per leaf in LDS (one
-// workgroup of one wave per leaf) and writes SoA vertex planes, normals from
-// central differences, and the grid's triangles, ready for the rasterizer.
+// workgroup of one wave per leaf): the four rows of control points at each
+// u once, then each vertex's column at its v; it writes SoA vertex planes,
+// normals from central differences, and the grid's triangles, ready for
+// the rasterizer.
 #include <cmath>
 #include <cstring>
 
@@ -400,11 +402,13 @@ __global__ __launch_bounds__(kRT) void k_split_round(SplitArgs a, int r, const f
 }
 
 // One wave per leaf: the grid in LDS, then vertices, normals and triangles.
-__global__ __launch_bounds__(kWave) void k_dice(const float *leaves, const int32_t *leaf_src,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(8))) void k_dice(const float *leaves, const int32_t *leaf_src,
                                                 int64_t nl, const float *pcol, int64_t np, int n,
                                                 float *pos, float *col, float *nrm, int32_t *idx,
                                                 int64_t V) {
     __shared__ float s_cp[kPatch];
+    // rows of control points evaluated at each u_j: [j][row][coordinate]
+    __shared__ float s_col[(kDiceMaxN + 1) * 12];
     __shared__ float s_g[3][(kDiceMaxN + 1) * (kDiceMaxN + 1)];
     const int m = n + 1, mm = m * m, nf = 6 * n * n;
     const float fn = (float)n;
@@ -412,18 +416,23 @@ __global__ __launch_bounds__(kWave) void k_dice(const float *leaves, const int32
     for (int64_t l = blockIdx.x; l < nl; l += gridDim.x) {
         if (lane < kPatch) s_cp[lane] = leaves[kPatch * l + lane];
         __syncthreads();
+        // every row of control points at u_j = j / n, once per j (each
+        // vertex of column j uses the same values)
+        for (int e = lane; e < m * 12; e += kWave) {
+            const int j = e / 12, rc = e - 12 * j, r = rc / 3, c = rc - 3 * r;
+            const float u = (float)j / fn;
+            s_col[e] = cubic_at(s_cp[3 * (4 * r) + c], s_cp[3 * (4 * r + 1) + c],
+                                s_cp[3 * (4 * r + 2) + c], s_cp[3 * (4 * r + 3) + c], u);
+        }
+        __syncthreads();
+        // then the resulting column at v_i = i / n
         for (int v = lane; v < mm; v += kWave) {
             const int i = v / m, j = v - i * m;
-            const float u = (float)j / fn, w = (float)i / fn;
+            const float w = (float)i / fn;
+            const float *cv = s_col + 12 * j;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float cv[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    cv[r] = cubic_at(s_cp[3 * (4 * r) + c], s_cp[3 * (4 * r + 1) + c],
-                                     s_cp[3 * (4 * r + 2) + c], s_cp[3 * (4 * r + 3) + c], u);
-                s_g[c][v] = cubic_at(cv[0], cv[1], cv[2], cv[3], w);
-            }
+            for (int c = 0; c < 3; ++c)
+                s_g[c][v] = cubic_at(cv[c], cv[3 + c], cv[6 + c], cv[9 + c], w);
         }
         __syncthreads();
         const int32_t s = leaf_src[l];
