@@ -612,6 +612,40 @@ def bench_reyes(reps: int = 10) -> dict:
                            "threads": 1}}
 
 
+# the paper's raster scenes at 1024x768 (triangle counts) and its K40c
+# frame times (Table "cudaraster"); context only: the models are not here,
+# grids of the same triangle counts stand in
+PAPER_SCENES = (("Fairy Forest", 174000, 8.80), ("Mecha", 254000, 6.40),
+                ("Dragon", 871000, 10.20), ("Buddha", 1100000, 11.20))
+
+
+def bench_paper_resolution(reps: int = 20) -> dict:
+    """The grid workload at the paper's resolution (1024x768) with the
+    triangle counts of its four raster scenes: 16-px bins, DIRECT_MAP, one
+    stream; medians of HIP-event frame times beside the paper's K40c times
+    for the scenes of the same counts (other scenes, other hardware)."""
+    import math
+    import torch
+    from paper_1404_6293_amd import pk, scenes
+    out = {}
+    for name, T, paper_ms in PAPER_SCENES:
+        ny = int(round(math.sqrt(T / 4.0)))
+        nx = int(round(T / (2.0 * ny)))
+        sc = scenes.grid(width=1024, height=768, nx=nx, ny=ny)
+        r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, schedule="direct_map", want_bary=False))
+        r.render()
+        torch.cuda.synchronize()
+        ms = _median_ms(torch, r.frame, reps)
+        out[name] = {"grid_quads": [nx, ny], "triangles": int(sc.num_tris),
+                     "frame_ms": round(ms, 4),
+                     "mtris_per_s": round(sc.num_tris / (ms * 1e-3) / 1e6, 1),
+                     "paper_k40c_ms": paper_ms,
+                     "paper_k40c_mtris_per_s": round(T / (paper_ms * 1e-3) / 1e6, 1)}
+        del r
+    return {"workload": "1024x768 displaced grids with the triangle counts of the paper's "
+                        "four raster scenes (16-px bins, one stream)", "frames": out}
+
+
 def bench_ablation(reps: int = 5) -> dict:
     """The schedule ablation of Sec. 7.2 on grid1080: whole-screen bins (the
     unbinned baseline) and every bin size with each schedule, the resolve in
@@ -1014,6 +1048,8 @@ def main():
         out["two_level"] = bench_two_level()
         print("bench: reyes", file=sys.stderr, flush=True)
         out["reyes"] = bench_reyes()
+        print("bench: paper resolution", file=sys.stderr, flush=True)
+        out["paper_resolution"] = bench_paper_resolution()
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(sc)
