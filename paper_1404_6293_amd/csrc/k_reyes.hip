@@ -100,22 +100,6 @@ struct SplitArgs {
     int64_t *counts;
 };
 
-__device__ inline void load_patch(const float *p, float (&cp)[kPatch]) {
-    const float4 *v = reinterpret_cast<const float4 *>(p);
-#pragma unroll
-    for (int k = 0; k < kPatch / 4; ++k) {
-        const float4 t = v[k];
-        cp[4 * k] = t.x; cp[4 * k + 1] = t.y; cp[4 * k + 2] = t.z; cp[4 * k + 3] = t.w;
-    }
-}
-
-__device__ inline void store_patch(float *p, const float (&cp)[kPatch]) {
-    float4 *v = reinterpret_cast<float4 *>(p);
-#pragma unroll
-    for (int k = 0; k < kPatch / 4; ++k)
-        v[k] = make_float4(cp[4 * k], cp[4 * k + 1], cp[4 * k + 2], cp[4 * k + 3]);
-}
-
 // The vertex transform of pk.h without snapping: products rounded, sums
 // left to right, one correctly rounded reciprocal of w.
 __device__ inline bool ctrl_screen(const float (&m)[16], bool has_m, float hw, float hh,
