@@ -129,6 +129,15 @@ def test_pin_configurations():
         check_dice(r, olv, osrc, ps)
 
 
+def test_largest_screen():
+    """8192 x 8192, the largest screen: leaves and diced meshes bit-exact."""
+    ps = small(seed=13, width=8192, height=8192, dice_px=64.0, dice_n=4)
+    _note("reyes 8192x8192")
+    r, olv, osrc = check_split(ps)
+    assert len(olv) > 1000
+    check_dice(r, olv, osrc, ps)
+
+
 def test_empty_input_and_all_culled():
     import torch
     ps = SimpleNamespace(width=64, height=64, patches=np.zeros((0, 16, 3), np.float32),
