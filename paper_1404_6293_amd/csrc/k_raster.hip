@@ -894,9 +894,11 @@ hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewi
 // all ones beforehand).  The keys are the same (depth, primitive) keys as in
 // the bin kernel, so the image is the same.  Triangles whose box is small
 // walk it per lane with stepped edge functions; larger ones are swept by the
-// whole wave, one triangle at a time, one pixel per lane.
-constexpr int kDirectThreads = 256;
-constexpr int kDirectLoopMax = 12;
+// whole wave, one triangle at a time, one pixel per lane.  One-wave
+// workgroups and a per-lane walk of up to 16 candidates measured fastest on
+// micropolygons (micro8m 256 us, against 278 with 256 threads and 12).
+constexpr int kDirectThreads = 64;
+constexpr int kDirectLoopMax = 16;
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     const Geom &G = a.G;
@@ -1039,7 +1041,10 @@ hipError_t launch_direct(const Geom &G, const Ws &w, const Shade &sh, RasterMode
 }
 
 // Resolve of every pixel of every scene from the key buffer: one thread per
-// pixel, 64 x 4 pixel tiles per workgroup.  Tiles are numbered row-major
+// pixel, TW x TH pixel tiles per workgroup (64 x 4 on wide screens, 16 x 16
+// on screens at most 512 pixels wide: measured on batch256's 256 x 256
+// scenes 264 against 309 us, on the 1080p grid 24.1 against 23.9 us; the
+// order-independent transparency resolve keeps 64 x 4).  Tiles are numbered row-major
 // (scene by scene) and split into kXcd contiguous ranges like the bins, and
 // workgroup w takes a tile from range w mod kXcd, so a die resolves the same
 // screen band whose triangles its bin kernel just read into its L2.
@@ -1052,10 +1057,11 @@ constexpr int kResW = 64, kResH = 4;
 constexpr int kResPPT = 1;
 constexpr int kResRows = kResH * kResPPT;   // rows of a tile
 
-template <int SHADE>
-__global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
+template <int SHADE, int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_resolve(RasterArgs a) {
+    constexpr int TR = TH * kResPPT;   // rows of a tile
     const Geom &G = a.G;
-    const int ntx = (G.W + kResW - 1) / kResW, nty = (G.H + kResRows - 1) / kResRows;
+    const int ntx = (G.W + TW - 1) / TW, nty = (G.H + TR - 1) / TR;
     const int64_t per_scene = (int64_t)ntx * nty;
     const int64_t ntiles = per_scene * G.S;
     const int64_t q = ntiles / kXcd, rem = ntiles % kXcd;
@@ -1065,8 +1071,8 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     const int32_t s = G.S == 1 ? 0 : (int32_t)(tile / (uint32_t)per_scene);
     const uint32_t ts = tile - (uint32_t)s * (uint32_t)per_scene;
     const int ty = (int)(ts / (uint32_t)ntx), tx = (int)(ts - (uint32_t)ty * (uint32_t)ntx);
-    const int px = tx * kResW + (int)(threadIdx.x % kResW);
-    const int py0 = ty * kResRows + (int)(threadIdx.x / kResW);
+    const int px = tx * TW + (int)(threadIdx.x % TW);
+    const int py0 = ty * TR + (int)(threadIdx.x / TW);
     if (px >= G.W || py0 >= G.H) return;
     const int64_t item_base = G.instanced ? (int64_t)s * G.T : (G.S > 1 ? G.tri_off[s] : 0);
     const int64_t vbase = (G.S > 1 && !G.instanced) ? G.vtx_off[s] : 0;
@@ -1077,7 +1083,7 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
     bool on[kResPPT];
 #pragma unroll
     for (int k = 0; k < kResPPT; ++k) {
-        const int py = py0 + k * kResH;
+        const int py = py0 + k * TH;
         on[k] = py < G.H;
         if (!on[k]) continue;
         const int64_t p = ((int64_t)s * G.H + py) * G.W + px;
@@ -1097,7 +1103,7 @@ __global__ __launch_bounds__(kResW * kResH) void k_resolve(RasterArgs a) {
         if (on[k]) resolve_attribs<SHADE>(a, s, r[k]);
 #pragma unroll
     for (int k = 0; k < kResPPT; ++k)
-        if (on[k]) resolve_finish<SHADE>(a, s, px, py0 + k * kResH, r[k], !split);
+        if (on[k]) resolve_finish<SHADE>(a, s, px, py0 + k * TH, r[k], !split);
 }
 
 // Order-independent transparency, per pixel: the layers' keys (nearest
@@ -1248,9 +1254,16 @@ template <int SHADE>
 static hipError_t launch_resolve(const RasterArgs &a, hipStream_t st) {
     // one workgroup per tile; the tile count is a multiple of nothing in
     // particular, so ranges differ by at most one tile between dies
+    if (a.G.W <= 512) {
+        const int64_t ntiles = (int64_t)((a.G.W + 15) / 16) * ((a.G.H + 16 * kResPPT - 1) /
+                                                            (16 * kResPPT)) * a.G.S;
+        hipLaunchKernelGGL((k_resolve<SHADE, 16, 16>), dim3((unsigned)ntiles), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     const int64_t ntiles = (int64_t)((a.G.W + kResW - 1) / kResW) *
                            ((a.G.H + kResRows - 1) / kResRows) * a.G.S;
-    hipLaunchKernelGGL((k_resolve<SHADE>), dim3((unsigned)ntiles), dim3(kResW * kResH), 0, st, a);
+    hipLaunchKernelGGL((k_resolve<SHADE, kResW, kResH>), dim3((unsigned)ntiles), dim3(kResW * kResH),
+                       0, st, a);
     return hipGetLastError();
 }
 
