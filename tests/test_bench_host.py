@@ -96,7 +96,9 @@ def test_source_hash_ignores_comments_not_code(tree):
     text = f.read_text()
     f.write_text("// an added comment\n/* and a block\n comment */\n" + text.replace("\n", "\n\n", 3))
     assert bench.kernel_source_hash() == h0
-    f.write_text(text.replace("kItemsPerThread = 4", "kItemsPerThread = 2"))
+    changed = text.replace("kItemsPerThread = ", "kItemsPerThread = 1 + ", 1)
+    assert changed != text
+    f.write_text(changed)
     assert bench.kernel_source_hash() != h0
 
 
