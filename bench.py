@@ -741,8 +741,17 @@ def scatter_rates(torch, r, sc, reps: int = 3) -> dict:
     addr = torch.stack(parts, dim=1).reshape(-1)     # pixel by pixel
     del parts, tri, bary, u, v, i0, j0
     n = 3 * V + th * tw * 3
-    out = {"scatters": int(addr.numel()),
+    m = int(addr.numel())
+    out = {"scatters": m,
            "probe": probe.global_add_f32_rate(addr.to(torch.int32).contiguous(), n)}
+    # the same number of atomics into the same buffer, a wave's addresses
+    # consecutive (one cache line per 16 lanes) or uniformly random
+    seq = (torch.arange(m, device="cuda", dtype=torch.int64) % n).to(torch.int32)
+    out["coalesced"] = probe.global_add_f32_rate(seq, n)
+    del seq
+    rnd = torch.randint(0, n, (m,), device="cuda", dtype=torch.int32)
+    out["random"] = probe.global_add_f32_rate(rnd, n)
+    del rnd
     vals = torch.ones(addr.numel(), dtype=torch.float32, device="cuda")
     dst = torch.zeros(n, dtype=torch.float32, device="cuda")
     ms = _median_ms(torch, lambda: dst.index_add_(0, addr, vals), reps)
@@ -788,6 +797,9 @@ def bench_backward(reps: int = 10) -> dict:
                                 "peak_kind": "pkp_global_add_f32: one device-scope float32 "
                                              "atomic add per scatter, same addresses and order",
                                 "frac": round(rate / rates["probe"], 4),
+                                "coalesced_g_per_s": round(rates["coalesced"], 2),
+                                "frac_of_coalesced": round(rate / rates["coalesced"], 4),
+                                "random_g_per_s": round(rates["random"], 2),
                                 "index_add_g_per_s": round(rates["index_add"], 2)}}
 
 
@@ -818,7 +830,13 @@ def main():
                          "(bin size --bin, default 16; 20 frames) and print its JSON")
     ap.add_argument("--reyes", action="store_true",
                     help="only run the Reyes pipeline's timings and print their JSON")
+    ap.add_argument("--backward", action="store_true",
+                    help="only time the diff64 forward and backward and print their JSON")
     args = ap.parse_args()
+    if args.backward:
+        print(json.dumps(bench_backward(reps=max(args.steps, 3) if args.steps < 400 else 10)),
+              flush=True)
+        return
     if args.reyes:
         print(json.dumps(bench_reyes(reps=max(args.steps, 3) if args.steps < 400 else 10)),
               flush=True)

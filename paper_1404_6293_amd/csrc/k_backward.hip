@@ -6,14 +6,15 @@
 //   textured:   dC[v_k][c] += b_k G_c T_c ,  dTex[j][c] += w_j G_c Cint_c
 // Coverage is not differentiated.
 //
-// Device-scope float atomics are slow on this part (about 20 G/s at spread
-// addresses, against about 2 T/s for LDS atomics), and neighbouring pixels
-// scatter to the same vertices (shared by neighbouring triangles) and the
-// same texels (overlapping bilinear footprints).  So each workgroup takes a
-// 64 x 16 pixel tile and sums its contributions per vertex and per texel in
-// LDS hash tables (open addressing, keys claimed by compare-and-swap, values
-// added with LDS float atomics), then adds each distinct entry to the
-// gradient buffers with one global atomic per channel.
+// Device-scope float atomics are slow on this part at spread addresses
+// (about 20 G/s, against about 2 T/s for LDS atomics), and neighbouring
+// pixels scatter to the same vertices (shared by neighbouring triangles) and
+// the same texels (overlapping bilinear footprints).  So each workgroup takes
+// a 64 x 16 pixel tile and sums its contributions per vertex and per texel
+// in LDS hash tables (open addressing, keys claimed by compare-and-swap,
+// values added with LDS float atomics), then adds each distinct entry to the
+// gradient buffers with one global atomic per channel, in runs of
+// neighbouring addresses (below).
 #include "pk_internal.h"
 
 #pragma clang fp contract(off)
@@ -21,9 +22,10 @@
 namespace pk {
 
 // Pixels per workgroup tile.  Wide tiles pre-reduce best here (measured on
-// 64 views of the textured grid: 64 x 16 4.13 ms, 16 x 16 4.29, 32 x 32
-// 4.31, 128 x 8 4.44, 256 x 4 5.08): fewer tile borders split a vertex's or
-// a texel's sum, and a tile row's texels are neighbours in memory.
+// 64 views of the textured grid: 64 x 16 2.50 ms, 32 x 32 2.55, 32 x 16
+// 2.70, 128 x 8 2.72, 256 x 4 2.87, 16 x 16 3.83): fewer tile borders split
+// a vertex's or a texel's sum, and a tile row's texels are neighbours in
+// memory.
 constexpr int kBwdTW = 64, kBwdTH = 16;
 constexpr int kBwdThreads = kBwdTW * kBwdTH;
 // A tile has at most 1024 x 3 distinct vertices and 1024 x 4 distinct
@@ -34,33 +36,56 @@ constexpr int kVtxSlots = 4096;
 constexpr int kTexSlots = 4096;
 constexpr int32_t kNoKey = -1;
 
+// Device-scope float atomics are executed at the memory side, one request
+// per cache line that a wave's instruction touches: measured on this GPU
+// with one atomic per lane into a 9 MB buffer, 322 G/s when a wave's
+// addresses are consecutive (318 G/s for random runs of 16), 21 G/s when
+// they are random.  So the tables keep neighbouring keys in neighbouring
+// slots: a key's home slot keeps its position within its run of
+// 2^kRunLog2 consecutive keys, and the run goes to a randomly placed group
+// of as many slots.  The flush walks the slots in order, so a wave's
+// atomics fall on a few runs of neighbouring addresses.  On 64 textured
+// views at 512 x 512 this took the pass from 4.12 ms (a plain multiplicative
+// hash of the key) to 2.49 ms; runs of 4 and 16 measured the same within
+// 1%, runs of 32 were slower (4.48 ms: long probe chains).
+constexpr int kRunLog2 = 3;
+
 template <int N>
 __device__ inline uint32_t slot_of(int32_t key) {
-    return ((uint32_t)key * 2654435761u) >> (32 - __builtin_ctz(N));
+    constexpr int LB = kRunLog2;
+    const uint32_t run = (uint32_t)key >> LB;
+    const uint32_t g = (run * 2654435761u) >> (32 - __builtin_ctz(N) + LB);
+    return (g << LB) | ((uint32_t)key & ((1u << LB) - 1));
 }
 
-// Add (v0, v1, v2) to the entry of `key` (>= 0), claiming a slot if needed.
-// Linear probing over at most N slots; the tables never fill (see above),
-// but should one, the values go straight to the global buffer at `gaddr`
-// with channel stride `gstride`.
+// Slot of `key` (>= 0) from slot h on, claiming a free one if needed, or -1
+// when the table is full.  Linear probing over at most N slots.
 template <int N>
-__device__ inline void lds_accumulate(int32_t *keys, float *vals, int32_t key, float v0, float v1,
-                                      float v2, float *gbase, int64_t gstride) {
-    uint32_t h = slot_of<N>(key);
+__device__ inline int lds_claim_from(int32_t *keys, int32_t key, uint32_t h) {
 #pragma unroll 1
     for (int probe = 0; probe < N; ++probe) {
         const int32_t k = atomicCAS(&keys[h], kNoKey, key);
-        if (k == kNoKey || k == key) {
-            atomicAdd(&vals[h], v0);
-            atomicAdd(&vals[N + h], v1);
-            atomicAdd(&vals[2 * N + h], v2);
-            return;
-        }
+        if (k == kNoKey || k == key) return (int)h;
         h = (h + 1) & (N - 1);
     }
-    atomicAdd(gbase, v0);
-    atomicAdd(gbase + gstride, v1);
-    atomicAdd(gbase + 2 * gstride, v2);
+    return -1;
+}
+
+// Add (v0, v1, v2) to slot h, or straight to the global buffer at `gbase`
+// (channel stride `gstride`) when the key found no slot (h < 0; the tables
+// never fill, see above).
+template <int N>
+__device__ inline void lds_add(float *vals, int h, float v0, float v1, float v2, float *gbase,
+                               int64_t gstride) {
+    if (h >= 0) {
+        atomicAdd(&vals[h], v0);
+        atomicAdd(&vals[N + h], v1);
+        atomicAdd(&vals[2 * N + h], v2);
+    } else {
+        atomicAdd(gbase, v0);
+        atomicAdd(gbase + gstride, v1);
+        atomicAdd(gbase + 2 * gstride, v2);
+    }
 }
 
 template <bool TEX>
@@ -109,6 +134,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Geom G, Shade sh, cons
         const float bw[3] = {b0, b1, b2};
         const float4 Gc = reinterpret_cast<const float4 *>(grad)[p];
         float gvc[3] = {Gc.x, Gc.y, Gc.z};     // what multiplies b_k per channel
+        int32_t tkey[4] = {0, 0, 0, 0};         // textured: the four taps' texels
+        float tval[4][3] = {};                  //   and what each adds per channel
         if (TEX) {
             float rgb[3];
 #pragma unroll
@@ -146,14 +173,50 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Geom G, Shade sh, cons
                 gC[c] = (c == 0 ? Gc.x : c == 1 ? Gc.y : Gc.z) * rgb[c];
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                lds_accumulate<kTexSlots>(s_tkey, s_tval, txl[j], w[j] * gC[0], w[j] * gC[1],
-                                          w[j] * gC[2], gt + 3 * (int64_t)txl[j], 1);
+            for (int j = 0; j < 4; ++j) {
+                tkey[j] = txl[j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) tval[j][c] = w[j] * gC[c];
+            }
+        }
+        // the slots of all entries: every claim is issued at its home slot
+        // before any result is needed (one LDS round trip), and only a key
+        // whose home slot holds another key probes on
+        int hv[3], ht[4] = {0, 0, 0, 0};
+        int32_t gotv[3], gott[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            hv[k] = (int)slot_of<kVtxSlots>(v[k]);
+            gotv[k] = atomicCAS(&s_vkey[hv[k]], kNoKey, v[k]);
+        }
+        if (TEX) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ht[j] = (int)slot_of<kTexSlots>(tkey[j]);
+                gott[j] = atomicCAS(&s_tkey[ht[j]], kNoKey, tkey[j]);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            lds_accumulate<kVtxSlots>(s_vkey, s_vval, v[k], bw[k] * gvc[0], bw[k] * gvc[1],
-                                      bw[k] * gvc[2], gv + v[k], V);
+            if (gotv[k] != kNoKey && gotv[k] != v[k])
+                hv[k] = lds_claim_from<kVtxSlots>(s_vkey, v[k], (hv[k] + 1) & (kVtxSlots - 1));
+        if (TEX) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (gott[j] != kNoKey && gott[j] != tkey[j])
+                    ht[j] = lds_claim_from<kTexSlots>(s_tkey, tkey[j],
+                                                      (ht[j] + 1) & (kTexSlots - 1));
+        }
+        if (TEX) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lds_add<kTexSlots>(s_tval, ht[j], tval[j][0], tval[j][1], tval[j][2],
+                                   gt + 3 * (int64_t)tkey[j], 1);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            lds_add<kVtxSlots>(s_vval, hv[k], bw[k] * gvc[0], bw[k] * gvc[1], bw[k] * gvc[2],
+                               gv + v[k], V);
     }
     __syncthreads();
     // one global atomic per channel of every distinct vertex and texel
