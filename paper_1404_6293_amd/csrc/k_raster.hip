@@ -892,13 +892,29 @@ hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewi
 // triangle over its sample bounding box on the screen, and the depth test as
 // a device-scope 64-bit atomic min into the workspace key buffer (cleared to
 // all ones beforehand).  The keys are the same (depth, primitive) keys as in
-// the bin kernel, so the image is the same.  Triangles whose box is small
-// walk it per lane with stepped edge functions; larger ones are swept by the
-// whole wave, one triangle at a time, one pixel per lane.  One-wave
-// workgroups and a per-lane walk of up to 16 candidates measured fastest on
-// micropolygons (micro8m 256 us, against 278 with 256 threads and 12).
+// the bin kernel, so the image is the same.  The candidates of triangles
+// whose box holds at most kDirectLoopMax samples are dealt over the wave's
+// lanes as (triangle, sample) pairs; larger boxes are swept by the whole
+// wave, one triangle at a time, one pixel per lane.  Measured on
+// micro8m and on the 1080p grid (k_direct per frame): each lane walking its
+// own box of up to 16 samples took 256 and 50 us (lanes idled while the
+// wave's largest box was walked: 5.3 times the useful iterations on
+// micro8m); dealing pairs up to 16, 32, 64 and 128 samples 271/41, 247/41,
+// 244/42 and 246/42 us.  Reading a pixel's key before the atomic min, to
+// skip atomics that cannot win, was slower (291 and 48 us).  One-wave
+// workgroups measured fastest.
 constexpr int kDirectThreads = 64;
-constexpr int kDirectLoopMax = 16;
+constexpr int kDirectLoopMax = 64;
+
+// A small-box triangle of k_direct as the wave's lanes read it from LDS.
+struct DirTri {
+    double C[3];
+    double inv;
+    int64_t kbase;
+    int32_t A[3], Bc[3];
+    float z[3];
+    int32_t x0, y0, wdt, own, prim;
+};
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     const Geom &G = a.G;
@@ -926,40 +942,69 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     }
     uint32_t frags = 0;
     unsigned long long *keys = a.w.keys;
-    // small boxes: each lane walks its own
+    // Small boxes: the wave's (triangle, candidate) pairs are laid end to end
+    // in lane order and dealt 64 at a time, one per lane, so that no lane
+    // idles while a neighbour walks a longer box.  Pair j belongs to the
+    // last lane whose first pair is at or before j; that lane's triangle is
+    // read from LDS.
     const int small = t.cnt <= kDirectLoopMax ? t.cnt : 0;
-    const int mx = wave_max(small);
-    if (mx > 0) {
-        int col = 0;
-        int64_t pix = kbase + (int64_t)t.y0 * G.W + t.x0;
-        const int64_t row_skip = (int64_t)G.W - t.wdt + 1;
-        const double Px = (double)(256 * t.x0 + 128), Py = (double)(256 * t.y0 + 128);
-        double e0 = (double)t.A[0] * Px + (double)t.Bc[0] * Py + t.C[0];
-        double e1 = (double)t.A[1] * Px + (double)t.Bc[1] * Py + t.C[1];
-        double e2 = (double)t.A[2] * Px + (double)t.Bc[2] * Py + t.C[2];
-        const double sx0 = (double)(256 * t.A[0]), sx1 = (double)(256 * t.A[1]),
-                     sx2 = (double)(256 * t.A[2]);
-        const double back = (double)(256 * (t.wdt - 1));
-        const double sy0 = (double)(256 * t.Bc[0]) - back * (double)t.A[0];
-        const double sy1 = (double)(256 * t.Bc[1]) - back * (double)t.A[1];
-        const double sy2 = (double)(256 * t.Bc[2]) - back * (double)t.A[2];
+    int incl = small;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    const int total = __shfl(incl, kWave - 1, kWave);
+    const int start = incl - small;
+    if (total > 0) {
+        // (one-wave workgroups: the barrier orders the wave's LDS stores
+        // before its loads)
+        static_assert(kDirectThreads == kWave, "k_direct deals pairs within one wave");
+        __shared__ DirTri s_tri[kDirectThreads];
+        if (small > 0) {
+            DirTri &mine = s_tri[threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                mine.C[k] = t.C[k];
+                mine.A[k] = t.A[k];
+                mine.Bc[k] = t.Bc[k];
+                mine.z[k] = t.z[k];
+            }
+            mine.inv = t.inv;
+            mine.kbase = kbase;
+            mine.x0 = t.x0;
+            mine.y0 = t.y0;
+            mine.wdt = t.wdt;
+            mine.own = t.own;
+            mine.prim = t.prim;
+        }
+        __syncthreads();
 #pragma unroll 1
-        for (int j = 0; j < mx; ++j) {
-            if (j < small) {
+        for (int b0 = 0; b0 < total; b0 += kWave) {
+            const int j = b0 + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int c = o + step;
+                const int sc = __shfl(start, c, kWave);
+                if (sc <= j) o = c;
+            }
+            const int o_start = __shfl(start, o, kWave);
+            if (j < total) {
+                const DirTri &q = s_tri[o];
+                const uint32_t local = (uint32_t)(j - o_start);
+                const uint32_t row = local / (uint32_t)q.wdt, col = local - row * (uint32_t)q.wdt;
+                const int px = q.x0 + (int)col, py = q.y0 + (int)row;
+                const double Px = (double)(256 * px + 128), Py = (double)(256 * py + 128);
+                const double e0 = (double)q.A[0] * Px + (double)q.Bc[0] * Py + q.C[0];
+                const double e1 = (double)q.A[1] * Px + (double)q.Bc[1] * Py + q.C[1];
+                const double e2 = (double)q.A[2] * Px + (double)q.Bc[2] * Py + q.C[2];
                 if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
                     ++frags;
                     unsigned long long key;
-                    if (depth_key(e0, e1, e2, t.own, t.inv, t.z[0], t.z[1], t.z[2],
-                                  (uint32_t)t.prim, key))
-                        atomicMin(keys + pix, key);
-                }
-                if (++col < t.wdt) {
-                    e0 += sx0; e1 += sx1; e2 += sx2;
-                    ++pix;
-                } else {
-                    col = 0;
-                    pix += row_skip;
-                    e0 += sy0; e1 += sy1; e2 += sy2;
+                    if (depth_key(e0, e1, e2, q.own, q.inv, q.z[0], q.z[1], q.z[2],
+                                  (uint32_t)q.prim, key))
+                        atomicMin(keys + q.kbase + (int64_t)py * G.W + px, key);
                 }
             }
         }
