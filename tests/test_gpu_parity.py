@@ -255,6 +255,40 @@ def test_batched_equals_sequential_plain():
             assert (gb[k][s] == gs[k][0]).all(), (s, k)
 
 
+
+def test_unbinned_box_sizes_around_the_lane_deal():
+    """Whole-screen bins deal the candidates of boxes of up to 64 samples over
+    a wave's lanes and sweep larger boxes one triangle at a time: waves that
+    mix one-sample boxes, boxes near 64 samples (8 x 8, 7 x 9, 1 x 64, 65 x 1,
+    5 x 13) and a few large triangles, overlapping in depth, against the
+    oracle (bit-exact coverage, primitive IDs and depth)."""
+    W, H = 96, 80
+    rng = np.random.default_rng(77)
+    shapes = [(1, 1), (8, 8), (7, 9), (1, 64), (64, 1), (65, 1), (5, 13), (2, 3), (30, 30),
+              (12, 5), (1, 2), (3, 1)]
+    P = []
+    for t in range(64 * 12):
+        w, h = shapes[rng.integers(len(shapes))]
+        # a right triangle whose box spans about w x h pixel centres
+        x0 = rng.uniform(0, W - w) + 0.3
+        y0 = rng.uniform(0, H - h) + 0.3
+        z = rng.uniform(0.05, 0.95)
+        tri = [(x0, y0), (x0 + w - 0.1, y0), (x0, y0 + h - 0.1)]
+        if rng.integers(2):
+            tri = [tri[0], tri[2], tri[1]]   # both windings
+        for (x, y) in tri:
+            P.append((2.0 * x / W - 1.0, 2.0 * y / H - 1.0, z))
+    pos = np.asarray(P, np.float32).T.copy()
+    col = rng.uniform(0, 1, pos.shape).astype(np.float32)
+    sc = SimpleNamespace(width=W, height=H, pos=pos, color=col, idx=None, num_tris=pos.shape[1] // 3,
+                         mvp=None, num_scenes=1, scene_tri_off=None, scene_vtx_off=None,
+                         instanced=False, uv=None, normal=None, texture=None, lights=None,
+                         shading="gouraud")
+    o = oracle.render(sc)
+    for B in (0, 8):
+        _note(f"box sizes around the lane deal, B={B}")
+        compare(sc, gpu_render(sc, bin_size=B), o)
+
 def test_empty_and_culled_inputs():
     # no triangles at all
     sc = scenes.tiny(seed=1, width=40, height=30, num_tris=1)
