@@ -906,14 +906,17 @@ hipError_t launch_epilogue(const Ws &w, unsigned long long *frag_count, int rewi
 constexpr int kDirectThreads = 64;
 constexpr int kDirectLoopMax = 64;
 
-// A small-box triangle of k_direct as the wave's lanes read it from LDS.
-struct DirTri {
-    double C[3];
-    double inv;
-    int64_t kbase;
-    int32_t A[3], Bc[3];
-    float z[3];
-    int32_t x0, y0, wdt, own, prim;
+// The small-box triangles of a k_direct wave as its lanes read them from
+// LDS: one array per field, so that lanes reading different triangles hit
+// neighbouring words.
+struct DirTris {
+    double C[3][kDirectThreads];
+    double inv[kDirectThreads];
+    int64_t kbase[kDirectThreads];
+    int32_t A[3][kDirectThreads], Bc[3][kDirectThreads];
+    float z[3][kDirectThreads];
+    int32_t x0[kDirectThreads], y0[kDirectThreads], wdt[kDirectThreads], own[kDirectThreads],
+        prim[kDirectThreads];
 };
 
 __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
@@ -960,23 +963,23 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
         // (one-wave workgroups: the barrier orders the wave's LDS stores
         // before its loads)
         static_assert(kDirectThreads == kWave, "k_direct deals pairs within one wave");
-        __shared__ DirTri s_tri[kDirectThreads];
+        __shared__ DirTris s_tri;
         if (small > 0) {
-            DirTri &mine = s_tri[threadIdx.x];
+            const int i = threadIdx.x;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                mine.C[k] = t.C[k];
-                mine.A[k] = t.A[k];
-                mine.Bc[k] = t.Bc[k];
-                mine.z[k] = t.z[k];
+                s_tri.C[k][i] = t.C[k];
+                s_tri.A[k][i] = t.A[k];
+                s_tri.Bc[k][i] = t.Bc[k];
+                s_tri.z[k][i] = t.z[k];
             }
-            mine.inv = t.inv;
-            mine.kbase = kbase;
-            mine.x0 = t.x0;
-            mine.y0 = t.y0;
-            mine.wdt = t.wdt;
-            mine.own = t.own;
-            mine.prim = t.prim;
+            s_tri.inv[i] = t.inv;
+            s_tri.kbase[i] = kbase;
+            s_tri.x0[i] = t.x0;
+            s_tri.y0[i] = t.y0;
+            s_tri.wdt[i] = t.wdt;
+            s_tri.own[i] = t.own;
+            s_tri.prim[i] = t.prim;
         }
         __syncthreads();
 #pragma unroll 1
@@ -991,20 +994,21 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
             }
             const int o_start = __shfl(start, o, kWave);
             if (j < total) {
-                const DirTri &q = s_tri[o];
                 const uint32_t local = (uint32_t)(j - o_start);
-                const uint32_t row = local / (uint32_t)q.wdt, col = local - row * (uint32_t)q.wdt;
-                const int px = q.x0 + (int)col, py = q.y0 + (int)row;
+                const uint32_t wdt = (uint32_t)s_tri.wdt[o];
+                const uint32_t row = local / wdt, col = local - row * wdt;
+                const int px = s_tri.x0[o] + (int)col, py = s_tri.y0[o] + (int)row;
                 const double Px = (double)(256 * px + 128), Py = (double)(256 * py + 128);
-                const double e0 = (double)q.A[0] * Px + (double)q.Bc[0] * Py + q.C[0];
-                const double e1 = (double)q.A[1] * Px + (double)q.Bc[1] * Py + q.C[1];
-                const double e2 = (double)q.A[2] * Px + (double)q.Bc[2] * Py + q.C[2];
-                if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) {
+                double e[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    e[k] = (double)s_tri.A[k][o] * Px + (double)s_tri.Bc[k][o] * Py + s_tri.C[k][o];
+                if (e[0] > 0.0 && e[1] > 0.0 && e[2] > 0.0) {
                     ++frags;
                     unsigned long long key;
-                    if (depth_key(e0, e1, e2, q.own, q.inv, q.z[0], q.z[1], q.z[2],
-                                  (uint32_t)q.prim, key))
-                        atomicMin(keys + q.kbase + (int64_t)py * G.W + px, key);
+                    if (depth_key(e[0], e[1], e[2], s_tri.own[o], s_tri.inv[o], s_tri.z[0][o],
+                                  s_tri.z[1][o], s_tri.z[2][o], (uint32_t)s_tri.prim[o], key))
+                        atomicMin(keys + s_tri.kbase[o] + (int64_t)py * G.W + px, key);
                 }
             }
         }
