@@ -90,10 +90,19 @@ __device__ inline void resolve_fetch(const RasterArgs &a, int32_t s, int64_t ite
         return;
     }
     const int64_t item = item_base + r.t;
-    const uint4 q0 = reinterpret_cast<const uint4 *>(a.w.rec + item)[0];
-    const uint32_t w4 = a.w.rec[item].xy[4];
+    uint32_t q[5];
+    if (G.B == 0) {
+        // whole-screen bins: the five-word record of the depth-test kernel
+        const uint32_t *src = xy20_of(a.w, item);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) q[k] = src[k];
+    } else {
+        const uint4 q0 = reinterpret_cast<const uint4 *>(a.w.rec + item)[0];
+        q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
+        q[4] = a.w.rec[item].xy[4];
+    }
     int32_t X[3], Y[3];
-    unpack_xy(q0.x, q0.y, q0.z, q0.w, w4, X, Y);
+    unpack_xy(q[0], q[1], q[2], q[3], q[4], X, Y);
     r.xy = make_uint4((uint32_t)X[0], (uint32_t)Y[0], (uint32_t)X[1], (uint32_t)Y[1]);
     r.xy2 = make_uint2((uint32_t)X[2], (uint32_t)Y[2]);
     if (G.mvp) {
@@ -929,7 +938,8 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     // Triangle setup happens here, not in pk_setup: the kernel reads the
     // triangle's vertices (the Vertex Shader's records, or raw positions),
     // snaps and culls it and keeps the result in registers; only an
-    // unindexed mesh's record is stored, for the per-pixel resolve.
+    // unindexed mesh's packed snapped vertices are stored, for the per-pixel
+    // resolve.
     TriIn tin;
     setup_indices(G, item, tin);
     setup_fetch(G, a.w, tin);
@@ -937,7 +947,10 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
         int32_t X[3], Y[3];
         float z[3], iw[3];
         if (setup_snap(G, tin, X, Y, z, iw) != kEmptyKey) {
-            if (!G.idx) store_record(G, a.w, item, X, Y, z, iw);
+            if (!G.idx) {
+                store_xy20(a.w, item, X, Y);
+                if (G.mvp) a.w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
+            }
             const ItemRef r = item_ref(G, item);
             edge_setup(X, Y, z[0], z[1], z[2], (int32_t)r.t, 0, 0, G.W, G.H, G.W, G.H, t);
             kbase = (int64_t)r.s * G.W * G.H;

@@ -489,6 +489,23 @@ __device__ inline void store_record(const Geom &G, const Ws &w, int64_t item, co
     if (!G.idx && G.mvp) w.iw[item] = make_float4(iw[0], iw[1], iw[2], 0.0f);
 }
 
+// Whole-screen bins, unindexed meshes: the per-pixel resolve is the only
+// reader of the setup record there, and it reads the packed snapped vertices
+// only, so the depth-test kernel stores just those five words per triangle
+// (20 bytes at 20-byte stride, in the record buffer), not the 32-byte record.
+__device__ inline uint32_t *xy20_of(const Ws &w, int64_t item) {
+    return reinterpret_cast<uint32_t *>(w.rec) + 5 * item;
+}
+
+__device__ inline void store_xy20(const Ws &w, int64_t item, const int32_t X[3],
+                                  const int32_t Y[3]) {
+    uint32_t xy[5];
+    pack_xy(X, Y, xy);
+    uint32_t *dst = xy20_of(w, item);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) dst[k] = xy[k];
+}
+
 __device__ inline uint32_t bb_x0(uint64_t b) { return (uint32_t)(b & 0xffff); }
 __device__ inline uint32_t bb_x1(uint64_t b) { return (uint32_t)((b >> 16) & 0xffff); }
 __device__ inline uint32_t bb_y0(uint64_t b) { return (uint32_t)((b >> 32) & 0xffff); }
