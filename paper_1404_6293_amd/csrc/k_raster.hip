@@ -125,7 +125,12 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
         const int64_t vb = a.G.instanced ? (int64_t)s * V : 0;
         int4 q[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) q[k] = reinterpret_cast<const int4 *>(a.w.vtx)[vb + r.v[k]];
+        for (int k = 0; k < 3; ++k) {
+            q[k] = reinterpret_cast<const int4 *>(a.w.vtx)[vb + r.v[k]];
+            // (z is not needed here; keeping it nominally live makes this one
+            // 16-byte gather instead of an 8-byte and a 4-byte one)
+            __asm__ volatile("" : : "v"(q[k].z));
+        }
         r.xy = make_uint4((uint32_t)q[0].x, (uint32_t)q[0].y, (uint32_t)q[1].x, (uint32_t)q[1].y);
         r.xy2 = make_uint2((uint32_t)q[2].x, (uint32_t)q[2].y);
 #pragma unroll
