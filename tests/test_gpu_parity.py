@@ -401,6 +401,49 @@ def test_backward_matches_oracle_gradient():
     assert (np.abs(gt.cpu().numpy() - ot) <= 1e-4 * np.abs(ot) + n * eps * at + 1e-7).all()
 
 
+
+@pytest.mark.parametrize("layout", ["instanced", "concatenated"])
+def test_backward_gouraud_ragged_magnified(layout):
+    """The untextured backward on a ragged screen (100 x 70: tiles cross the
+    right and bottom edges) with magnified triangles (an 8 x 4-quad grid, so
+    long runs of pixels share a triangle and its vertices in a wave), over
+    three instanced views or three concatenated scenes, against the oracle
+    gradient under the float32 atomic-order bound."""
+    import torch
+    W, H = 100, 70
+    base = scenes.diffgrid(size=64, num_views=3, nx=8, ny=4, tex_size=16)
+    pos, col, idx, mvp = base.pos, base.color, base.idx, base.mvp
+    if layout == "instanced":
+        sc = SimpleNamespace(width=W, height=H, pos=pos, color=col, idx=idx,
+                             num_tris=idx.shape[0], mvp=mvp, num_scenes=3, scene_tri_off=None,
+                             scene_vtx_off=None, instanced=True, uv=None, normal=None,
+                             texture=None, lights=None, shading="gouraud")
+    else:
+        V, T = pos.shape[1], idx.shape[0]
+        rng = np.random.default_rng(11)
+        sc = SimpleNamespace(width=W, height=H, pos=np.concatenate([pos] * 3, axis=1),
+                             color=rng.uniform(0, 1, (3, 3 * V)).astype(np.float32),
+                             idx=np.concatenate([idx] * 3, axis=0), num_tris=3 * T, mvp=mvp,
+                             num_scenes=3, scene_tri_off=np.array([0, T, 2 * T, 3 * T], np.int32),
+                             scene_vtx_off=np.array([0, V, 2 * V, 3 * V], np.int32),
+                             instanced=False, uv=None, normal=None, texture=None, lights=None,
+                             shading="gouraud")
+    _note(f"backward gouraud {layout}")
+    r = pk.Renderer(sc, pk.RenderConfig(bin_size=16, want_bary=True))
+    out = r.render()
+    G = np.random.default_rng(4).standard_normal((3, H, W, 4)).astype(np.float32)
+    gv = torch.zeros((3, sc.pos.shape[1]), dtype=torch.float32, device="cuda")
+    r.backward(torch.from_numpy(G).cuda(), gv)
+    torch.cuda.synchronize()
+    pid, bary = out["primid"].cpu().numpy(), out["bary"].cpu().numpy()
+    assert (pid >= 0).mean() > 0.3                      # the views do cover the screen
+    ov, _ = oracle.backward(sc, pid, bary, G)
+    av, _ = oracle.backward(sc, pid, bary, np.abs(G))
+    n, eps = 64, 2.0 ** -24
+    got = gv.cpu().numpy()
+    assert (np.abs(got - ov) <= 1e-4 * np.abs(ov) + n * eps * av + 1e-7).all()
+    assert np.abs(ov).max() > 0
+
 @pytest.mark.parametrize("drop", ["depth", "primid"])
 def test_defer_shade_keys_in_workspace(drop):
     """Without both the depth and primid targets the deferred pass hands the
