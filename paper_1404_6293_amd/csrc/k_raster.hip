@@ -947,6 +947,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     // resolve.
     TriIn tin;
     setup_indices(G, item, tin);
+    if (G.idx) setup_index_load(G, tin);
     setup_fetch(G, a.w, tin);
     if (item < G.items) {
         int32_t X[3], Y[3];

@@ -239,6 +239,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_setup(Geom G, Ws w) {
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k)
         setup_indices(G, first + k * kGroupThreads + tid, tin[k]);
+    if (G.idx) {
+#pragma unroll
+        for (int k = 0; k < kItemsPerThread; ++k) setup_index_load(G, tin[k]);
+    }
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) setup_fetch(G, w, tin[k]);
     if (G.B == 0) {

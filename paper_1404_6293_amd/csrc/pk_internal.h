@@ -357,11 +357,6 @@ __device__ inline ItemRef item_ref(const Geom &G, int64_t item) {
     return r;
 }
 
-__device__ inline int64_t vertex_of(const Geom &G, const ItemRef &r, int k) {
-    const int64_t local = G.idx ? (int64_t)G.idx[3 * r.g + k] : 3 * (int64_t)r.t + k;
-    return r.vbase + local;
-}
-
 // Vertex shader stage: clip = MVP (x,y,z,1) with every product rounded and
 // the sums taken left to right, NDC = clip * (1/w) with one correctly
 // rounded reciprocal, viewport, 8-bit sub-pixel snap (round half to even).  Returns false for a vertex that drops its triangle.
@@ -405,32 +400,58 @@ __device__ inline bool vertex_stage(const Geom &G, int64_t v, const float *m, in
 
 // Setup of one triangle in three steps, so that a thread can issue the loads
 // of all its triangles before it waits for any: (1) the vertex numbers (the
-// index buffer), (2) the vertices (snapped records of k_vertex, or raw
-// positions), (3) transform if needed, snap, cull and write the record.
+// index buffer's three entries issued together, checked only in the next
+// step), (2) the vertices (snapped records of k_vertex, or raw positions),
+// (3) transform if needed, snap, cull and write the record.
 struct TriIn {
-    int64_t v[3];          // vertex numbers
+    int64_t v[3];          // vertex numbers (valid after setup_fetch)
     int4 q[3];             // indexed: snapped X, Y, z, 1/w; else raw x, y, z
+    int64_t vbase;         // added to scene-local vertex numbers
+    int64_t vlo, vhi;      // the vertices the triangle's scene owns
+    int64_t g;             // indexed: the triangle's entry in the index buffer
+    int32_t iv[3];         // indexed: the index buffer's entries (in flight)
+    int32_t tloc;          // scene-local triangle number
     int32_t s;             // scene
     bool ok;
 };
 
 __device__ inline void setup_indices(const Geom &G, int64_t item, TriIn &t) {
     t.s = 0;
+    t.g = 0;
     t.ok = item < G.items;
     if (!t.ok) return;
     const ItemRef r = item_ref(G, item);
     t.s = r.s;
+    t.tloc = r.t;
+    t.vbase = r.vbase;
     // a triangle may only use the vertices of its own scene
-    const int64_t vlo = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s] : 0;
-    const int64_t vhi = (G.S > 1 && !G.instanced) ? (int64_t)G.vtx_off[r.s + 1] : G.V;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        t.v[k] = vertex_of(G, r, k);
-        if (t.v[k] < vlo || t.v[k] >= vhi || t.v[k] >= G.V) t.ok = false;
-    }
+    const bool own_range = G.S > 1 && !G.instanced;
+    t.vlo = own_range ? (int64_t)G.vtx_off[r.s] : 0;
+    t.vhi = own_range ? (int64_t)G.vtx_off[r.s + 1] : G.V;
+    t.g = r.g;
+}
+
+// Indexed meshes: the index buffer's three entries, one load.  A caller with
+// several triangles issues these for all of them in one branch on G.idx, so
+// that no wait for one triangle's entries comes before the next one's load.
+// A lane without a triangle loads entry 0 instead (it exists whenever the
+// kernel runs: items > 0 means at least one triangle) and ignores it, so the
+// loads need no branch of their own.
+__device__ inline void setup_index_load(const Geom &G, TriIn &t) {
+    const int32_t *ip = G.idx + 3 * (t.ok ? t.g : 0);
+    t.iv[0] = ip[0];
+    t.iv[1] = ip[1];
+    t.iv[2] = ip[2];
 }
 
 __device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
+    if (!t.ok) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t local = G.idx ? (int64_t)t.iv[k] : 3 * (int64_t)t.tloc + k;
+        t.v[k] = t.vbase + local;
+        if (t.v[k] < t.vlo || t.v[k] >= t.vhi || t.v[k] >= G.V) t.ok = false;
+    }
     if (!t.ok) return;
     if (G.idx) {
         const int64_t vb = G.instanced ? (int64_t)t.s * G.V : 0;
