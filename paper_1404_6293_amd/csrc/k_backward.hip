@@ -161,14 +161,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Geom G, Shade sh, cons
         int64_t g, vb;
         if (G.S == 1 || G.instanced) { g = t; vb = 0; }
         else { g = (int64_t)G.tri_off[s] + t; vb = G.vtx_off[s]; }
-        int32_t v[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            v[k] = (int32_t)(vb + (G.idx ? (int64_t)G.idx[3 * g + k] : 3 * (int64_t)t + k));
+        // the pixel's own inputs and the triangle's three indices (one
+        // load) are issued together
         const float2 bb = reinterpret_cast<const float2 *>(bary)[p];
+        const float4 Gc = reinterpret_cast<const float4 *>(grad)[p];
+        int32_t v[3];
+        if (G.idx) {
+            const int32_t *ip = G.idx + 3 * g;
+            const int32_t i0 = ip[0], i1 = ip[1], i2 = ip[2];
+            v[0] = (int32_t)(vb + i0);
+            v[1] = (int32_t)(vb + i1);
+            v[2] = (int32_t)(vb + i2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[k] = (int32_t)(vb + 3 * (int64_t)t + k);
+        }
         const float b1 = bb.x, b2 = bb.y, b0 = (1.0f - b1) - b2;
         const float bw[3] = {b0, b1, b2};
-        const float4 Gc = reinterpret_cast<const float4 *>(grad)[p];
         float gvc[3] = {Gc.x, Gc.y, Gc.z};     // what multiplies b_k per channel
         if (TEX) {
             float rgb[3];
