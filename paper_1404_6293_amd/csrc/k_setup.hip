@@ -350,10 +350,18 @@ __device__ inline int64_t block_scan(int64_t n, Get get, Put put, uint32_t *s_v,
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     int64_t carry = 0;
     for (int64_t t0 = 0; t0 < n; t0 += kScanTile) {
+        // all of a thread's loads first (past the end from entry n - 1, which
+        // exists here, and ignored), then the stores: no load waits for another
+        uint32_t g[kScanPer];
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const int64_t i = t0 + k * kScanThreads + tid;
-            s_v[k * kScanThreads + tid] = i < n ? get(i) : 0u;
+            g[k] = get(i < n ? i : n - 1);
+        }
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int64_t i = t0 + k * kScanThreads + tid;
+            s_v[k * kScanThreads + tid] = i < n ? g[k] : 0u;
         }
         __syncthreads();
         uint32_t v[kScanPer];
@@ -462,10 +470,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_scatter(Geom G, Ws w) {
     const int32_t s_lo = group_scene(G, first);
     uint64_t bb[kItemsPerThread];
     int32_t sc[kItemsPerThread];
+    // (both boxes loaded before either is used; an item past the end reads
+    // box items - 1, which exists whenever this kernel runs, and ignores it)
 #pragma unroll
     for (int k = 0; k < kItemsPerThread; ++k) {
         const int64_t item = first + k * kGroupThreads + tid;
-        bb[k] = item < G.items ? w.bbox[item] : kEmptyKey;
+        bb[k] = w.bbox[item < G.items ? item : G.items - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kItemsPerThread; ++k) {
+        const int64_t item = first + k * kGroupThreads + tid;
+        if (item >= G.items) bb[k] = kEmptyKey;
         sc[k] = bb[k] != kEmptyKey ? scene_of(G, item) : 0;
     }
     // the span of bins this workgroup touches
