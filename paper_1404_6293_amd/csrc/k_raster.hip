@@ -948,7 +948,7 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(RasterArgs a) {
     TriIn tin;
     setup_indices(G, item, tin);
     if (G.idx) setup_index_load(G, tin);
-    setup_fetch(G, a.w, tin);
+    setup_fetch<true>(G, a.w, tin);
     if (item < G.items) {
         int32_t X[3], Y[3];
         float z[3], iw[3];

@@ -444,6 +444,11 @@ __device__ inline void setup_index_load(const Geom &G, TriIn &t) {
     t.iv[2] = ip[2];
 }
 
+// WHOLE: keep each loaded vertex record's four words live in the indexed
+// branch, so that the compiler issues one 16-byte load per record instead of
+// merging the branch with the unindexed one into separate 4-byte loads.  It
+// also waits for the records there: for callers that use them right away.
+template <bool WHOLE = false>
 __device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
     if (!t.ok) return;
 #pragma unroll
@@ -457,6 +462,11 @@ __device__ inline void setup_fetch(const Geom &G, const Ws &w, TriIn &t) {
         const int64_t vb = G.instanced ? (int64_t)t.s * G.V : 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) t.q[k] = reinterpret_cast<const int4 *>(w.vtx)[vb + t.v[k]];
+        if (WHOLE) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                __asm__ volatile("" : : "v"(t.q[k].x), "v"(t.q[k].y), "v"(t.q[k].z), "v"(t.q[k].w));
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k)
