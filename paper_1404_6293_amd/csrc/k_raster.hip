@@ -123,14 +123,28 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
     const int64_t V = a.G.V;
     if (a.G.idx) {
         const int64_t vb = a.G.instanced ? (int64_t)s * V : 0;
+        // the three vertex records and every attribute gather are issued
+        // before any of them is used
         int4 q[3];
 #pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] = reinterpret_cast<const int4 *>(a.w.vtx)[vb + r.v[k]];
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            q[k] = reinterpret_cast<const int4 *>(a.w.vtx)[vb + r.v[k]];
-            // (z is not needed here; keeping it nominally live makes this one
-            // 16-byte gather instead of an 8-byte and a 4-byte one)
-            __asm__ volatile("" : : "v"(q[k].z));
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) r.c[k][ch] = sh.color[ch * V + r.v[k]];
+            if (SHADE == PK_SHADE_TEXTURED) {
+                r.ex[k][0] = sh.uv[r.v[k]];
+                r.ex[k][1] = sh.uv[V + r.v[k]];
+            }
+            if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) r.ex[k][ch] = sh.normal[ch * V + r.v[k]];
+            }
         }
+        // (z is not needed here; keeping it nominally live makes each record
+        // one 16-byte gather instead of an 8-byte and a 4-byte one)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) __asm__ volatile("" : : "v"(q[k].z));
         r.xy = make_uint4((uint32_t)q[0].x, (uint32_t)q[0].y, (uint32_t)q[1].x, (uint32_t)q[1].y);
         r.xy2 = make_uint2((uint32_t)q[2].x, (uint32_t)q[2].y);
 #pragma unroll
@@ -138,43 +152,28 @@ __device__ inline void resolve_attribs(const RasterArgs &a, int32_t s, Resolve &
         // 1 / |2 area| with the sign of the winding, computed exactly as setup does
         const int32_t X[3] = {q[0].x, q[1].x, q[2].x}, Y[3] = {q[0].y, q[1].y, q[2].y};
         r.sinv = signed_inv_area(area2(X, Y));
-    }
-    if (!a.G.idx) {
-        // unindexed: the three vertices are consecutive in every plane, one
-        // 12-byte load per plane instead of three
-        const int64_t v0 = r.v[0];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const Float3 c = *reinterpret_cast<const Float3 *>(sh.color + ch * V + v0);
-            r.c[0][ch] = c.x; r.c[1][ch] = c.y; r.c[2][ch] = c.z;
-        }
-        if (SHADE == PK_SHADE_TEXTURED) {
-#pragma unroll
-            for (int ch = 0; ch < 2; ++ch) {
-                const Float3 u = *reinterpret_cast<const Float3 *>(sh.uv + ch * V + v0);
-                r.ex[0][ch] = u.x; r.ex[1][ch] = u.y; r.ex[2][ch] = u.z;
-            }
-        }
-        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const Float3 n = *reinterpret_cast<const Float3 *>(sh.normal + ch * V + v0);
-                r.ex[0][ch] = n.x; r.ex[1][ch] = n.y; r.ex[2][ch] = n.z;
-            }
-        }
         return;
     }
+    // unindexed: the three vertices are consecutive in every plane, one
+    // 12-byte load per plane instead of three
+    const int64_t v0 = r.v[0];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int ch = 0; ch < 3; ++ch) {
+        const Float3 c = *reinterpret_cast<const Float3 *>(sh.color + ch * V + v0);
+        r.c[0][ch] = c.x; r.c[1][ch] = c.y; r.c[2][ch] = c.z;
+    }
+    if (SHADE == PK_SHADE_TEXTURED) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) r.c[k][ch] = sh.color[ch * V + r.v[k]];
-        if (SHADE == PK_SHADE_TEXTURED) {
-            r.ex[k][0] = sh.uv[r.v[k]];
-            r.ex[k][1] = sh.uv[V + r.v[k]];
+        for (int ch = 0; ch < 2; ++ch) {
+            const Float3 u = *reinterpret_cast<const Float3 *>(sh.uv + ch * V + v0);
+            r.ex[0][ch] = u.x; r.ex[1][ch] = u.y; r.ex[2][ch] = u.z;
         }
-        if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
+    }
+    if (SHADE == PK_SHADE_DEFERRED || SHADE == PK_SHADE_LIT) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) r.ex[k][ch] = sh.normal[ch * V + r.v[k]];
+        for (int ch = 0; ch < 3; ++ch) {
+            const Float3 n = *reinterpret_cast<const Float3 *>(sh.normal + ch * V + v0);
+            r.ex[0][ch] = n.x; r.ex[1][ch] = n.y; r.ex[2][ch] = n.z;
         }
     }
 }
