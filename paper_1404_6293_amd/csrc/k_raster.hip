@@ -576,6 +576,14 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
         __syncthreads();
 
         // Process: every wave takes chunks of 64 triangles of the bin list
+        // (without the pipeline, each chunk's pair numbers are loaded while
+        // the chunk before it is tested)
+        int32_t id_next = 0;
+        bool ok_next = false;
+        if (!piped) {
+            ok_next = lbeg + wbase + lane < lend;
+            id_next = prefetch_pair(a.w, ok_next, lbeg + wbase + lane);
+        }
 #pragma unroll 1
         for (int32_t c0 = lbeg + wbase;; c0 += TPB) {
             RawTri raw;
@@ -591,8 +599,10 @@ __attribute__((amdgpu_waves_per_eu(SHADE == kKeysOnly ? 4 : 1))) void k_raster(R
                 advance_nn();
             } else {
                 if (c0 >= lend) break;
-                item = c0 + lane < lend ? a.w.pairs[c0 + lane] : -1;
+                item = ok_next ? id_next : -1;
                 if (item >= 0) fetch_tri(a.w, item, raw);
+                ok_next = c0 + TPB + lane < lend;
+                id_next = prefetch_pair(a.w, ok_next, c0 + TPB + lane);
             }
             EdgeTri t;
             t.cnt = 0;
